@@ -1,0 +1,33 @@
+"""CPU FP64 oracle for the manifold-graph embedding hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this package: only the test suite, the smoke check and the
+benchmark's CPU-baseline leg use it.  It shares no code with the HIP library
+and does not import it.
+
+What it computes, following Chen, Cheung & Zhang, "Fast computation of
+generalized eigenvectors for manifold graph embedding":
+
+* ``graph_ops``: validation of the graph (Section 3.1), degrees and the
+  combinatorial Laplacian L = D - W (Section 3.1), the disconnected two-hop
+  sets T_i (Section 4.1.1), Q = sum_i Theta_i (eq. (Q)), epsilon = lambda_2(Q)
+  (Section 4.2), mu = min_i mu_i (eq. (mu)), A = L - mu Q + eps I
+  (eq. (obj2)), Gershgorin radii r_i and b_i (Section 4.3).
+* ``solve``: the first K generalized eigenpairs of (A, B = diag(b)) with
+  P^T B P = I (Section 4.3), by dense symmetric eigendecomposition of
+  B^-1/2 A B^-1/2 for small N and by shift-invert Lanczos (ARPACK, a library
+  eigensolver) for large N; residuals, B-orthonormality and principal angles.
+
+Readings of passages that are silent or ambiguous are listed at the top of
+``graph_ops``.
+"""
+from .graph_ops import (  # noqa: F401
+    OracleInputError, validate, degrees, laplacian, two_hop, theta_sum_q,
+    fiedler_value, mu_from_q, operator_a, gershgorin_radii, b_from_radii,
+    build_ops, two_hop_components,
+)
+from .solve import (  # noqa: F401
+    generalized_eigs, dense_generalized_eigs, sparse_generalized_eigs,
+    relative_residuals, b_orthonormality_error, sin_principal_angle_b,
+    fix_signs, embed,
+)
