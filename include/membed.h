@@ -1,0 +1,184 @@
+/*
+ * membed.h -- C ABI of the MI355X (gfx950) manifold-graph embedding library.
+ *
+ * Method: F. Chen, G. Cheung, X. Zhang, "Fast computation of generalized
+ * eigenvectors for manifold graph embedding".  Given a symmetric positive
+ * graph W (Section 3.1) the library builds
+ *   - the disconnected two-hop sets T_i and Q = sum_i Theta_i   (Section 4.1.1, eq. (Q)),
+ *   - eps = lambda_2(Q)                                        (Section 4.2),
+ *   - mu = min_i mu_i                                          (Section 4.2, eq. (mu)),
+ *   - A = L - mu Q + eps I                                     (eq. (obj2)),
+ *   - b_i from the Gershgorin radii r_i of A, prod b_i = 1     (Section 4.3),
+ * and returns the first K generalized eigenvectors of (A, B = diag(b)),
+ * B-orthonormal (P^T B P = I), by LOBPCG (Section 4.3).
+ *
+ * Conventions for every entry point:
+ *   - Pointers documented "device" point to GPU memory of the current HIP
+ *     device; "host" pointers to CPU memory.  `stream` is a hipStream_t
+ *     (NULL = the legacy default stream); all GPU work of a call is ordered
+ *     on it.  Calls return after their results are complete on the device
+ *     unless stated otherwise.
+ *   - Status codes: 0 = success, > 0 = warning (outputs valid), < 0 = error
+ *     (outputs untouched).  No entry point prints or aborts.
+ *   - Dense N x K blocks are row-major (row i holds node i's K coordinates).
+ *   - Threading: a handle may be used by one host thread at a time.
+ */
+#ifndef MEMBED_H
+#define MEMBED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ME_OK = 0,
+  ME_WARN_NOT_CONVERGED = 1, /* max_iter reached; X, lambda are the last iterate      */
+  ME_WARN_EPS_ZERO = 2,      /* two-hop graph disconnected: eps = mu = 0, A = L         */
+  ME_ERR_INVALID_ARG = -1,   /* null pointer, bad sizes, unsorted/duplicate/out-of-range columns */
+  ME_ERR_NOT_SYMMETRIC = -2, /* W_ij != W_ji (Section 3.1)                              */
+  ME_ERR_SELF_LOOP = -3,     /* W_ii present                                            */
+  ME_ERR_BAD_WEIGHT = -4,    /* weight not finite or <= 0 (Section 3.1: W_ij > 0)       */
+  ME_ERR_ISOLATED_NODE = -5, /* node with no edge: r_i = 0, b undefined (Section 4.3)   */
+  ME_ERR_K_RANGE = -6,       /* K outside 1..16, or the LOBPCG block does not fit N     */
+  ME_ERR_WORKSPACE = -7,     /* workspace missing or smaller than the query returned    */
+  ME_ERR_HIP = -8,           /* a HIP runtime call failed                               */
+  ME_ERR_BREAKDOWN = -9,     /* non-finite values appeared in the iteration             */
+  ME_ERR_TOO_LARGE = -10     /* nnz(W) + nnz(T) exceeds 2^31 - 1                        */
+} me_status;
+
+/* Precision of the bulk N-length work (SpMM, Gram products, block updates).
+ * The small dense solves (Cholesky, Rayleigh-Ritz) and the final residual
+ * certificate are always FP64. */
+enum { ME_FP64 = 0, ME_MIXED = 1 };
+/* Preconditioner T of the LOBPCG residual: none, or Jacobi diag(A)^-1. */
+enum { ME_PRECOND_NONE = 0, ME_PRECOND_JACOBI = 1 };
+
+/* Input graph W (Section 3.1), CSR, device memory, owned by the caller and
+ * only read during the call.  rowptr int64[n+1] (rowptr[0] = 0), col int32[nnz]
+ * strictly increasing inside each row, val float64[nnz].  Must be symmetric
+ * (exactly), with no self loops, all weights finite and > 0, every node with
+ * at least one edge. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t* rowptr;
+  const int32_t* col;
+  const double* val;
+} me_csr;
+
+typedef struct {
+  int precision;      /* ME_FP64 (default) or ME_MIXED                              */
+  int precond;        /* ME_PRECOND_JACOBI (default) or ME_PRECOND_NONE             */
+  int max_iter;       /* LOBPCG iteration cap for the embedding solve (default 20000) */
+  int eps_max_iter;   /* iteration cap for the eps = lambda_2(Q) solve (default 20000) */
+  double eps_tol;     /* relative residual target of the eps solve (default 1e-8)   */
+  int check_every;    /* iterations enqueued between host convergence reads (default 16) */
+  uint64_t seed;      /* seed of the library's starting blocks (default 0)          */
+} me_opts;
+
+/* Per-solve report.  Times are host wall-clock milliseconds of the phases. */
+typedef struct {
+  int status;          /* me_status of the call                                    */
+  int iterations;      /* LOBPCG iterations of the embedding solve                 */
+  int eps_iterations;  /* LOBPCG iterations of the eps solve (0 if not needed)     */
+  int block;           /* internal LOBPCG block width (>= K)                       */
+  double eps;          /* lambda_2(Q)                                              */
+  double mu;           /* Gershgorin weight of eq. (mu)                            */
+  double max_residual; /* max_j |A x_j - l_j B x_j| / (|l_j| |B x_j|), FP64, at exit */
+  double orth_error;   /* max |X^T B X - I| at exit, FP64                           */
+  double ms_build;     /* graph-operator build incl. eps (0 in me_embed)           */
+  double ms_solve;     /* embedding LOBPCG incl. final FP64 pass                   */
+} me_info;
+
+/* Opaque graph-operator handle (device-resident T, Q, eps, mu, b, packed A). */
+typedef struct me_graph_ops me_graph_ops;
+
+/* Fills `opts` with the defaults listed above.  `opts` host, not null. */
+void me_opts_default(me_opts* opts);
+
+/* Text of a status code (static storage). */
+const char* me_status_string(int status);
+
+/* Validates W and builds every operator of the generalized problem
+ * (Sections 3.1, 4.1.1, 4.2, 4.3): degrees, the two-hop pattern T with
+ * counts T_i, Q (with the (i,i) entry of Theta_i equal to 1 so that Q is the
+ * Laplacian of the two-hop graph; the printed 1/T_i makes Q indefinite),
+ * eps = lambda_2(Q) by LOBPCG on Q with the constant vector deflated (exactly
+ * 0 when the two-hop graph is disconnected: ME_WARN_EPS_ZERO), mu, b and the
+ * packed difference-form operator A.
+ *   W      host struct holding device pointers (see me_csr).
+ *   opts   host, may be NULL (defaults).
+ *   out    host; receives a new handle on success (ME_OK or a warning).
+ *   info   host, may be NULL; receives eps, mu, eps_iterations, ms_build.
+ * The handle owns device memory allocated by the library; release it with
+ * me_graph_ops_destroy.  The call synchronises `stream`. */
+int me_build_graph_ops(const me_csr* W, const me_opts* opts, void* stream,
+                       me_graph_ops** out, me_info* info);
+
+/* Scalars of a built handle (host outputs, any may be NULL). */
+int me_graph_ops_query(const me_graph_ops* ops, int64_t* n, int64_t* nnz_T,
+                       double* eps, double* mu, int* components_gt1);
+
+/* Bytes of device memory held by the handle. */
+size_t me_graph_ops_bytes(const me_graph_ops* ops);
+
+/* Copies the operators out, in the caller's node order (device outputs, each
+ * may be NULL): T_rowptr int64[n+1], T_col int32[nnz_T] (sorted per row),
+ * T_count int32[n], d float64[n] (degrees), qdiag float64[n] (Q_ii),
+ * r float64[n] (Gershgorin radii of A), b float64[n].  Synchronises `stream`. */
+int me_graph_ops_export(const me_graph_ops* ops, int64_t* T_rowptr, int32_t* T_col,
+                        int32_t* T_count, double* d, double* qdiag, double* r,
+                        double* b, void* stream);
+
+/* Applies the operators to a dense block (device, row-major n x k, 1 <= k <= 16):
+ * which = 0: Y = A X;  1: Y = Q X;  2: Y = B X.  FP64, difference form.
+ * A test and diagnostic hook; not on the solve path. */
+int me_apply(const me_graph_ops* ops, int which, int k, const double* X, double* Y,
+             void* stream);
+
+/* Device workspace needed by me_embed for this graph and K. */
+size_t me_embed_workspace_bytes(const me_graph_ops* ops, int K, const me_opts* opts);
+
+/* The first K generalized eigenpairs of (A, B) (Section 4.3) by LOBPCG until
+ * every one of the K pairs has relative residual
+ *   rho_j = |A x_j - lambda_j B x_j|_2 / (|lambda_j| |B x_j|_2) <= tol
+ * evaluated in FP64 at exit.  When |lambda_j| < 1e-8 a_max, with a_max the
+ * largest diagonal entry of A (the eps = 0 case has lambda_1 = 0), |lambda_j|
+ * in the denominator is replaced by a_max.
+ *   K        1..16; the internal block is 4, 8 or 16 columns and must satisfy
+ *            3 * block <= n (graphs with n <= 48 use a dense solve instead).
+ *   tol      > 0.
+ *   X0       device n x K float64 starting block, or NULL to use the
+ *            library's seeded counter-based generator (opts->seed).
+ *   ws       device workspace of at least me_embed_workspace_bytes bytes, or
+ *            NULL to let the library allocate (and free) it on `stream`.
+ *   X        device n x K float64 output, row-major, X^T B X = I, columns in
+ *            ascending lambda order, each column's largest-magnitude entry
+ *            positive (lowest row on ties).
+ *   lambda   device float64[K] output, ascending.
+ *   info     host, may be NULL.
+ * Synchronises `stream`. */
+int me_embed(const me_graph_ops* ops, int K, double tol, const me_opts* opts,
+             const double* X0, void* ws, size_t ws_bytes, double* X, double* lambda,
+             me_info* info, void* stream);
+
+/* Kernel timing (diagnostic).  me_kernel_timing(kind) starts timing every
+ * launch of one kernel kind with HIP events recorded on the launching stream
+ * (kind 0 = off, 1 = SpMM of A on the embedding block, 2 = Rayleigh-Ritz
+ * Gram of the embedding block, 3 = block combine of the embedding block) and
+ * clears the totals.  me_kernel_timing_read returns the number of launches,
+ * their summed duration in milliseconds and the algorithmic bytes they moved
+ * (host outputs).  Totals are updated when me_embed returns. */
+int me_kernel_timing(int kind);
+int me_kernel_timing_read(int64_t* launches, double* total_ms, double* bytes);
+
+/* Releases a handle (NULL is allowed). */
+void me_graph_ops_destroy(me_graph_ops* ops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MEMBED_H */

@@ -1,0 +1,9 @@
+"""MI355X (gfx950) manifold-graph embedding: the disconnected two-hop
+difference matrix Q, eps = lambda_2(Q), mu, the degree-equalising B and the
+first K generalized eigenvectors of (A = L - mu Q + eps I, B) by LOBPCG, all
+in hand-written HIP kernels behind the C ABI of include/membed.h."""
+from ._lib import LIB_PATH, load  # noqa: F401
+from .api import (  # noqa: F401
+    DeviceCSR, GraphOps, MembedError, build_graph_ops, embed, kernel_timing, kernel_timing_read, make_opts,
+    to_device,
+)

@@ -1,0 +1,214 @@
+"""Python binding of libmembed: torch tensors supply device memory and the
+stream; every step of the computation runs in the HIP library."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class MembedError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        self.name = L.STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{what}: {self.name} ({L.load().me_status_string(status).decode()})")
+
+
+def _check(st: int, what: str) -> int:
+    if st < 0:
+        raise MembedError(st, what)
+    return st
+
+
+def _stream_ptr(stream=None) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+_PRECISION = {"fp64": L.ME_FP64, "mixed": L.ME_MIXED}
+_PRECOND = {"none": L.ME_PRECOND_NONE, "jacobi": L.ME_PRECOND_JACOBI}
+
+
+def make_opts(precision="fp64", precond="jacobi", max_iter=None, eps_max_iter=None,
+              eps_tol=None, check_every=None, seed=None) -> L.MeOpts:
+    o = L.MeOpts()
+    L.load().me_opts_default(ctypes.byref(o))
+    o.precision = _PRECISION[precision]
+    o.precond = _PRECOND[precond]
+    if max_iter is not None:
+        o.max_iter = int(max_iter)
+    if eps_max_iter is not None:
+        o.eps_max_iter = int(eps_max_iter)
+    if eps_tol is not None:
+        o.eps_tol = float(eps_tol)
+    if check_every is not None:
+        o.check_every = int(check_every)
+    if seed is not None:
+        o.seed = int(seed)
+    return o
+
+
+@dataclass
+class DeviceCSR:
+    n: int
+    rowptr: torch.Tensor  # int64 [n+1]
+    col: torch.Tensor     # int32 [nnz]
+    val: torch.Tensor     # float64 [nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    def as_struct(self) -> L.MeCsr:
+        return L.MeCsr(self.n, self.nnz, self.rowptr.data_ptr(), self.col.data_ptr(),
+                       self.val.data_ptr())
+
+
+def to_device(csr, device="cuda") -> DeviceCSR:
+    """Uploads a host CSR (anything with n, rowptr, col, val)."""
+    if isinstance(csr, DeviceCSR):
+        return csr
+    rp = torch.as_tensor(np.ascontiguousarray(csr.rowptr, dtype=np.int64)).to(device)
+    col = torch.as_tensor(np.ascontiguousarray(csr.col, dtype=np.int32)).to(device)
+    val = torch.as_tensor(np.ascontiguousarray(csr.val, dtype=np.float64)).to(device)
+    return DeviceCSR(int(csr.n), rp, col, val)
+
+
+class GraphOps:
+    """Device-resident operators of one graph (T, Q, eps, mu, b, packed A)."""
+
+    def __init__(self, handle: ctypes.c_void_p, n: int, info: L.MeInfo, status: int, csr):
+        self._h = handle
+        self.n = n
+        self.build_info = info.as_dict()
+        self.status = status
+        self._csr = csr  # keep the input alive for the handle's lifetime
+        lib = L.load()
+        nn, nt, eps, mu, c = c_int64_(), c_int64_(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        _check(lib.me_graph_ops_query(self._h, ctypes.byref(nn), ctypes.byref(nt), ctypes.byref(eps),
+                                      ctypes.byref(mu), ctypes.byref(c)), "query")
+        self.nnz_t = nt.value
+        self.eps = eps.value
+        self.mu = mu.value
+        self.two_hop_disconnected = bool(c.value)
+        self.device_bytes = int(lib.me_graph_ops_bytes(self._h))
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("GraphOps already closed")
+        return self._h
+
+    def export(self, stream=None) -> dict:
+        dev = self._csr.rowptr.device
+        n, nt = self.n, self.nnz_t
+        out = dict(
+            t_rowptr=torch.empty(n + 1, dtype=torch.int64, device=dev),
+            t_col=torch.empty(max(nt, 1), dtype=torch.int32, device=dev),
+            t_count=torch.empty(n, dtype=torch.int32, device=dev),
+            d=torch.empty(n, dtype=torch.float64, device=dev),
+            qdiag=torch.empty(n, dtype=torch.float64, device=dev),
+            r=torch.empty(n, dtype=torch.float64, device=dev),
+            b=torch.empty(n, dtype=torch.float64, device=dev),
+        )
+        _check(L.load().me_graph_ops_export(
+            self.handle, _ptr(out["t_rowptr"]), _ptr(out["t_col"]), _ptr(out["t_count"]),
+            _ptr(out["d"]), _ptr(out["qdiag"]), _ptr(out["r"]), _ptr(out["b"]),
+            _stream_ptr(stream)), "export")
+        out["t_col"] = out["t_col"][:nt]
+        return out
+
+    def apply(self, which: str, X: torch.Tensor, stream=None) -> torch.Tensor:
+        """Y = A X, Q X or B X (FP64 difference form)."""
+        code = {"A": 0, "Q": 1, "B": 2}[which]
+        X = X.contiguous()
+        if X.dim() == 1:
+            X = X[:, None]
+        Y = torch.empty_like(X)
+        _check(L.load().me_apply(self.handle, code, X.shape[1], _ptr(X), _ptr(Y),
+                                 _stream_ptr(stream)), "apply")
+        return Y
+
+    def close(self):
+        if self._h is not None:
+            L.load().me_graph_ops_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def c_int64_():
+    return ctypes.c_int64()
+
+
+def build_graph_ops(csr, stream=None, **opts) -> GraphOps:
+    dcsr = to_device(csr)
+    o = make_opts(**opts)
+    h = ctypes.c_void_p()
+    info = L.MeInfo()
+    st = L.load().me_build_graph_ops(ctypes.byref(dcsr.as_struct()), ctypes.byref(o),
+                                     _stream_ptr(stream), ctypes.byref(h), ctypes.byref(info))
+    _check(st, "build_graph_ops")
+    return GraphOps(h, dcsr.n, info, st, dcsr)
+
+
+def embed(graph, K: int, tol: float = 1e-6, X0: torch.Tensor | None = None,
+          workspace: torch.Tensor | None = None, stream=None, **opts):
+    """First K generalized eigenpairs of (A, B).  `graph` is a GraphOps or a
+    CSR (built and released inside).  Returns (X [n, K] float64 B-orthonormal,
+    lambda [K] float64 ascending, info dict)."""
+    own = not isinstance(graph, GraphOps)
+    ops = build_graph_ops(graph, stream=stream, **opts) if own else graph
+    try:
+        lib = L.load()
+        o = make_opts(**opts)
+        dev = ops._csr.rowptr.device
+        need = int(lib.me_embed_workspace_bytes(ops.handle, int(K), ctypes.byref(o)))
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        X = torch.empty((ops.n, int(K)), dtype=torch.float64, device=dev)
+        lam = torch.empty(int(K), dtype=torch.float64, device=dev)
+        if X0 is not None:
+            X0 = X0.to(device=dev, dtype=torch.float64).contiguous()
+            if X0.shape != (ops.n, int(K)):
+                raise ValueError("X0 must be n x K")
+        info = L.MeInfo()
+        st = lib.me_embed(ops.handle, int(K), float(tol), ctypes.byref(o), _ptr(X0),
+                          _ptr(workspace), workspace.numel(), _ptr(X), _ptr(lam),
+                          ctypes.byref(info), _stream_ptr(stream))
+        _check(st, "embed")
+        d = info.as_dict()
+        d["status_name"] = L.STATUS_NAMES.get(st, str(st))
+        d["ms_build"] = ops.build_info.get("ms_build", 0.0) if own else 0.0
+        d["eps"] = ops.eps
+        d["mu"] = ops.mu
+        d["eps_iterations"] = ops.build_info.get("eps_iterations", 0)
+        return X, lam, d
+    finally:
+        if own:
+            ops.close()
+
+
+def kernel_timing(kind: int) -> None:
+    """Start timing one kernel kind (0 off, 1 SpMM of A, 2 Rayleigh-Ritz Gram,
+    3 block combine); clears the totals."""
+    _check(L.load().me_kernel_timing(int(kind)), "kernel_timing")
+
+
+def kernel_timing_read() -> dict:
+    n, ms, b = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(L.load().me_kernel_timing_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)),
+           "kernel_timing_read")
+    return {"launches": n.value, "total_ms": ms.value, "bytes": b.value}

@@ -1,0 +1,640 @@
+// Graph-operator build: validation of W (Section 3.1), degrees, the
+// disconnected two-hop pattern T (Section 4.1.1), Q's diagonal and the mu
+// denominators (eq. (Q), eq. (mu)), connectivity of the two-hop graph
+// (lambda_2(Q) = 0 iff it is disconnected), eps (Section 4.2), r and b
+// (Section 4.3), and the packed difference-form operator A = L - mu Q + eps I
+// (eq. (obj2)).
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace me {
+
+enum : int {
+  F_INVALID = 1,
+  F_SELF_LOOP = 2,
+  F_BAD_WEIGHT = 4,
+  F_NOT_SYMMETRIC = 8,
+  F_ISOLATED = 16,
+};
+
+static int flags_to_status(int f) {
+  if (f & F_INVALID) return ME_ERR_INVALID_ARG;
+  if (f & F_SELF_LOOP) return ME_ERR_SELF_LOOP;
+  if (f & F_BAD_WEIGHT) return ME_ERR_BAD_WEIGHT;
+  if (f & F_NOT_SYMMETRIC) return ME_ERR_NOT_SYMMETRIC;
+  if (f & F_ISOLATED) return ME_ERR_ISOLATED_NODE;
+  return ME_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Validation
+// ---------------------------------------------------------------------------
+
+__global__ void k_check_rowptr(int64_t n, int64_t nnz, const int64_t* rp, int* flags) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i > n) return;
+  int64_t v = rp[i];
+  bool bad = (i == 0 && v != 0) || (i == n && v != nnz) || (v < 0) || (v > nnz);
+  if (i < n && rp[i + 1] < v) bad = true;
+  if (bad) atomicOr(flags, F_INVALID);
+}
+
+// One thread per row: column range and order, self loops, weights,
+// exact symmetry (binary search of i in row j), isolated nodes, degree.
+__global__ void k_validate_rows(int64_t n, const int64_t* rp, const int32_t* col,
+                                const double* val, double* deg, int* flags) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t s = rp[i], e = rp[i + 1];
+  int f = 0;
+  if (s == e) f |= F_ISOLATED;
+  double d = 0.0;
+  int32_t prev = -1;
+  for (int64_t t = s; t < e; ++t) {
+    int32_t c = col[t];
+    double v = val[t];
+    if (c < 0 || c >= n) { f |= F_INVALID; continue; }
+    if (c <= prev) f |= F_INVALID;
+    prev = c;
+    if (c == i) f |= F_SELF_LOOP;
+    if (!(v > 0.0) || !isfinite(v)) f |= F_BAD_WEIGHT;
+    d += v;
+    int64_t lo = rp[c], hi = rp[c + 1];
+    bool found = false;
+    while (lo < hi) {
+      int64_t mid = lo + ((hi - lo) >> 1);
+      int32_t cm = col[mid];
+      if (cm == (int32_t)i) { found = (val[mid] == v); break; }
+      if (cm < (int32_t)i) lo = mid + 1; else hi = mid;
+    }
+    if (!found) f |= F_NOT_SYMMETRIC;
+  }
+  deg[i] = d;
+  if (f) atomicOr(flags, f);
+}
+
+// ---------------------------------------------------------------------------
+// Two-hop pattern.  Row i's candidates are the members of N(k) for k in N(i);
+// T_i is that union minus N(i) and i.  Rows whose candidate count fits the
+// LDS table use an open-addressing hash in LDS (one wave per row); larger
+// rows go to a bitmap kernel.  Output columns are sorted ascending.
+// ---------------------------------------------------------------------------
+
+constexpr int kHashCap = 2048;            // slots per row table (power of two)
+constexpr int kHashMaxKeys = kHashCap / 2; // keys admitted (load factor <= 1/2)
+
+__device__ inline unsigned hash_slot(int32_t j) {
+  return ((uint32_t)j * 2654435761u) >> (32 - 11);  // 11 = log2(kHashCap)
+}
+
+__device__ inline void hash_insert(int* table, int32_t j, bool excluded) {
+  int key = excluded ? -(j + 1) : (j + 1);
+  unsigned h = hash_slot(j);
+  for (;;) {
+    int prev = atomicCAS(&table[h], 0, key);
+    if (prev == 0 || prev == j + 1 || prev == -(j + 1)) return;
+    h = (h + 1) & (kHashCap - 1);
+  }
+}
+
+__device__ inline int64_t wave_sum_i64(int64_t v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// mode 0: count (tcnt[i] = T_i, big rows appended to big_list with tcnt = 0)
+// mode 1: fill (writes sorted columns at t_rp[i]; big rows skipped)
+__global__ void __launch_bounds__(64) k_twohop_lds(int64_t n, const int64_t* rp, const int32_t* col,
+                                                   int mode, int32_t* tcnt, const int64_t* t_rp,
+                                                   int32_t* t_col, int32_t* big_list,
+                                                   int32_t* big_count) {
+  __shared__ int table[kHashCap];
+  __shared__ int32_t list[kHashMaxKeys];
+  __shared__ int lane_off[kWave];
+  const int lane = threadIdx.x;
+  constexpr int per = kHashCap / kWave;  // 32 slots per lane
+  for (int q = 0; q < per; ++q) table[lane * per + q] = 0;
+  __syncthreads();
+  for (int64_t row = blockIdx.x; row < n; row += gridDim.x) {
+    const int64_t s = rp[row], e = rp[row + 1];
+    int64_t cand = 0;
+    for (int64_t t = s + lane; t < e; t += kWave) {
+      int32_t k = col[t];
+      cand += rp[k + 1] - rp[k];
+    }
+    cand = wave_sum_i64(cand);
+    if (cand + (e - s) + 1 > kHashMaxKeys) {
+      if (mode == 0 && lane == 0) {
+        int slot = atomicAdd(big_count, 1);
+        big_list[slot] = (int32_t)row;
+        tcnt[row] = 0;
+      }
+      continue;
+    }
+    if (lane == 0) hash_insert(table, (int32_t)row, true);
+    for (int64_t t = s + lane; t < e; t += kWave) hash_insert(table, col[t], true);
+    __syncthreads();
+    for (int64_t t = s; t < e; ++t) {
+      int32_t k = col[t];
+      const int64_t ks = rp[k], ke = rp[k + 1];
+      for (int64_t u = ks + lane; u < ke; u += kWave) hash_insert(table, col[u], false);
+    }
+    __syncthreads();
+    int mine = 0;
+    for (int q = 0; q < per; ++q) mine += table[lane * per + q] > 0;
+    if (mode == 0) {
+      int64_t total = wave_sum_i64(mine);
+      if (lane == 0) tcnt[row] = (int32_t)total;
+    } else {
+      // exclusive prefix of `mine` over lanes
+      lane_off[lane] = mine;
+      __syncthreads();
+      int off = 0;
+      for (int q = 0; q < lane; ++q) off += lane_off[q];
+      int total = off;
+      for (int q = lane; q < kWave; ++q) total += lane_off[q];
+      for (int q = 0; q < per; ++q) {
+        int v = table[lane * per + q];
+        if (v > 0) list[off++] = v - 1;
+      }
+      __syncthreads();
+      const int64_t base = t_rp[row];
+      for (int a = lane; a < total; a += kWave) {
+        int32_t v = list[a];
+        int rank = 0;
+        for (int c = 0; c < total; ++c) rank += list[c] < v;
+        t_col[base + rank] = v;
+      }
+      __syncthreads();
+    }
+    for (int q = 0; q < per; ++q) table[lane * per + q] = 0;
+    __syncthreads();
+  }
+}
+
+// Rows too large for the LDS table: one block per row, a bitmap over all
+// nodes in global scratch (one bitmap per block).  Scanning the bitmap in
+// order yields sorted columns.
+__global__ void __launch_bounds__(256) k_twohop_big(int64_t n, const int64_t* rp, const int32_t* col,
+                                                    int mode, const int32_t* big_list, int nbig,
+                                                    uint32_t* bitmaps, int32_t* tcnt,
+                                                    const int64_t* t_rp, int32_t* t_col) {
+  __shared__ int64_t part[256];
+  const int64_t nwords = (n + 31) / 32;
+  uint32_t* bm = bitmaps + (int64_t)blockIdx.x * nwords;
+  for (int qi = blockIdx.x; qi < nbig; qi += gridDim.x) {
+    const int64_t row = big_list[qi];
+    const int64_t s = rp[row], e = rp[row + 1];
+    for (int64_t t = s; t < e; ++t) {
+      int32_t k = col[t];
+      for (int64_t u = rp[k] + threadIdx.x; u < rp[k + 1]; u += blockDim.x) {
+        uint32_t j = (uint32_t)col[u];
+        atomicOr(&bm[j >> 5], 1u << (j & 31));
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAnd(&bm[row >> 5], ~(1u << (row & 31)));
+    for (int64_t t = s + threadIdx.x; t < e; t += blockDim.x) {
+      uint32_t j = (uint32_t)col[t];
+      atomicAnd(&bm[j >> 5], ~(1u << (j & 31)));
+    }
+    __syncthreads();
+    // contiguous word chunk per thread
+    const int64_t chunk = (nwords + blockDim.x - 1) / blockDim.x;
+    const int64_t w0 = threadIdx.x * chunk;
+    const int64_t w1 = (w0 + chunk < nwords) ? w0 + chunk : nwords;
+    int64_t cnt = 0;
+    for (int64_t w = w0; w < w1; ++w) cnt += __popc(bm[w]);
+    part[threadIdx.x] = cnt;
+    __syncthreads();
+    if (mode == 0) {
+      if (threadIdx.x == 0) {
+        int64_t tot = 0;
+        for (int q = 0; q < (int)blockDim.x; ++q) tot += part[q];
+        tcnt[row] = (int32_t)tot;
+      }
+    } else {
+      int64_t off = t_rp[row];
+      for (int q = 0; q < (int)threadIdx.x; ++q) off += part[q];
+      for (int64_t w = w0; w < w1; ++w) {
+        uint32_t bits = bm[w];
+        while (bits) {
+          int b = __ffs(bits) - 1;
+          bits &= bits - 1;
+          t_col[off++] = (int32_t)(w * 32 + b);
+        }
+      }
+    }
+    __syncthreads();
+    // clear what this row set
+    for (int64_t t = s; t < e; ++t) {
+      int32_t k = col[t];
+      for (int64_t u = rp[k] + threadIdx.x; u < rp[k + 1]; u += blockDim.x) {
+        uint32_t j = (uint32_t)col[u];
+        bm[j >> 5] = 0u;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of int32 counts into int64 offsets (out[n] = total).
+// ---------------------------------------------------------------------------
+
+constexpr int kScanPer = 4;
+constexpr int kScanTile = kBlock * kScanPer;
+
+__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    int64_t add = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  int64_t incl = sh[t];
+  *total = sh[kBlock - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_tiles(int64_t n, const int32_t* in, int64_t* out,
+                                                       int64_t* tile_sums) {
+  __shared__ int64_t sh[kBlock];
+  const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * kScanPer;
+  int64_t v[kScanPer];
+  int64_t sum = 0;
+  for (int q = 0; q < kScanPer; ++q) {
+    v[q] = (base + q < n) ? in[base + q] : 0;
+    sum += v[q];
+  }
+  int64_t tot;
+  int64_t ex = block_exclusive_scan(sum, sh, &tot);
+  for (int q = 0; q < kScanPer; ++q) {
+    if (base + q < n) out[base + q] = ex;
+    ex += v[q];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_sums(int64_t ntiles, int64_t* tile_sums,
+                                                      int64_t* out_total) {
+  __shared__ int64_t sh[kBlock];
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < ntiles; b0 += kBlock) {
+    int64_t i = b0 + threadIdx.x;
+    int64_t v = i < ntiles ? tile_sums[i] : 0;
+    int64_t tot;
+    int64_t ex = block_exclusive_scan(v, sh, &tot);
+    if (i < ntiles) tile_sums[i] = ex + carry;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *out_total = carry;
+}
+
+__global__ void k_scan_add(int64_t n, int64_t* out, const int64_t* tile_sums) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] += tile_sums[i / kScanTile];
+}
+
+static void scan_counts(int64_t n, const int32_t* cnt, int64_t* out, int64_t* tile_tmp,
+                        hipStream_t s) {
+  int64_t ntiles = ceil_div(n, kScanTile);
+  if (ntiles == 0) ntiles = 1;
+  k_scan_tiles<<<ntiles, kBlock, 0, s>>>(n, cnt, out, tile_tmp);
+  k_scan_sums<<<1, kBlock, 0, s>>>(ntiles, tile_tmp, out + n);
+  k_scan_add<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, out, tile_tmp);
+}
+
+// ---------------------------------------------------------------------------
+// Connected components of the two-hop graph (union-find: hook the larger
+// root under the smaller one, path halving; parents only decrease, so every
+// loop ends).
+// ---------------------------------------------------------------------------
+
+__device__ inline int32_t uf_find(int32_t* parent, int32_t x) {
+  for (;;) {
+    int32_t p = __atomic_load_n(&parent[x], __ATOMIC_RELAXED);
+    if (p == x) return x;
+    int32_t gp = __atomic_load_n(&parent[p], __ATOMIC_RELAXED);
+    if (gp != p) __atomic_store_n(&parent[x], gp, __ATOMIC_RELAXED);
+    x = gp;
+  }
+}
+
+__global__ void k_uf_init(int64_t n, int32_t* parent) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) parent[i] = (int32_t)i;
+}
+
+__global__ void k_uf_hook(int64_t n, const int64_t* t_rp, const int32_t* t_col, int32_t* parent) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t t = t_rp[i]; t < t_rp[i + 1]; ++t) {
+    int32_t j = t_col[t];
+    if (j >= i) break;  // sorted: each undirected pair once
+    int32_t a = uf_find(parent, (int32_t)i), b = uf_find(parent, j);
+    while (a != b) {
+      if (a < b) { int32_t tmp = a; a = b; b = tmp; }  // a > b: hook a under b
+      int32_t old = atomicCAS(&parent[a], a, b);
+      if (old == a) break;
+      a = uf_find(parent, old);
+      b = uf_find(parent, b);
+    }
+  }
+}
+
+__global__ void k_uf_count_roots(int64_t n, int32_t* parent, int* roots) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int is_root = 0;
+  if (i < n) is_root = uf_find(parent, (int32_t)i) == (int32_t)i;
+  // wave-level count then one atomic per wave
+  unsigned long long m = __ballot(is_root);
+  if ((threadIdx.x & (kWave - 1)) == 0 && m) atomicAdd(roots, __popcll(m));
+}
+
+// ---------------------------------------------------------------------------
+// Per-node scalars
+// ---------------------------------------------------------------------------
+
+__global__ void k_invt(int64_t n, const int32_t* tcnt, double* invt, float* invt32) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t t = tcnt[i];
+  double v = t > 0 ? 1.0 / (double)t : 0.0;
+  invt[i] = v;
+  invt32[i] = (float)v;
+}
+
+__device__ inline void atomic_max_pos_double(unsigned long long* addr, double v) {
+  // non-negative doubles order like their bit patterns
+  atomicMax(addr, (unsigned long long)__double_as_longlong(v));
+}
+
+// Q_ii = sum_{j in T_i} (1/T_i + 1/T_j) and the eq. (mu) denominator
+// den_i = Q_ii - sum_{j != i} Q_ij with Q_ij = -(1/T_i + 1/T_j).
+__global__ void k_qdiag(int64_t n, const int64_t* t_rp, const int32_t* t_col, const double* invt,
+                        double* qdiag, unsigned long long* maxden_bits) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double den = 0.0;
+  if (i < n) {
+    const double ti = invt[i];
+    double qii = 0.0, off = 0.0;
+    for (int64_t t = t_rp[i]; t < t_rp[i + 1]; ++t) {
+      double q = ti + invt[t_col[t]];
+      qii += q;
+      off -= q;
+    }
+    qdiag[i] = qii;
+    den = qii - off;
+  }
+  for (int o = 32; o > 0; o >>= 1) den = fmax(den, __shfl_xor(den, o));
+  if ((threadIdx.x & (kWave - 1)) == 0) atomic_max_pos_double(maxden_bits, den);
+}
+
+// Merged difference-form operator rows: [W columns | T columns].
+__global__ void k_pack(int64_t n, const int64_t* w_rp, const int32_t* w_col, const double* w_val,
+                       const int64_t* t_rp, const int32_t* t_col, int32_t* a_rp, int32_t* a_split,
+                       int32_t* a_col, double* a_w, float* a_w32) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i > n) return;
+  const int64_t start = w_rp[i] + t_rp[i];
+  a_rp[i] = (int32_t)start;
+  if (i == n) return;
+  const int64_t nw = w_rp[i + 1] - w_rp[i];
+  a_split[i] = (int32_t)(start + nw);
+  for (int64_t t = 0; t < nw; ++t) {
+    a_col[start + t] = w_col[w_rp[i] + t];
+    double v = w_val[w_rp[i] + t];
+    a_w[start + t] = v;
+    a_w32[start + t] = (float)v;
+  }
+  const int64_t tb = t_rp[i], te = t_rp[i + 1];
+  for (int64_t t = tb; t < te; ++t) a_col[start + nw + (t - tb)] = t_col[t];
+}
+
+// r_i = sum_{j != i} |A_ij| = d_i + mu Q_ii; log r partial sums (fixed order).
+__global__ void __launch_bounds__(kBlock) k_radius(int64_t n, const double* d, const double* qdiag,
+                                                   double mu, double* r, double* partial) {
+  __shared__ double sh[kBlock];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    double ri = d[i] + mu * qdiag[i];
+    r[i] = ri;
+    acc += log(ri);
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// b_i = r_i / (prod r)^(1/N) through logs; Jacobi 1 / A_ii, A_ii = d_i - mu Q_ii + eps.
+__global__ void k_bvec(int64_t n, const double* r, const double* d, const double* qdiag,
+                       const double* partial, int nparts, double mu, double eps, double* b,
+                       float* b32, double* dinv, float* dinv32, unsigned long long* maxdiag_bits) {
+  double sum = 0.0;
+  for (int q = 0; q < nparts; ++q) sum += partial[q];
+  const double mean = sum / (double)n;
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double diag = 0.0;
+  if (i < n) {
+    double bi = exp(log(r[i]) - mean);
+    b[i] = bi;
+    b32[i] = (float)bi;
+    diag = d[i] - mu * qdiag[i] + eps;
+    dinv[i] = 1.0 / diag;
+    dinv32[i] = (float)(1.0 / diag);
+  }
+  for (int o = 32; o > 0; o >>= 1) diag = fmax(diag, __shfl_xor(diag, o));
+  if ((threadIdx.x & (kWave - 1)) == 0) atomic_max_pos_double(maxdiag_bits, diag);
+}
+
+// ---------------------------------------------------------------------------
+// Host orchestration
+// ---------------------------------------------------------------------------
+
+template <typename T>
+static int read_scalar(const T* dev, T* host, hipStream_t s) {
+  ME_TRY(hipMemcpyAsync(host, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+  ME_TRY(hipStreamSynchronize(s));
+  return ME_OK;
+}
+
+int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g,
+                    me_info* info) {
+  const int64_t n = W->n, nnz = W->nnz;
+  if (n < 1 || nnz < 0 || !W->rowptr || (nnz > 0 && (!W->col || !W->val)))
+    return ME_ERR_INVALID_ARG;
+  if (n >= (int64_t)INT32_MAX) return ME_ERR_TOO_LARGE;
+  ME_TRY(hipGetDevice(&g->device));
+  g->n = n;
+  g->nnz_w = nnz;
+
+  // ---- allocation 1: W copy, per-node arrays, scratch of the count phase
+  size_t b1 = 0;
+  b1 += Arena::round((n + 1) * 8) + Arena::round(nnz * 4) + Arena::round(nnz * 8);  // W
+  b1 += Arena::round((n + 1) * 8) + Arena::round(n * 4);                            // t_rp, t_cnt
+  b1 += 7 * Arena::round(n * 8) + 3 * Arena::round(n * 4);                          // per node
+  b1 += Arena::round((n + 1) * 4) + Arena::round(n * 4);                            // a_rp, a_split
+  b1 += Arena::round(sizeof(int) * 64);
+  void* mem1 = nullptr;
+  ME_TRY(hipMallocAsync(&mem1, b1, s));
+  g->mem = mem1;
+  g->mem_bytes = b1;
+  Arena ar{(char*)mem1, b1, 0};
+  g->w_rp = ar.take<int64_t>(n + 1);
+  g->w_col = ar.take<int32_t>(nnz > 0 ? nnz : 1);
+  g->w_val = ar.take<double>(nnz > 0 ? nnz : 1);
+  g->t_rp = ar.take<int64_t>(n + 1);
+  g->t_cnt = ar.take<int32_t>(n);
+  g->d = ar.take<double>(n);
+  g->qdiag = ar.take<double>(n);
+  g->r = ar.take<double>(n);
+  g->b = ar.take<double>(n);
+  g->dinv = ar.take<double>(n);
+  g->invt = ar.take<double>(n);
+  double* scratch_d = ar.take<double>(n);  // tile sums / partials / parents
+  g->b32 = ar.take<float>(n);
+  g->dinv32 = ar.take<float>(n);
+  g->invt32 = ar.take<float>(n);
+  g->a_rp = ar.take<int32_t>(n + 1);
+  g->a_split = ar.take<int32_t>(n);
+  int* dflags = ar.take<int>(64);
+  if (!dflags) return ME_ERR_HIP;
+
+  ME_TRY(hipMemcpyAsync(g->w_rp, W->rowptr, (n + 1) * 8, hipMemcpyDeviceToDevice, s));
+  if (nnz > 0) {
+    ME_TRY(hipMemcpyAsync(g->w_col, W->col, nnz * 4, hipMemcpyDeviceToDevice, s));
+    ME_TRY(hipMemcpyAsync(g->w_val, W->val, nnz * 8, hipMemcpyDeviceToDevice, s));
+  }
+  ME_TRY(hipMemsetAsync(dflags, 0, sizeof(int) * 64, s));
+
+  // ---- validation (row pointers first: the row kernel indexes with them)
+  k_check_rowptr<<<ceil_div(n + 1, kBlock), kBlock, 0, s>>>(n, nnz, g->w_rp, dflags);
+  int hflags = 0;
+  ME_TRY_STATUS(read_scalar(dflags, &hflags, s));
+  if (hflags) return flags_to_status(hflags);
+  k_validate_rows<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->w_rp, g->w_col, g->w_val, g->d,
+                                                         dflags);
+  ME_TRY_STATUS(read_scalar(dflags, &hflags, s));
+  if (hflags) return flags_to_status(hflags);
+
+  // ---- two-hop pattern: count
+  int32_t* big_list = reinterpret_cast<int32_t*>(g->r);  // n int32 fit in n doubles
+  int32_t* big_count = dflags + 1;
+  const int grid_lds = (int)std::min<int64_t>(n, 256 * 20);
+  k_twohop_lds<<<grid_lds, kWave, 0, s>>>(n, g->w_rp, g->w_col, 0, g->t_cnt, nullptr, nullptr,
+                                          big_list, big_count);
+  int nbig = 0;
+  ME_TRY_STATUS(read_scalar(big_count, &nbig, s));
+  uint32_t* bitmaps = nullptr;
+  const int64_t nwords = (n + 31) / 32;
+  const int grid_big = nbig > 0 ? std::min(nbig, 128) : 0;
+  if (nbig > 0) {
+    ME_TRY(hipMallocAsync((void**)&bitmaps, (size_t)grid_big * nwords * 4, s));
+    ME_TRY(hipMemsetAsync(bitmaps, 0, (size_t)grid_big * nwords * 4, s));
+    k_twohop_big<<<grid_big, 256, 0, s>>>(n, g->w_rp, g->w_col, 0, big_list, nbig, bitmaps,
+                                          g->t_cnt, nullptr, nullptr);
+  }
+  int64_t* tile_tmp = reinterpret_cast<int64_t*>(scratch_d);
+  scan_counts(n, g->t_cnt, g->t_rp, tile_tmp, s);
+  int64_t nnz_t = 0;
+  ME_TRY_STATUS(read_scalar(g->t_rp + n, &nnz_t, s));
+  g->nnz_t = nnz_t;
+  if (nnz + nnz_t >= (int64_t)INT32_MAX) {
+    if (bitmaps) (void)hipFreeAsync(bitmaps, s);
+    return ME_ERR_TOO_LARGE;
+  }
+
+  // ---- allocation 2: T columns and the merged operator
+  size_t b2 = Arena::round(nnz_t * 4 + 4) + Arena::round((nnz + nnz_t) * 4 + 4) +
+              Arena::round((nnz + nnz_t) * 8 + 8) + Arena::round((nnz + nnz_t) * 4 + 4);
+  void* mem2 = nullptr;
+  ME_TRY(hipMallocAsync(&mem2, b2, s));
+  g->mem2 = mem2;
+  Arena ar2{(char*)mem2, b2, 0};
+  g->t_col = ar2.take<int32_t>(nnz_t + 1);
+  g->a_col = ar2.take<int32_t>(nnz + nnz_t + 1);
+  g->a_w = ar2.take<double>(nnz + nnz_t + 1);
+  g->a_w32 = ar2.take<float>(nnz + nnz_t + 1);
+  g->mem_bytes += b2;
+
+  k_twohop_lds<<<grid_lds, kWave, 0, s>>>(n, g->w_rp, g->w_col, 1, g->t_cnt, g->t_rp, g->t_col,
+                                          big_list, big_count);
+  if (nbig > 0) {
+    k_twohop_big<<<grid_big, 256, 0, s>>>(n, g->w_rp, g->w_col, 1, big_list, nbig, bitmaps,
+                                          g->t_cnt, g->t_rp, g->t_col);
+    ME_TRY(hipFreeAsync(bitmaps, s));
+  }
+
+  // ---- connectivity of the two-hop graph
+  int32_t* parent = reinterpret_cast<int32_t*>(scratch_d);
+  int* roots = dflags + 2;
+  k_uf_init<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, parent);
+  k_uf_hook<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->t_rp, g->t_col, parent);
+  k_uf_count_roots<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, parent, roots);
+
+  // ---- Q diagonal, mu denominators, packed operator
+  k_invt<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->t_cnt, g->invt, g->invt32);
+  unsigned long long* maxden_bits = reinterpret_cast<unsigned long long*>(dflags + 4);
+  unsigned long long* maxdiag_bits = reinterpret_cast<unsigned long long*>(dflags + 6);
+  k_qdiag<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->t_rp, g->t_col, g->invt, g->qdiag,
+                                                 maxden_bits);
+  k_pack<<<ceil_div(n + 1, kBlock), kBlock, 0, s>>>(n, g->w_rp, g->w_col, g->w_val, g->t_rp,
+                                                    g->t_col, g->a_rp, g->a_split, g->a_col,
+                                                    g->a_w, g->a_w32);
+  int hroots = 0;
+  unsigned long long hmaxden = 0;
+  ME_TRY_STATUS(read_scalar(roots, &hroots, s));
+  ME_TRY_STATUS(read_scalar(maxden_bits, &hmaxden, s));
+  g->components = hroots;
+  double maxden;
+  std::memcpy(&maxden, &hmaxden, 8);
+  g->maxden = maxden;
+
+  // ---- eps = lambda_2(Q)
+  double eps = 0.0;
+  int eps_iters = 0;
+  int st = ME_OK;
+  if (hroots > 1 || n < 2) {
+    st = ME_WARN_EPS_ZERO;
+  } else {
+    ME_TRY_STATUS(solve_eps(*g, o, s, &eps, &eps_iters));
+    if (!(eps > 0.0)) st = ME_WARN_EPS_ZERO, eps = 0.0;
+  }
+  g->eps = eps;
+  g->eps_iters = eps_iters;
+  // mu = min_i eps / den_i over den_i > 0 = eps / max_i den_i
+  g->mu = (eps > 0.0 && maxden > 0.0) ? eps / maxden : 0.0;
+
+  // ---- r, b, Jacobi diagonal
+  const int nparts = (int)std::min<int64_t>(ceil_div(n, kBlock), kPartialBlocks);
+  double* partial = reinterpret_cast<double*>(scratch_d);
+  k_radius<<<nparts, kBlock, 0, s>>>(n, g->d, g->qdiag, g->mu, g->r, partial);
+  k_bvec<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->r, g->d, g->qdiag, partial, nparts, g->mu,
+                                                g->eps, g->b, g->b32, g->dinv, g->dinv32,
+                                                maxdiag_bits);
+  unsigned long long hmaxdiag = 0;
+  ME_TRY_STATUS(read_scalar(maxdiag_bits, &hmaxdiag, s));
+  std::memcpy(&g->max_diag_a, &hmaxdiag, 8);
+  g->status = st;
+  if (info) {
+    info->eps = g->eps;
+    info->mu = g->mu;
+    info->eps_iterations = eps_iters;
+    info->status = st;
+  }
+  return st;
+}
+
+}  // namespace me

@@ -1,0 +1,63 @@
+"""The C ABI library loads on the CPU and exports every entry point that
+include/membed.h declares (no GPU call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "membed.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(me_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("me_build_graph_ops", "me_embed", "me_embed_workspace_bytes",
+                     "me_graph_ops_export", "me_graph_ops_destroy", "me_status_string"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2112_07862_amd import _lib
+    lib = _lib.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, f"{name} has no ctypes signature"
+
+
+def test_host_only_entry_points():
+    from paper_2112_07862_amd import _lib
+    lib = _lib.load()
+    o = _lib.MeOpts()
+    lib.me_opts_default(ctypes.byref(o))
+    assert o.precond == _lib.ME_PRECOND_JACOBI and o.max_iter > 0 and o.check_every > 0
+    assert 0 < o.eps_tol < 1e-6
+    for st in list(_lib.STATUS_NAMES):
+        assert lib.me_status_string(st).decode()
+    assert lib.me_embed_workspace_bytes(None, 4, None) == 0
+    assert lib.me_graph_ops_bytes(None) == 0
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    from paper_2112_07862_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(RuntimeError, match="not found"):
+        _lib.load()
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2112_07862_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f
+                assert "synthgraphs" not in src, f

@@ -1,0 +1,212 @@
+"""Parity of the HIP path (through the C ABI) against the CPU FP64 oracle on
+the same seeded inputs.
+
+Bars: two-hop pattern, counts and sizes bit-exact; per-node scalars to FP64
+rounding; eps and mu relative 1e-9; generalized eigenvalues relative 1e-6;
+sine of the largest B-principal angle of the K-subspace 1e-5 (with the solve
+tolerance set from the oracle's relative gap, so that the bound
+sin theta <= rho / relgap is below 1e-5); X^T B X = I to 1e-10."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+import oracle
+import synthgraphs as sg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def me():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_2112_07862_amd as pkg
+    pkg.load()
+    return pkg
+
+
+def _graphs():
+    return {
+        "square_2k": lambda: sg.manifold_graph("square", 2000, 8, 0),
+        "swiss_3k": lambda: sg.manifold_graph("swiss_roll", 3000, 10, 1),
+        "sphere_3k": lambda: sg.manifold_graph("sphere", 3000, 12, 2),
+        "torus_2500": lambda: sg.manifold_graph("torus", 2500, 8, 3),
+        "random_300": lambda: sg.random_graph(300, 0.05, 4),
+        "ring_40": lambda: sg.ring(40, 2),
+        "ring_203": lambda: sg.ring(203, 3),
+        "tri_mesh": lambda: sg.tri_mesh(3),
+        "line_5": lambda: sg.line(5),
+        "grid_bipartite": lambda: sg.grid(30, 40),
+        "star_1500": lambda: sg.star(1500),
+        "two_squares": lambda: sg.disjoint_union([sg.manifold_graph("square", 400, 8, 5),
+                                                  sg.manifold_graph("square", 300, 8, 6)]),
+    }
+
+
+GRAPHS = _graphs()
+_cache = {}
+
+
+def oracle_ops(name):
+    if name not in _cache:
+        g = GRAPHS[name]()
+        _cache[name] = (g, oracle.build_ops(g.n, g.rowptr, g.col, g.val))
+    return _cache[name]
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_operators_match_oracle(me, name):
+    g, ops = oracle_ops(name)
+    print(f"[gpu] operators {name} n={g.n}", flush=True)
+    h = me.build_graph_ops(g)
+    ex = h.export()
+    # two-hop pattern: bit-exact
+    assert h.nnz_t == len(ops["t_col"])
+    assert np.array_equal(_np(ex["t_rowptr"]), ops["t_rowptr"])
+    assert np.array_equal(_np(ex["t_col"]), ops["t_col"])
+    assert np.array_equal(_np(ex["t_count"]), ops["t_count"])
+    # per-node scalars
+    np.testing.assert_allclose(_np(ex["d"]), ops["d"], rtol=1e-14, atol=0)
+    np.testing.assert_allclose(_np(ex["qdiag"]), ops["Q"].diagonal(), rtol=1e-13, atol=0)
+    # eps, mu
+    if ops["eps"] == 0.0:
+        assert h.eps == 0.0 and h.mu == 0.0 and h.two_hop_disconnected == (ops["components"] > 1)
+    else:
+        assert abs(h.eps - ops["eps"]) <= 1e-9 * ops["eps"], (h.eps, ops["eps"])
+        assert abs(h.mu - ops["mu"]) <= 1e-9 * ops["mu"]
+    np.testing.assert_allclose(_np(ex["r"]), ops["r"], rtol=2e-9, atol=0)
+    np.testing.assert_allclose(_np(ex["b"]), ops["b"], rtol=2e-9, atol=0)
+    h.close()
+
+
+@pytest.mark.parametrize("name", ["square_2k", "sphere_3k", "random_300", "ring_40", "tri_mesh",
+                                  "star_1500"])
+@pytest.mark.parametrize("k", [1, 3, 8, 16])
+def test_apply_matches_oracle(me, name, k):
+    g, ops = oracle_ops(name)
+    print(f"[gpu] apply {name} k={k}", flush=True)
+    h = me.build_graph_ops(g)
+    X = sg.initial_block(g.n, k, 99)
+    Xd = torch.tensor(X, device="cuda")
+    # the handle's own eps and mu (equal to the oracle's within 1e-9)
+    L, Q = ops["L"], ops["Q"]
+    A = L - h.mu * Q + h.eps * sp.identity(g.n)
+    for which, M in (("A", A), ("Q", Q)):
+        Y = _np(h.apply(which, Xd))
+        ref = M @ X
+        scale = np.abs(M).max() * np.abs(X).max() * 64
+        assert np.max(np.abs(Y - ref)) <= 1e-14 * scale, which
+    YB = _np(h.apply("B", Xd))
+    np.testing.assert_allclose(YB, ops["b"][:, None] * X, rtol=2e-9)
+    h.close()
+
+
+EMBED_CASES = [
+    # name, K
+    ("square_2k", 4),
+    ("sphere_3k", 16),
+    ("torus_2500", 8),
+    ("swiss_3k", 8),
+    ("random_300", 5),
+    ("ring_203", 3),
+    ("tri_mesh", 3),
+]
+
+
+@pytest.mark.parametrize("name,K", EMBED_CASES)
+def test_embed_matches_oracle(me, name, K):
+    g, ops = oracle_ops(name)
+    lam_o, V_o = oracle.generalized_eigs(ops["A"], ops["b"], K)
+    relgap = (lam_o[K] - lam_o[K - 1]) / lam_o[K - 1]
+    tol = min(1e-6, 1e-5 * relgap / 4)
+    print(f"[gpu] embed {name} n={g.n} K={K} tol={tol:.2e} relgap={relgap:.3g}", flush=True)
+    X, lam, info = me.embed(g, K, tol=tol, seed=1)
+    X, lam = _np(X), _np(lam)
+    assert info["status"] == 0, info
+    np.testing.assert_array_less(np.abs(lam - lam_o[:K]) / np.abs(lam_o[:K]), 1e-6)
+    s = oracle.sin_principal_angle_b(X, V_o[:, :K], ops["b"])
+    assert s <= 1e-5, s
+    assert oracle.b_orthonormality_error(X, ops["b"]) <= 1e-10
+    rho = oracle.relative_residuals(ops["A"], ops["b"], X, lam)
+    assert np.all(rho <= tol * 1.01 + 1e-12), rho
+    # sign convention: largest-magnitude entry of each column positive
+    idx = np.argmax(np.abs(X), axis=0)
+    assert np.all(X[idx, np.arange(K)] > 0)
+
+
+def test_embed_eps_zero_graph(me):
+    """A bipartite grid: two-hop graph disconnected, eps = mu = 0, A = L;
+    lambda_1 = 0 with a constant vector."""
+    g, ops = oracle_ops("grid_bipartite")
+    K = 4
+    lam_o, V_o = oracle.generalized_eigs(ops["A"], ops["b"], K)
+    X, lam, info = me.embed(g, K, tol=1e-8, seed=2)
+    assert info["status_name"] == "ME_WARN_EPS_ZERO"
+    lam = _np(lam)
+    assert abs(lam[0]) < 1e-10
+    np.testing.assert_allclose(lam[1:], lam_o[1:K], rtol=1e-6)
+
+
+def test_embed_with_explicit_start_block_and_determinism(me):
+    g, ops = oracle_ops("square_2k")
+    X0 = torch.tensor(sg.initial_block(g.n, 4, 5), device="cuda")
+    X1, l1, _ = me.embed(g, 4, tol=1e-8, X0=X0)
+    X2, l2, _ = me.embed(g, 4, tol=1e-8, X0=X0)
+    assert torch.equal(X1, X2) and torch.equal(l1, l2)
+
+
+@pytest.mark.parametrize("bad,status", [
+    ("negative_weight", "ME_ERR_BAD_WEIGHT"),
+    ("asymmetric", "ME_ERR_NOT_SYMMETRIC"),
+    ("self_loop", "ME_ERR_SELF_LOOP"),
+    ("col_range", "ME_ERR_INVALID_ARG"),
+    ("unsorted", "ME_ERR_INVALID_ARG"),
+    ("isolated", "ME_ERR_ISOLATED_NODE"),
+    ("rowptr", "ME_ERR_INVALID_ARG"),
+])
+def test_invalid_graphs_rejected(me, bad, status):
+    g = sg.random_graph(30, 0.2, 7, wlo=1.0, whi=2.0)
+    rp, col, val = g.rowptr.copy(), g.col.copy(), g.val.copy()
+    n = g.n
+    if bad == "negative_weight":
+        val[0] = -1.0
+    elif bad == "asymmetric":
+        val[2] = 0.5
+    elif bad == "self_loop":
+        col[0] = 0
+    elif bad == "col_range":
+        col[1] = n + 5
+    elif bad == "unsorted":
+        col[rp[3]], col[rp[3] + 1] = col[rp[3] + 1], col[rp[3]]
+    elif bad == "isolated":
+        g = sg.from_edges(4, np.array([0, 1]), np.array([1, 2]), np.array([1.0, 1.0]))
+        rp, col, val, n = g.rowptr, g.col, g.val, g.n
+    elif bad == "rowptr":
+        rp[5] = rp[4] - 1
+    bad_g = sg.CSR(n, rp, col.astype(np.int32), val)
+    with pytest.raises(me.MembedError) as e:
+        me.build_graph_ops(bad_g)
+    assert e.value.name == status
+
+
+def test_k_range_errors(me):
+    g = sg.manifold_graph("square", 100, 8, 1)
+    with pytest.raises(me.MembedError) as e:
+        me.embed(g, 17)
+    assert e.value.name == "ME_ERR_K_RANGE"
+    with pytest.raises(me.MembedError) as e:
+        me.embed(g, 0)
+    assert e.value.name == "ME_ERR_K_RANGE"
+    g = sg.tri_mesh(3)  # dense path: K <= n
+    with pytest.raises(me.MembedError) as e:
+        me.embed(g, 11)
+    assert e.value.name == "ME_ERR_K_RANGE"
+    # smallest LOBPCG graph with the largest block: 3 * 16 <= 49
+    g = sg.ring(49, 2)
+    X, lam, info = me.embed(g, 16, tol=1e-8)
+    assert info["status"] == 0 and info["block"] == 16
