@@ -31,10 +31,11 @@ if ROOT not in sys.path:
 
 METRIC = "graph nodes embedded/sec at rel. residual ≤1e-6; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
-KERNELS = {"spmm": 1, "gram": 2, "combine": 3}
+KERNELS = {"spmm": 1, "gram": 2, "combine": 3, "cheb": 4}
 KERNEL_NAMES = {"spmm": "k_spmm (difference-form SpMM of A on the LOBPCG block)",
                 "gram": "k_gram (Rayleigh-Ritz Gram S^T B S, S^T A S on MFMA)",
-                "combine": "k_combine (block update X, P, AX, AP)"}
+                "combine": "k_combine (block update X, P, AX, AP)",
+                "cheb": "k_cheb_step (Chebyshev preconditioner step: fused SpMM + recurrence)"}
 
 
 def cpu_baseline(kind: str, n: int, knn: int, K: int, seed: int) -> dict:
@@ -65,8 +66,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="swiss_roll_100k")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--time-kernel", default="spmm", choices=list(KERNELS))
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    ap.add_argument("--time-kernel", default="cheb", choices=list(KERNELS))
     ap.add_argument("--cpu-sample-n", type=int, default=50_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()

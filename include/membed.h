@@ -53,8 +53,12 @@ typedef enum {
  * The small dense solves (Cholesky, Rayleigh-Ritz) and the final residual
  * certificate are always FP64. */
 enum { ME_FP64 = 0, ME_MIXED = 1 };
-/* Preconditioner T of the LOBPCG residual: none, or Jacobi diag(A)^-1. */
-enum { ME_PRECOND_NONE = 0, ME_PRECOND_JACOBI = 1 };
+/* Preconditioner T of the LOBPCG residual (the paper names LOBPCG and leaves
+ * T open): none; Jacobi diag(A)^-1; or `cheb_degree` steps of Chebyshev
+ * iteration for A y = r with Jacobi scaling, i.e. a polynomial in
+ * diag(A)^-1 A that approximates A^-1 on [a, b] (b: Gershgorin bound,
+ * a: half the diag(A)-Rayleigh quotient of the leading Ritz vector). */
+enum { ME_PRECOND_NONE = 0, ME_PRECOND_JACOBI = 1, ME_PRECOND_CHEBYSHEV = 2 };
 
 /* Input graph W (Section 3.1), CSR, device memory, owned by the caller and
  * only read during the call.  rowptr int64[n+1] (rowptr[0] = 0), col int32[nnz]
@@ -71,12 +75,13 @@ typedef struct {
 
 typedef struct {
   int precision;      /* ME_FP64 (default) or ME_MIXED                              */
-  int precond;        /* ME_PRECOND_JACOBI (default) or ME_PRECOND_NONE             */
+  int precond;        /* ME_PRECOND_CHEBYSHEV (default), _JACOBI or _NONE           */
   int max_iter;       /* LOBPCG iteration cap for the embedding solve (default 20000) */
   int eps_max_iter;   /* iteration cap for the eps = lambda_2(Q) solve (default 20000) */
   double eps_tol;     /* relative residual target of the eps solve (default 1e-8)   */
   int check_every;    /* iterations enqueued between host convergence reads (default 16) */
   uint64_t seed;      /* seed of the library's starting blocks (default 0)          */
+  int cheb_degree;    /* Chebyshev preconditioner degree, 2..64 (default 32)        */
 } me_opts;
 
 /* Per-solve report.  Times are host wall-clock milliseconds of the phases. */
@@ -133,6 +138,14 @@ int me_graph_ops_export(const me_graph_ops* ops, int64_t* T_rowptr, int32_t* T_c
                         int32_t* T_count, double* d, double* qdiag, double* r,
                         double* b, void* stream);
 
+/* The node order the solver works in (a locality order; outputs are always
+ * in the caller's order): perm[i] = caller's node id of solver row i
+ * (device int32[n]).  Breadth-first levels from a pseudo-peripheral node
+ * (the lowest-numbered node on the last level of a search from node 0),
+ * ties by node id, further components after the first, each started at
+ * its lowest-numbered node.  A test and diagnostic hook.  Synchronises. */
+int me_graph_ops_order(const me_graph_ops* ops, int32_t* perm, void* stream);
+
 /* Applies the operators to a dense block (device, row-major n x k, 1 <= k <= 16):
  * which = 0: Y = A X;  1: Y = Q X;  2: Y = B X.  FP64, difference form.
  * A test and diagnostic hook; not on the solve path. */
@@ -168,7 +181,8 @@ int me_embed(const me_graph_ops* ops, int K, double tol, const me_opts* opts,
 /* Kernel timing (diagnostic).  me_kernel_timing(kind) starts timing every
  * launch of one kernel kind with HIP events recorded on the launching stream
  * (kind 0 = off, 1 = SpMM of A on the embedding block, 2 = Rayleigh-Ritz
- * Gram of the embedding block, 3 = block combine of the embedding block) and
+ * Gram of the embedding block, 3 = block combine of the embedding block,
+ * 4 = Chebyshev preconditioner step of the embedding solve) and
  * clears the totals.  me_kernel_timing_read returns the number of launches,
  * their summed duration in milliseconds and the algorithmic bytes they moved
  * (host outputs).  Totals are updated when me_embed returns. */

@@ -15,7 +15,7 @@ ME_OK = 0
 ME_WARN_NOT_CONVERGED = 1
 ME_WARN_EPS_ZERO = 2
 ME_FP64, ME_MIXED = 0, 1
-ME_PRECOND_NONE, ME_PRECOND_JACOBI = 0, 1
+ME_PRECOND_NONE, ME_PRECOND_JACOBI, ME_PRECOND_CHEBYSHEV = 0, 1, 2
 
 STATUS_NAMES = {
     0: "ME_OK", 1: "ME_WARN_NOT_CONVERGED", 2: "ME_WARN_EPS_ZERO", -1: "ME_ERR_INVALID_ARG",
@@ -33,7 +33,7 @@ class MeCsr(ctypes.Structure):
 class MeOpts(ctypes.Structure):
     _fields_ = [("precision", c_int), ("precond", c_int), ("max_iter", c_int),
                 ("eps_max_iter", c_int), ("eps_tol", c_double), ("check_every", c_int),
-                ("seed", c_uint64)]
+                ("seed", c_uint64), ("cheb_degree", c_int)]
 
 
 class MeInfo(ctypes.Structure):
@@ -58,6 +58,7 @@ SIGNATURES = {
     "me_graph_ops_bytes": (c_size_t, [c_void_p]),
     "me_graph_ops_export": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_void_p, c_void_p, c_void_p]),
+    "me_graph_ops_order": (c_int, [c_void_p, c_void_p, c_void_p]),
     "me_apply": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "me_embed_workspace_bytes": (c_size_t, [c_void_p, c_int, ctypes.POINTER(MeOpts)]),
     "me_embed": (c_int, [c_void_p, c_int, c_double, ctypes.POINTER(MeOpts), c_void_p, c_void_p,
@@ -68,7 +69,7 @@ SIGNATURES = {
                                       ctypes.POINTER(c_double)]),
 }
 
-KT_OFF, KT_SPMM_A, KT_GRAM_RR, KT_COMBINE = 0, 1, 2, 3
+KT_OFF, KT_SPMM_A, KT_GRAM_RR, KT_COMBINE, KT_CHEB = 0, 1, 2, 3, 4
 
 _lib = None
 

@@ -34,11 +34,12 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 _PRECISION = {"fp64": L.ME_FP64, "mixed": L.ME_MIXED}
-_PRECOND = {"none": L.ME_PRECOND_NONE, "jacobi": L.ME_PRECOND_JACOBI}
+_PRECOND = {"none": L.ME_PRECOND_NONE, "jacobi": L.ME_PRECOND_JACOBI,
+            "chebyshev": L.ME_PRECOND_CHEBYSHEV}
 
 
-def make_opts(precision="fp64", precond="jacobi", max_iter=None, eps_max_iter=None,
-              eps_tol=None, check_every=None, seed=None) -> L.MeOpts:
+def make_opts(precision="fp64", precond="chebyshev", max_iter=None, eps_max_iter=None,
+              eps_tol=None, check_every=None, seed=None, cheb_degree=None) -> L.MeOpts:
     o = L.MeOpts()
     L.load().me_opts_default(ctypes.byref(o))
     o.precision = _PRECISION[precision]
@@ -53,6 +54,8 @@ def make_opts(precision="fp64", precond="jacobi", max_iter=None, eps_max_iter=No
         o.check_every = int(check_every)
     if seed is not None:
         o.seed = int(seed)
+    if cheb_degree is not None:
+        o.cheb_degree = int(cheb_degree)
     return o
 
 
@@ -125,6 +128,12 @@ class GraphOps:
             _stream_ptr(stream)), "export")
         out["t_col"] = out["t_col"][:nt]
         return out
+
+    def order(self, stream=None) -> torch.Tensor:
+        """Node order of the solver: perm[i] = caller's node of solver row i."""
+        perm = torch.empty(self.n, dtype=torch.int32, device=self._csr.rowptr.device)
+        _check(L.load().me_graph_ops_order(self.handle, _ptr(perm), _stream_ptr(stream)), "order")
+        return perm
 
     def apply(self, which: str, X: torch.Tensor, stream=None) -> torch.Tensor:
         """Y = A X, Q X or B X (FP64 difference form)."""

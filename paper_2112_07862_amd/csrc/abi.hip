@@ -12,12 +12,13 @@ extern "C" {
 void me_opts_default(me_opts* o) {
   if (!o) return;
   o->precision = ME_FP64;
-  o->precond = ME_PRECOND_JACOBI;
+  o->precond = ME_PRECOND_CHEBYSHEV;
   o->max_iter = 20000;
   o->eps_max_iter = 20000;
   o->eps_tol = 1e-8;
   o->check_every = 16;
   o->seed = 0;
+  o->cheb_degree = 32;
 }
 
 const char* me_status_string(int st) {
@@ -110,6 +111,14 @@ int me_graph_ops_export(const me_graph_ops* ops, int64_t* t_rowptr, int32_t* t_c
   return ME_OK;
 }
 
+int me_graph_ops_order(const me_graph_ops* ops, int32_t* perm, void* stream) {
+  if (!ops || !perm) return ME_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  ME_TRY(hipMemcpyAsync(perm, ops->g.perm, ops->g.n * 4, hipMemcpyDeviceToDevice, s));
+  ME_TRY(hipStreamSynchronize(s));
+  return ME_OK;
+}
+
 int me_apply(const me_graph_ops* ops, int which, int k, const double* X, double* Y,
              void* stream) {
   if (!ops || !X || !Y || k < 1 || k > kMaxBlockCols || which < 0 || which > 2)
@@ -126,9 +135,10 @@ int me_apply(const me_graph_ops* ops, int which, int k, const double* X, double*
   const size_t bytes = (size_t)g.n * kb * 8;
   ME_TRY(hipMallocAsync((void**)&buf, 2 * bytes, s));
   ME_TRY(hipMemsetAsync(buf, 0, bytes, s));
-  launch_copy_cols(g.n, k, kb, k, X, buf, s);
+  // into the solver order, apply, back to the caller's order
+  launch_copy_cols(g.n, k, kb, k, g.perm, X, buf, s);
   launch_spmm<double>(g, kb, which == 0 ? OP_A : OP_Q, buf, buf + (size_t)g.n * kb, nullptr, s);
-  launch_copy_cols(g.n, kb, k, k, buf + (size_t)g.n * kb, Y, s);
+  launch_copy_cols(g.n, kb, k, k, g.iperm, buf + (size_t)g.n * kb, Y, s);
   ME_TRY(hipFreeAsync(buf, s));
   ME_TRY(hipStreamSynchronize(s));
   return ME_OK;
@@ -146,7 +156,9 @@ int me_embed(const me_graph_ops* ops, int K, double tol, const me_opts* opts, co
   if (!ops) return ME_ERR_INVALID_ARG;
   me_opts o;
   if (opts) o = *opts; else me_opts_default(&o);
-  if (o.max_iter < 1 || o.check_every < 1) return ME_ERR_INVALID_ARG;
+  if (o.max_iter < 1 || o.check_every < 1 || o.precond < 0 || o.precond > 2 ||
+      (o.precond == ME_PRECOND_CHEBYSHEV && (o.cheb_degree < 2 || o.cheb_degree > 64)))
+    return ME_ERR_INVALID_ARG;
   return embed(ops->g, K, tol, &o, X0, ws, ws_bytes, X, lambda, info, (hipStream_t)stream);
 }
 

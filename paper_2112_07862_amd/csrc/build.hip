@@ -359,6 +359,231 @@ __global__ void k_uf_count_roots(int64_t n, int32_t* parent, int* roots) {
 }
 
 // ---------------------------------------------------------------------------
+// Locality order of the solver.  The LOBPCG kernels gather the rows of the
+// neighbours (one- and two-hop) of every row; with the caller's node order
+// (random for sampled point clouds) each gather touches its own cache line.
+// Nodes are ordered by breadth-first level from a pseudo-peripheral node
+// (the lowest-numbered node on the last level of a search from node 0),
+// ties by node id, components one after the other: neighbours then lie
+// within a few level widths of each other.  Levels come from a
+// level-synchronous search; the order from a stable LSD radix sort on the
+// level, so the permutation is deterministic.
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_i32(int64_t n, int32_t* a, int32_t v) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void k_bfs_seed(int32_t* level, int32_t* frontier, int32_t* counts, int32_t node,
+                           int32_t lev) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    level[node] = lev;
+    frontier[0] = node;
+    counts[lev] = 1;
+  }
+}
+
+// One level: every node of frontier `fin` (counts[lev] of them) claims its
+// unvisited neighbours for level lev + 1 and appends them to `fout`.
+__global__ void k_bfs_level(const int64_t* rp, const int32_t* col, int32_t* level,
+                            const int32_t* fin, int32_t* fout, int32_t* counts, int32_t lev) {
+  const int32_t nin = counts[lev];
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nin; i += gridDim.x * blockDim.x) {
+    const int32_t u = fin[i];
+    for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
+      const int32_t v = col[t];
+      if (__atomic_load_n(&level[v], __ATOMIC_RELAXED) < 0 && atomicCAS(&level[v], -1, lev + 1) == -1)
+        fout[atomicAdd(&counts[lev + 1], 1)] = v;
+    }
+  }
+}
+
+// lowest node id with level == lev (lev = -1: lowest unvisited node)
+__global__ void k_min_node_at(int64_t n, const int32_t* level, int32_t lev, int32_t* out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n && level[i] == lev) atomicMin(out, (int32_t)i);
+}
+
+// --- stable LSD radix sort of (key, value) int32 pairs, 8-bit digits ------
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 4 * kRsThreads;  // per block
+
+__global__ void __launch_bounds__(kRsThreads) k_rs_count(int64_t n, const int32_t* key, int shift,
+                                                         int nblk, int32_t* cnt) {
+  __shared__ int32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRsItems;
+  for (int r = 0; r < 4; ++r) {
+    const int64_t i = base + r * kRsThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(key[i] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  cnt[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];  // digit-major
+}
+
+// Items of a block are placed in index order within each digit: per round
+// of 256 items, the rank among equal digits is the count in earlier rounds,
+// earlier waves of this round and earlier lanes of this wave.
+__global__ void __launch_bounds__(kRsThreads) k_rs_scatter(int64_t n, const int32_t* key,
+                                                           const int32_t* val, int shift, int nblk,
+                                                           const int64_t* off, int32_t* key_out,
+                                                           int32_t* val_out) {
+  __shared__ int32_t running[256];
+  __shared__ int32_t wcnt[kRsThreads / kWave][256];
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  running[tid] = 0;
+  const int64_t base = (int64_t)blockIdx.x * kRsItems;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (int r = 0; r < 4; ++r) {
+    for (int q = 0; q < kRsThreads / kWave; ++q) wcnt[q][tid] = 0;
+    const int64_t i = base + r * kRsThreads + tid;
+    const bool valid = i < n;
+    const int32_t k = valid ? key[i] : 0;
+    const int d = (k >> shift) & 255;
+    unsigned long long mask = __ballot(valid);
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool b = (d >> bit) & 1;
+      const unsigned long long bs = __ballot(valid && b);
+      mask &= b ? bs : ~bs;
+    }
+    const int rank = __popcll(mask & lt);
+    __syncthreads();
+    if (valid && rank == 0) wcnt[wave][d] = __popcll(mask);
+    __syncthreads();
+    if (valid) {
+      int64_t pos = off[(int64_t)d * nblk + blockIdx.x] + running[d] + rank;
+      for (int q = 0; q < wave; ++q) pos += wcnt[q][d];
+      key_out[pos] = k;
+      val_out[pos] = val[i];
+    }
+    __syncthreads();
+    int add = 0;
+    for (int q = 0; q < kRsThreads / kWave; ++q) add += wcnt[q][tid];
+    running[tid] += add;
+    __syncthreads();
+  }
+}
+
+__global__ void k_iota(int64_t n, int32_t* a) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) a[i] = (int32_t)i;
+}
+
+__global__ void k_invert_perm(int64_t n, const int32_t* perm, int32_t* iperm) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) iperm[perm[i]] = (int32_t)i;
+}
+
+// BFS from `start` (levels from lev0) over the component; returns the last
+// non-empty level.
+static int bfs_component(const GraphOps* g, int32_t* level, int32_t* fa, int32_t* fb,
+                         int32_t* counts, int32_t start, int32_t lev0, int32_t* host_counts,
+                         hipStream_t s, int* last) {
+  constexpr int kChunk = 32;
+  k_bfs_seed<<<1, 1, 0, s>>>(level, fa, counts, start, lev0);
+  const int grid = 512;
+  for (int32_t l0 = lev0;; l0 += kChunk) {
+    for (int32_t l = l0; l < l0 + kChunk; ++l) {
+      if (l + 1 > g->n) break;
+      const bool even = ((l - lev0) & 1) == 0;
+      k_bfs_level<<<grid, 256, 0, s>>>(g->w_rp, g->w_col, level, even ? fa : fb, even ? fb : fa,
+                                       counts, l);
+    }
+    const int64_t hi = std::min<int64_t>(l0 + kChunk, g->n);
+    const int cnt = (int)(hi - l0 + 1);
+    ME_TRY(hipMemcpyAsync(host_counts, counts + l0, cnt * 4, hipMemcpyDeviceToHost, s));
+    ME_TRY(hipStreamSynchronize(s));
+    for (int j = 1; j < cnt; ++j) {
+      if (host_counts[j] == 0) {
+        *last = l0 + j - 1;
+        return ME_OK;
+      }
+    }
+    if (hi >= g->n) {
+      *last = (int)g->n - 1;
+      return ME_OK;
+    }
+  }
+}
+
+// perm (solver index -> user index), iperm (user -> solver).
+static int locality_order(GraphOps* g, int32_t* perm, int32_t* iperm, hipStream_t s) {
+  const int64_t n = g->n;
+  if (n <= kDenseMaxN) {
+    k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, perm);
+    k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, iperm);
+    return ME_OK;
+  }
+  const int64_t nblk = ceil_div(n, kRsItems);
+  const size_t bytes = Arena::round((n + 2) * 4) * 7 + Arena::round(256 * nblk * 4) +
+                       Arena::round(256 * nblk * 8 + 8) + Arena::round((256 * nblk / kScanTile + 2) * 8) +
+                       Arena::round(64);
+  void* mem = nullptr;
+  ME_TRY(hipMallocAsync(&mem, bytes, s));
+  Arena a{(char*)mem, bytes, 0};
+  int32_t* level = a.take<int32_t>(n + 2);
+  int32_t* fa = a.take<int32_t>(n + 2);
+  int32_t* fb = a.take<int32_t>(n + 2);
+  int32_t* counts = a.take<int32_t>(n + 2);
+  int32_t* k2 = a.take<int32_t>(n + 2);
+  int32_t* v1 = a.take<int32_t>(n + 2);
+  int32_t* v2 = a.take<int32_t>(n + 2);
+  int32_t* cnt = a.take<int32_t>(256 * nblk);
+  int64_t* off = a.take<int64_t>(256 * nblk + 1);
+  int64_t* tiles = a.take<int64_t>(256 * nblk / kScanTile + 2);
+  int32_t* minv = a.take<int32_t>(16);
+  std::vector<int32_t> hc(40);
+  int st = ME_OK;
+  auto reset = [&]() -> int {
+    k_fill_i32<<<ceil_div(n + 2, kBlock), kBlock, 0, s>>>(n + 2, level, -1);
+    k_fill_i32<<<ceil_div(n + 2, kBlock), kBlock, 0, s>>>(n + 2, counts, 0);
+    return ME_OK;
+  };
+  auto min_at = [&](int32_t lev, int32_t* out) -> int {
+    k_fill_i32<<<1, 1, 0, s>>>(1, minv, INT32_MAX);
+    k_min_node_at<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, level, lev, minv);
+    ME_TRY(hipMemcpyAsync(out, minv, 4, hipMemcpyDeviceToHost, s));
+    ME_TRY(hipStreamSynchronize(s));
+    return ME_OK;
+  };
+  // pseudo-peripheral start: search from node 0, restart from its last level
+  reset();
+  int last = 0;
+  st = bfs_component(g, level, fa, fb, counts, 0, 0, hc.data(), s, &last);
+  int32_t start = 0;
+  if (st >= 0) st = min_at(last, &start);
+  if (st >= 0) {
+    reset();
+    st = bfs_component(g, level, fa, fb, counts, start, 0, hc.data(), s, &last);
+  }
+  // remaining components, lowest unvisited node first
+  while (st >= 0) {
+    int32_t nxt = INT32_MAX;
+    st = min_at(-1, &nxt);
+    if (st < 0 || nxt == INT32_MAX) break;
+    st = bfs_component(g, level, fa, fb, counts, nxt, last + 1, hc.data(), s, &last);
+  }
+  if (st >= 0) {
+    // stable sort of node ids by level
+    k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, v1);
+    int32_t *kin = level, *kout = k2, *vin = v1, *vout = v2;
+    for (int shift = 0; shift < 32 && (last >> shift) > 0; shift += 8) {
+      k_rs_count<<<nblk, kRsThreads, 0, s>>>(n, kin, shift, (int)nblk, cnt);
+      scan_counts(256 * nblk, cnt, off, tiles, s);
+      k_rs_scatter<<<nblk, kRsThreads, 0, s>>>(n, kin, vin, shift, (int)nblk, off, kout, vout);
+      std::swap(kin, kout);
+      std::swap(vin, vout);
+    }
+    ME_TRY(hipMemcpyAsync(perm, vin, n * 4, hipMemcpyDeviceToDevice, s));
+    k_invert_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, perm, iperm);
+  }
+  (void)hipFreeAsync(mem, s);
+  return st;
+}
+
+// ---------------------------------------------------------------------------
 // Per-node scalars
 // ---------------------------------------------------------------------------
 
@@ -379,7 +604,8 @@ __device__ inline void atomic_max_pos_double(unsigned long long* addr, double v)
 // Q_ii = sum_{j in T_i} (1/T_i + 1/T_j) and the eq. (mu) denominator
 // den_i = Q_ii - sum_{j != i} Q_ij with Q_ij = -(1/T_i + 1/T_j).
 __global__ void k_qdiag(int64_t n, const int64_t* t_rp, const int32_t* t_col, const double* invt,
-                        double* qdiag, unsigned long long* maxden_bits) {
+                        double* qdiag, double* qinv, float* qinv32,
+                        unsigned long long* maxden_bits) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   double den = 0.0;
   if (i < n) {
@@ -391,31 +617,56 @@ __global__ void k_qdiag(int64_t n, const int64_t* t_rp, const int32_t* t_col, co
       off -= q;
     }
     qdiag[i] = qii;
+    qinv[i] = qii > 0.0 ? 1.0 / qii : 0.0;
+    qinv32[i] = (float)qinv[i];
     den = qii - off;
   }
   for (int o = 32; o > 0; o >>= 1) den = fmax(den, __shfl_xor(den, o));
   if ((threadIdx.x & (kWave - 1)) == 0) atomic_max_pos_double(maxden_bits, den);
 }
 
-// Merged difference-form operator rows: [W columns | T columns].
-__global__ void k_pack(int64_t n, const int64_t* w_rp, const int32_t* w_col, const double* w_val,
-                       const int64_t* t_rp, const int32_t* t_col, int32_t* a_rp, int32_t* a_split,
-                       int32_t* a_col, double* a_w, float* a_w32) {
+// Merged difference-form operator rows in the solver order: solver row i'
+// is user row o = perm[i'], entries [W columns | T columns] in the user
+// row's order, columns renumbered by iperm.
+__global__ void k_row_len_perm(int64_t n, const int32_t* perm, const int64_t* w_rp,
+                               const int64_t* t_rp, int32_t* len) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t o = perm[i];
+  len[i] = (int32_t)((w_rp[o + 1] - w_rp[o]) + (t_rp[o + 1] - t_rp[o]));
+}
+
+__global__ void k_pack_perm(int64_t n, const int32_t* perm, const int32_t* iperm,
+                            const int64_t* off, const int64_t* w_rp, const int32_t* w_col,
+                            const double* w_val, const int64_t* t_rp, const int32_t* t_col,
+                            int32_t* a_rp, int32_t* a_split, int32_t* a_col, double* a_w,
+                            float* a_w32) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i > n) return;
-  const int64_t start = w_rp[i] + t_rp[i];
+  const int64_t start = off[i];
   a_rp[i] = (int32_t)start;
   if (i == n) return;
-  const int64_t nw = w_rp[i + 1] - w_rp[i];
+  const int32_t o = perm[i];
+  const int64_t nw = w_rp[o + 1] - w_rp[o];
   a_split[i] = (int32_t)(start + nw);
   for (int64_t t = 0; t < nw; ++t) {
-    a_col[start + t] = w_col[w_rp[i] + t];
-    double v = w_val[w_rp[i] + t];
+    a_col[start + t] = iperm[w_col[w_rp[o] + t]];
+    const double v = w_val[w_rp[o] + t];
     a_w[start + t] = v;
     a_w32[start + t] = (float)v;
   }
-  const int64_t tb = t_rp[i], te = t_rp[i + 1];
-  for (int64_t t = tb; t < te; ++t) a_col[start + nw + (t - tb)] = t_col[t];
+  const int64_t tb = t_rp[o], te = t_rp[o + 1];
+  for (int64_t t = tb; t < te; ++t) a_col[start + nw + (t - tb)] = iperm[t_col[t]];
+}
+
+// dst[i'] = src[perm[i']] for a double array and its FP32 copy
+__global__ void k_gather_node(int64_t n, const int32_t* perm, const double* src, double* dst,
+                              float* dst32) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = src[perm[i]];
+  dst[i] = v;
+  dst32[i] = (float)v;
 }
 
 // r_i = sum_{j != i} |A_ij| = d_i + mu Q_ii; log r partial sums (fixed order).
@@ -441,12 +692,13 @@ __global__ void __launch_bounds__(kBlock) k_radius(int64_t n, const double* d, c
 // b_i = r_i / (prod r)^(1/N) through logs; Jacobi 1 / A_ii, A_ii = d_i - mu Q_ii + eps.
 __global__ void k_bvec(int64_t n, const double* r, const double* d, const double* qdiag,
                        const double* partial, int nparts, double mu, double eps, double* b,
-                       float* b32, double* dinv, float* dinv32, unsigned long long* maxdiag_bits) {
+                       float* b32, double* dinv, float* dinv32, unsigned long long* maxdiag_bits,
+                       unsigned long long* maxratio_bits) {
   double sum = 0.0;
   for (int q = 0; q < nparts; ++q) sum += partial[q];
   const double mean = sum / (double)n;
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  double diag = 0.0;
+  double diag = 0.0, ratio = 0.0;
   if (i < n) {
     double bi = exp(log(r[i]) - mean);
     b[i] = bi;
@@ -454,9 +706,16 @@ __global__ void k_bvec(int64_t n, const double* r, const double* d, const double
     diag = d[i] - mu * qdiag[i] + eps;
     dinv[i] = 1.0 / diag;
     dinv32[i] = (float)(1.0 / diag);
+    ratio = (diag + r[i]) / diag;  // Gershgorin right end of row i of diag(A)^-1 A
   }
-  for (int o = 32; o > 0; o >>= 1) diag = fmax(diag, __shfl_xor(diag, o));
-  if ((threadIdx.x & (kWave - 1)) == 0) atomic_max_pos_double(maxdiag_bits, diag);
+  for (int o = 32; o > 0; o >>= 1) {
+    diag = fmax(diag, __shfl_xor(diag, o));
+    ratio = fmax(ratio, __shfl_xor(ratio, o));
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomic_max_pos_double(maxdiag_bits, diag);
+    atomic_max_pos_double(maxratio_bits, ratio);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -484,8 +743,10 @@ int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* 
   size_t b1 = 0;
   b1 += Arena::round((n + 1) * 8) + Arena::round(nnz * 4) + Arena::round(nnz * 8);  // W
   b1 += Arena::round((n + 1) * 8) + Arena::round(n * 4);                            // t_rp, t_cnt
-  b1 += 7 * Arena::round(n * 8) + 3 * Arena::round(n * 4);                          // per node
+  b1 += 8 * Arena::round(n * 8) + 4 * Arena::round(n * 4);                          // per node
   b1 += Arena::round((n + 1) * 4) + Arena::round(n * 4);                            // a_rp, a_split
+  b1 += 2 * Arena::round(n * 4) + 4 * Arena::round(n * 8) + 4 * Arena::round(n * 4);  // solver order
+  b1 += Arena::round((n + 1) * 8);                                                  // offsets
   b1 += Arena::round(sizeof(int) * 64);
   void* mem1 = nullptr;
   ME_TRY(hipMallocAsync(&mem1, b1, s));
@@ -503,12 +764,25 @@ int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* 
   g->b = ar.take<double>(n);
   g->dinv = ar.take<double>(n);
   g->invt = ar.take<double>(n);
+  g->qinv = ar.take<double>(n);
   double* scratch_d = ar.take<double>(n);  // tile sums / partials / parents
   g->b32 = ar.take<float>(n);
   g->dinv32 = ar.take<float>(n);
   g->invt32 = ar.take<float>(n);
+  g->qinv32 = ar.take<float>(n);
   g->a_rp = ar.take<int32_t>(n + 1);
   g->a_split = ar.take<int32_t>(n);
+  g->perm = ar.take<int32_t>(n);
+  g->iperm = ar.take<int32_t>(n);
+  g->invt_s = ar.take<double>(n);
+  g->qinv_s = ar.take<double>(n);
+  g->b_s = ar.take<double>(n);
+  g->dinv_s = ar.take<double>(n);
+  g->invt32_s = ar.take<float>(n);
+  g->qinv32_s = ar.take<float>(n);
+  g->b32_s = ar.take<float>(n);
+  g->dinv32_s = ar.take<float>(n);
+  int64_t* aoff = ar.take<int64_t>(n + 1);
   int* dflags = ar.take<int>(64);
   if (!dflags) return ME_ERR_HIP;
 
@@ -588,11 +862,22 @@ int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* 
   k_invt<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->t_cnt, g->invt, g->invt32);
   unsigned long long* maxden_bits = reinterpret_cast<unsigned long long*>(dflags + 4);
   unsigned long long* maxdiag_bits = reinterpret_cast<unsigned long long*>(dflags + 6);
+  unsigned long long* maxratio_bits = reinterpret_cast<unsigned long long*>(dflags + 8);
   k_qdiag<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->t_rp, g->t_col, g->invt, g->qdiag,
-                                                 maxden_bits);
-  k_pack<<<ceil_div(n + 1, kBlock), kBlock, 0, s>>>(n, g->w_rp, g->w_col, g->w_val, g->t_rp,
-                                                    g->t_col, g->a_rp, g->a_split, g->a_col,
-                                                    g->a_w, g->a_w32);
+                                                 g->qinv, g->qinv32, maxden_bits);
+  // locality order of the solver and the packed operator in that order
+  ME_TRY_STATUS(locality_order(g, g->perm, g->iperm, s));
+  int32_t* rowlen = reinterpret_cast<int32_t*>(g->r);  // n int32 fit in n doubles
+  k_row_len_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->w_rp, g->t_rp, rowlen);
+  scan_counts(n, rowlen, aoff, tile_tmp, s);
+  k_pack_perm<<<ceil_div(n + 1, kBlock), kBlock, 0, s>>>(n, g->perm, g->iperm, aoff, g->w_rp,
+                                                         g->w_col, g->w_val, g->t_rp, g->t_col,
+                                                         g->a_rp, g->a_split, g->a_col, g->a_w,
+                                                         g->a_w32);
+  k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->invt, g->invt_s,
+                                                       g->invt32_s);
+  k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->qinv, g->qinv_s,
+                                                       g->qinv32_s);
   int hroots = 0;
   unsigned long long hmaxden = 0;
   ME_TRY_STATUS(read_scalar(roots, &hroots, s));
@@ -623,10 +908,15 @@ int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* 
   k_radius<<<nparts, kBlock, 0, s>>>(n, g->d, g->qdiag, g->mu, g->r, partial);
   k_bvec<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->r, g->d, g->qdiag, partial, nparts, g->mu,
                                                 g->eps, g->b, g->b32, g->dinv, g->dinv32,
-                                                maxdiag_bits);
-  unsigned long long hmaxdiag = 0;
+                                                maxdiag_bits, maxratio_bits);
+  unsigned long long hmaxdiag = 0, hmaxratio = 0;
   ME_TRY_STATUS(read_scalar(maxdiag_bits, &hmaxdiag, s));
+  ME_TRY_STATUS(read_scalar(maxratio_bits, &hmaxratio, s));
   std::memcpy(&g->max_diag_a, &hmaxdiag, 8);
+  std::memcpy(&g->cheb_b_a, &hmaxratio, 8);
+  k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->b, g->b_s, g->b32_s);
+  k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->dinv, g->dinv_s,
+                                                       g->dinv32_s);
   g->status = st;
   if (info) {
     info->eps = g->eps;

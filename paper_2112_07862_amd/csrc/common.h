@@ -29,6 +29,7 @@ constexpr int kMaxBlockCols = 16;    // largest LOBPCG block width
 constexpr int kMaxBasis = 48;        // 3 x kMaxBlockCols: Rayleigh-Ritz basis size
 constexpr int kDenseMaxN = 48;       // graphs up to this size are solved densely
 constexpr int kPartialBlocks = 256;  // grid of the reducing streaming kernels
+constexpr int kMaxChebDegree = 64;   // largest Chebyshev preconditioner degree
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -66,6 +67,15 @@ struct Ctrl {
   double lam_floor;          // |lambda| below this is treated as zero ...
   double lam_scale;          // ... and replaced by this operator scale in rho
   double rho[kMaxBlockCols]; // last residuals
+  // Chebyshev preconditioner: spectrum of D^-1 Op taken as [cheb_a, cheb_b];
+  // cheb_a follows the leading Ritz pair (cheb_afac times its D-Rayleigh
+  // quotient).  Step k uses dd <- alpha_k dd + beta_k D^-1 (R - Op y).
+  int cheb_deg;
+  int pad2;
+  double cheb_afac;
+  double cheb_a, cheb_b, cheb_theta;
+  double cheb_alpha[kMaxChebDegree];
+  double cheb_beta[kMaxChebDegree];
 };
 
 // Packed graph operators (device pointers into one allocation).
@@ -90,10 +100,19 @@ struct GraphOps {
   double* b = nullptr;      // B = diag(b)
   double* dinv = nullptr;   // 1 / A_ii (Jacobi)
   double* invt = nullptr;   // 1 / T_i (0 if T_i = 0)
+  double* qinv = nullptr;   // 1 / Q_ii (0 if Q_ii = 0)
+  float* qinv32 = nullptr;
+  double cheb_b_a = 2.0;    // Gershgorin bound of the spectrum of diag(A)^-1 A
+  double cheb_b_q = 2.0;    // and of diag(Q)^-1 Q
   float* b32 = nullptr;
   float* dinv32 = nullptr;
   float* invt32 = nullptr;
-  // merged difference-form operator: row i = [W cols | T cols]
+  // Solver order (locality permutation): solver row i' is user row perm[i'].
+  int32_t* perm = nullptr;     // solver index -> user index
+  int32_t* iperm = nullptr;    // user index -> solver index
+  double *invt_s = nullptr, *qinv_s = nullptr, *b_s = nullptr, *dinv_s = nullptr;
+  float *invt32_s = nullptr, *qinv32_s = nullptr, *b32_s = nullptr, *dinv32_s = nullptr;
+  // merged difference-form operator in solver order: row i = [W cols | T cols]
   int32_t* a_rp = nullptr;     // int32[n+1]
   int32_t* a_split = nullptr;  // int32[n]: first T position of row i
   int32_t* a_col = nullptr;    // int32[nnz_w + nnz_t]
@@ -129,7 +148,13 @@ enum OpKind { OP_A = 0, OP_Q = 1 };
 template <typename T>
 void launch_spmm(const GraphOps& g, int kb, OpKind op, const T* x, T* y, const int* done,
                  hipStream_t s);
-// precond: 0 none, 1 multiply by dinv[i], 2 divide by dinv[i]
+// precond: 0 W = R, 1 W = dinv R (Jacobi); dinv (D^-1) is always read
+template <typename T>
+void launch_cheb_first(const GraphOps& g, int kb, const T* r, const T* dinv, const Ctrl* ctrl,
+                       T* y, T* dd, hipStream_t s);
+template <typename T>
+void launch_cheb_step(const GraphOps& g, int kb, OpKind op, int k, const T* r, const T* dinv,
+                      const Ctrl* ctrl, const T* yin, T* yout, T* dd, hipStream_t s);
 template <typename T>
 void launch_resid(int64_t n, int kb, const T* x, const T* ax, const T* bdiag, const T* dinv,
                   int precond, const double* lam, T* w, double* partials, int nparts,
@@ -146,26 +171,33 @@ void launch_reduce_partials(int nparts, int nent, const double* partials, double
 template <typename T>
 void launch_combine(int64_t n, int kb, int nin, const T* const* in, int nout, T* const* out,
                     const double* coef, const int* done, hipStream_t s);
+// Two groups sharing coefficients: group g maps in_g to out_g.
+template <typename T>
+void launch_combine2(int64_t n, int kb, int nin, int ngroup, const T* const* in0,
+                     const T* const* in1, int nout, T* const* out0, T* const* out1,
+                     const double* coef, const int* done, hipStream_t s);
 template <typename T>
 void launch_deflate_ones(int64_t n, int kb, T* x, double* partials, int nparts, double* sums,
                          const int* done, hipStream_t s);
-void launch_fill_random(int64_t n, int kb, int kcopy, const double* x0, uint64_t seed, double* x,
-                        hipStream_t s);
-// scratch: 64 * kb * 16 bytes
+// start block in solver order (perm: solver -> user row, may be null)
+void launch_fill_random(int64_t n, int kb, int kcopy, const double* x0, uint64_t seed,
+                        const int32_t* perm, double* x, hipStream_t s);
+// scratch: 64 * kb * 16 bytes; x in solver order, out in user order
 void launch_sign_fix_and_copy(int64_t n, int kb, int k, const double* x, double* out,
                               const double* lam, double* lam_out, double* scratch,
-                              hipStream_t s);
+                              const int32_t* perm, const int32_t* iperm, hipStream_t s);
 template <typename Tin, typename Tout>
 void launch_convert(int64_t count, const Tin* in, Tout* out, hipStream_t s);
 void launch_scale_rows(int64_t n, int k, const double* b, const double* x, double* y,
                        hipStream_t s);
 // dense n x n operator (which 0: A, 1: Q) and matching B (diag(b) or I)
 void launch_dense_ops(const GraphOps& g, int which, double* out, double* bmat, hipStream_t s);
-void launch_copy_cols(int64_t n, int ksrc, int kdst, int kcopy, const double* src, double* dst,
-                      hipStream_t s);
+// dst[i][j] = src[map ? map[i] : i][j]
+void launch_copy_cols(int64_t n, int ksrc, int kdst, int kcopy, const int32_t* map,
+                      const double* src, double* dst, hipStream_t s);
 
 // ---- timing.hip -------------------------------------------------------------
-enum KTimeKind { KT_OFF = 0, KT_SPMM_A = 1, KT_GRAM_RR = 2, KT_COMBINE = 3 };
+enum KTimeKind { KT_OFF = 0, KT_SPMM_A = 1, KT_GRAM_RR = 2, KT_COMBINE = 3, KT_CHEB = 4 };
 // Records HIP events around one launch when `kind` is the kind being timed.
 struct KScope {
   KScope(int kind, hipStream_t s, double bytes, int tag);

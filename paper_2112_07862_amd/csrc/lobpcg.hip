@@ -31,6 +31,12 @@ int block_width(int K) {
   return 16;
 }
 
+// Drop threshold on the pivots of the unit-diagonal basis Gram (squared sine
+// of the angle between a column and the span of the earlier ones).  Small
+// thresholds let the inverse Cholesky factor grow without bound on nearly
+// dependent bases; 1e-4 keeps it bounded and costs no iterations.
+constexpr double kRrPivot = 1e-4;
+
 static int partial_blocks(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(kPartialBlocks, ceil_div(n, 64)));
 }
@@ -41,6 +47,9 @@ struct SolveBufs {
   int64_t n = 0;
   int kb = 0;
   T *X = nullptr, *AX = nullptr, *W = nullptr, *AW = nullptr, *P = nullptr, *AP = nullptr;
+  T *R = nullptr, *Y = nullptr, *DD = nullptr;  // Chebyshev preconditioner
+  // FP32 copies for the mixed-precision preconditioner
+  float *R32 = nullptr, *W32 = nullptr, *Y32 = nullptr, *DD32 = nullptr;
   double* partials = nullptr;  // kPartialBlocks x (2 (3kb)^2)
   double* gram = nullptr;      // 2 (3kb)^2
   double* coef = nullptr;      // 2 (3kb) kb
@@ -52,7 +61,8 @@ struct SolveBufs {
 
   static size_t bytes(int64_t n, int kb) {
     const int m = 3 * kb;
-    size_t b = 6 * Arena::round((size_t)n * kb * sizeof(T));
+    size_t b = 9 * Arena::round((size_t)n * kb * sizeof(T));
+    b += 4 * Arena::round((size_t)n * kb * sizeof(float));
     b += Arena::round((size_t)kPartialBlocks * 2 * m * m * 8);
     b += Arena::round(2 * m * m * 8) + Arena::round(2 * m * kb * 8) + Arena::round(2 * kb * kb * 8);
     b += 2 * Arena::round(kb * 8) + Arena::round(64 * kb * 16) + Arena::round(sizeof(Ctrl));
@@ -69,6 +79,13 @@ struct SolveBufs {
     AW = a.take<T>(n * kb);
     P = a.take<T>(n * kb);
     AP = a.take<T>(n * kb);
+    R = a.take<T>(n * kb);
+    Y = a.take<T>(n * kb);
+    DD = a.take<T>(n * kb);
+    R32 = a.take<float>(n * kb);
+    W32 = a.take<float>(n * kb);
+    Y32 = a.take<float>(n * kb);
+    DD32 = a.take<float>(n * kb);
     partials = a.take<double>((size_t)kPartialBlocks * 2 * m * m);
     gram = a.take<double>(2 * m * m);
     coef = a.take<double>(2 * m * kb);
@@ -84,8 +101,13 @@ struct SolveBufs {
 struct Problem {
   OpKind op;
   const double* bdiag;  // nullptr: B = I
-  const double* dinv;   // preconditioner array (see precond)
-  int precond;          // 0 none, 1 multiply, 2 divide
+  const double* dinv;   // D^-1, D = diag(Op)
+  int precond;          // ME_PRECOND_NONE / _JACOBI / _CHEBYSHEV
+  int cheb_deg;
+  bool cheb_fp32;       // run the Chebyshev preconditioner in FP32
+  const float* dinv32;  // D^-1 in FP32
+  double cheb_afac;     // lower end of the Chebyshev interval: afac x Rayleigh quotient
+  double cheb_b;        // upper end: Gershgorin bound of D^-1 Op
   bool deflate_ones;    // keep the iterates orthogonal to the constant vector
   int need;             // leading columns that must converge
   double tol;
@@ -160,8 +182,31 @@ struct Lobpcg {
     T* outa[1] = {B.AX};
     const T* inx[1] = {B.X};
     const T* ina[1] = {B.AX};
-    launch_combine<T>(B.n, kb, 1, inx, 1, outx, cx, dn, s);
-    launch_combine<T>(B.n, kb, 1, ina, 1, outa, cx, dn, s);
+    launch_combine2<T>(B.n, kb, 1, 2, inx, ina, 1, outx, outa, cx, dn, s);
+  }
+
+  template <typename U>
+  double cheb_bytes() const {
+    const double sz = sizeof(U);
+    return 4.0 * (double)(g.nnz_w + g.nnz_t) + sz * (double)g.nnz_w + (double)g.n * (8.0 + sz) +
+           6.0 * (double)g.n * B.kb * sz;
+  }
+
+  // W = p(D^-1 Op) R by cheb_deg Chebyshev steps (type U); ping-pongs
+  // between w and y so that the last step writes w.
+  template <typename U>
+  void cheb_block(const U* r, const U* dinv, U* w, U* y, U* dd) {
+    const int deg = pr.cheb_deg;
+    U* cur = ((deg - 1) % 2 == 0) ? w : y;
+    U* nxt = (cur == w) ? y : w;
+    launch_cheb_first<U>(g, B.kb, r, dinv, B.ctrl, cur, dd, s);
+    for (int k = 1; k < deg; ++k) {
+      KScope ks(kt(KT_CHEB), s, cheb_bytes<U>(), tag);
+      launch_cheb_step<U>(g, B.kb, pr.op, k, r, dinv, B.ctrl, cur, nxt, dd, s);
+      U* t = cur;
+      cur = nxt;
+      nxt = t;
+    }
   }
 
   void iteration(bool first) {
@@ -169,9 +214,19 @@ struct Lobpcg {
     const int* dn = done();
     ++tag;
     // residual, preconditioned W, convergence test
-    launch_resid<T>(B.n, kb, B.X, B.AX, (const T*)pr.bdiag, (const T*)pr.dinv, pr.precond, B.lam,
-                    B.W, B.partials, nparts_res, dn, s);
+    const bool cheb = pr.precond == ME_PRECOND_CHEBYSHEV;
+    launch_resid<T>(B.n, kb, B.X, B.AX, (const T*)pr.bdiag, (const T*)pr.dinv,
+                    pr.precond == ME_PRECOND_JACOBI ? 1 : 0, B.lam, cheb ? B.R : B.W, B.partials,
+                    nparts_res, dn, s);
     launch_resid_finalize(kb, B.partials, nparts_res, B.lam, B.ctrl, 0, s);
+    if (cheb && pr.cheb_fp32) {
+      // mixed precision: the preconditioner only shapes the search direction
+      launch_convert<T, float>(B.n * kb, B.R, B.R32, s);
+      cheb_block<float>(B.R32, pr.dinv32, B.W32, B.Y32, B.DD32);
+      launch_convert<float, T>(B.n * kb, B.W32, B.W, s);
+    } else if (cheb) {
+      cheb_block<T>(B.R, (const T*)pr.dinv, B.W, B.Y, B.DD);
+    }
     if (pr.deflate_ones)
       launch_deflate_ones<T>(B.n, kb, B.W, B.partials, nparts_res, B.sums, dn, s);
     // W <- (W - X C) R^-1
@@ -198,16 +253,12 @@ struct Lobpcg {
                      dn, s);
     }
     launch_reduce_partials(nparts_gram, 2 * m * m, B.partials, B.gram, dn, s);
-    launch_rayleigh_ritz(kb, nb, B.gram + m * m, B.gram, 1e-10, B.coef, B.lam, B.ctrl, 0, s);
+    launch_rayleigh_ritz(kb, nb, B.gram + m * m, B.gram, kRrPivot, B.coef, B.lam, B.ctrl, 0, s);
     T* out_x[2] = {B.P, B.X};
     T* out_a[2] = {B.AP, B.AX};
     {
-      KScope ks(kt(KT_COMBINE), s, (nb + 2) * blk, tag);
-      launch_combine<T>(B.n, kb, nb, S, 2, out_x, B.coef, dn, s);
-    }
-    {
-      KScope ks(kt(KT_COMBINE), s, (nb + 2) * blk, tag);
-      launch_combine<T>(B.n, kb, nb, AS, 2, out_a, B.coef, dn, s);
+      KScope ks(kt(KT_COMBINE), s, 2.0 * (nb + 2) * blk, tag);
+      launch_combine2<T>(B.n, kb, nb, 2, S, AS, 2, out_x, out_a, B.coef, dn, s);
     }
   }
 
@@ -221,6 +272,9 @@ struct Lobpcg {
     c0.tol = pr.tol;
     c0.lam_floor = pr.lam_floor;
     c0.lam_scale = pr.lam_scale;
+    c0.cheb_deg = pr.precond == ME_PRECOND_CHEBYSHEV ? pr.cheb_deg : 0;
+    c0.cheb_afac = pr.cheb_afac;
+    c0.cheb_b = pr.cheb_b;
     *hc = c0;
     ME_TRY(hipMemcpyAsync(B.ctrl, hc, sizeof(Ctrl), hipMemcpyHostToDevice, s));
     if (pr.deflate_ones) launch_deflate_ones<T>(B.n, kb, B.X, B.partials, nparts_res, B.sums,
@@ -247,8 +301,8 @@ struct Lobpcg {
       phase = ktimer_new_phase();
       tag = 0;
       rr_x(1);
-      launch_resid<T>(B.n, kb, B.X, B.AX, (const T*)pr.bdiag, (const T*)pr.dinv, pr.precond,
-                      B.lam, nullptr, B.partials, nparts_res, nullptr, s);
+      launch_resid<T>(B.n, kb, B.X, B.AX, (const T*)pr.bdiag, (const T*)pr.dinv, 0, B.lam,
+                      nullptr, B.partials, nparts_res, nullptr, s);
       launch_resid_finalize(kb, B.partials, nparts_res, B.lam, B.ctrl, 1, s);
       ME_TRY_STATUS(read_ctrl(B.ctrl, hc, s));
       if (hc->nonfinite) return ME_ERR_BREAKDOWN;
@@ -308,8 +362,13 @@ int solve_eps(GraphOps& g, const me_opts* o, hipStream_t s, double* eps, int* it
   Problem pr;
   pr.op = OP_Q;
   pr.bdiag = nullptr;
-  pr.dinv = g.qdiag;
-  pr.precond = o->precond == ME_PRECOND_JACOBI ? 2 : 0;
+  pr.dinv = g.qinv_s;
+  pr.dinv32 = g.qinv32_s;
+  pr.cheb_fp32 = o->precision == ME_MIXED;
+  pr.precond = o->precond;
+  pr.cheb_deg = o->cheb_degree;
+  pr.cheb_afac = 0.5;
+  pr.cheb_b = g.cheb_b_q * 1.01;
   pr.deflate_ones = true;
   pr.need = 1;
   pr.tol = o->eps_tol;
@@ -317,7 +376,7 @@ int solve_eps(GraphOps& g, const me_opts* o, hipStream_t s, double* eps, int* it
   pr.check_every = o->check_every > 0 ? o->check_every : 16;
   pr.lam_scale = g.maxden > 0 ? g.maxden : 1.0;
   pr.lam_floor = 1e-8 * pr.lam_scale;
-  launch_fill_random(n, kb, 0, nullptr, o->seed ^ 0x51ED2701D5ull, B.X, s);
+  launch_fill_random(n, kb, 0, nullptr, o->seed ^ 0x51ED2701D5ull, g.perm, B.X, s);
   HostCtrl hc;
   if (hc.alloc()) { (void)hipFreeAsync(ws, s); return ME_ERR_HIP; }
   Lobpcg<double> L(g, pr, B, s);
@@ -367,7 +426,7 @@ int embed(const GraphOps& g, int K, double tol, const me_opts* o, const double* 
     launch_dense_ops(g, 0, buf, buf + nn, s);
     launch_dense_geneig((int)n, buf, buf + nn, buf + 2 * nn, buf + 3 * nn, s);
     launch_sign_fix_and_copy(n, (int)n, K, buf + 2 * nn, X, buf + 3 * nn, lambda,
-                             buf + 3 * nn + n, s);
+                             buf + 3 * nn + n, nullptr, nullptr, s);
     ME_TRY(hipStreamSynchronize(s));
     kb = (int)n;
   } else {
@@ -378,12 +437,17 @@ int embed(const GraphOps& g, int K, double tol, const me_opts* o, const double* 
     }
     SolveBufs<double> B;
     B.carve(ws, need_bytes, n, kb);
-    launch_fill_random(n, kb, x0 ? K : 0, x0, o->seed, B.X, s);
+    launch_fill_random(n, kb, x0 ? K : 0, x0, o->seed, g.perm, B.X, s);
     Problem pr;
     pr.op = OP_A;
-    pr.bdiag = g.b;
-    pr.dinv = g.dinv;
-    pr.precond = o->precond == ME_PRECOND_JACOBI ? 1 : 0;
+    pr.bdiag = g.b_s;
+    pr.dinv = g.dinv_s;
+    pr.dinv32 = g.dinv32_s;
+    pr.cheb_fp32 = o->precision == ME_MIXED;
+    pr.precond = o->precond;
+    pr.cheb_deg = o->cheb_degree;
+    pr.cheb_afac = 0.5;
+    pr.cheb_b = g.cheb_b_a * 1.01;
     pr.deflate_ones = false;
     pr.need = K;
     pr.tol = tol;
@@ -401,7 +465,7 @@ int embed(const GraphOps& g, int K, double tol, const me_opts* o, const double* 
     iters = hc.h->iter;
     for (int j = 0; j < K; ++j) worst = std::max(worst, hc.h->rho[j]);
     if (st >= 0) {
-      launch_sign_fix_and_copy(n, kb, K, B.X, X, B.lam, lambda, B.scratch, s);
+      launch_sign_fix_and_copy(n, kb, K, B.X, X, B.lam, lambda, B.scratch, g.perm, g.iperm, s);
       ME_TRY(hipStreamSynchronize(s));
     }
     ktimer_collect();

@@ -108,7 +108,7 @@ extern "C" int me_kernel_timing(int kind) {
   using namespace me;
   KTimer& t = kt();
   std::lock_guard<std::mutex> l(t.mu);
-  if (kind < 0 || kind > 3) return ME_ERR_INVALID_ARG;
+  if (kind < 0 || kind > 4) return ME_ERR_INVALID_ARG;
   t.kind = kind;
   t.launches = 0;
   t.ms = 0.0;

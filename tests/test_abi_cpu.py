@@ -37,7 +37,7 @@ def test_host_only_entry_points():
     lib = _lib.load()
     o = _lib.MeOpts()
     lib.me_opts_default(ctypes.byref(o))
-    assert o.precond == _lib.ME_PRECOND_JACOBI and o.max_iter > 0 and o.check_every > 0
+    assert o.precond == _lib.ME_PRECOND_CHEBYSHEV and o.max_iter > 0 and o.check_every > 0
     assert 0 < o.eps_tol < 1e-6
     for st in list(_lib.STATUS_NAMES):
         assert lib.me_status_string(st).decode()

@@ -210,3 +210,80 @@ def test_k_range_errors(me):
     g = sg.ring(49, 2)
     X, lam, info = me.embed(g, 16, tol=1e-8)
     assert info["status"] == 0 and info["block"] == 16
+
+
+@pytest.mark.parametrize("name,K", [("square_2k", 4), ("sphere_3k", 16), ("torus_2500", 8)])
+@pytest.mark.parametrize("precond,deg", [("none", None), ("jacobi", None), ("chebyshev", 8),
+                                         ("chebyshev", 48)])
+def test_embed_preconditioners(me, name, K, precond, deg):
+    """Every preconditioner reaches the same pairs (the converged result
+    does not depend on the preconditioner)."""
+    g, ops = oracle_ops(name)
+    lam_o, V_o = oracle.generalized_eigs(ops["A"], ops["b"], K)
+    relgap = (lam_o[K] - lam_o[K - 1]) / lam_o[K - 1]
+    tol = min(1e-6, 1e-5 * relgap / 4)
+    X, lam, info = me.embed(g, K, tol=tol, seed=3, precond=precond, cheb_degree=deg)
+    assert info["status"] == 0, info
+    lam = _np(lam)
+    np.testing.assert_array_less(np.abs(lam - lam_o[:K]) / np.abs(lam_o[:K]), 1e-6)
+    assert oracle.sin_principal_angle_b(_np(X), V_o[:, :K], ops["b"]) <= 1e-5
+
+
+@pytest.mark.parametrize("name,K", EMBED_CASES)
+def test_embed_mixed_precision_matches_oracle(me, name, K):
+    """FP32 preconditioner, FP64 everything else: same bar as FP64."""
+    g, ops = oracle_ops(name)
+    lam_o, V_o = oracle.generalized_eigs(ops["A"], ops["b"], K)
+    relgap = (lam_o[K] - lam_o[K - 1]) / lam_o[K - 1]
+    tol = min(1e-6, 1e-5 * relgap / 4)
+    X, lam, info = me.embed(g, K, tol=tol, seed=1, precision="mixed")
+    assert info["status"] == 0, info
+    X, lam = _np(X), _np(lam)
+    np.testing.assert_array_less(np.abs(lam - lam_o[:K]) / np.abs(lam_o[:K]), 1e-6)
+    assert oracle.sin_principal_angle_b(X, V_o[:, :K], ops["b"]) <= 1e-5
+    assert oracle.b_orthonormality_error(X, ops["b"]) <= 1e-10
+    assert np.all(oracle.relative_residuals(ops["A"], ops["b"], X, lam) <= tol * 1.01 + 1e-12)
+
+
+def bfs_order_reference(g):
+    """Breadth-first levels from a pseudo-peripheral node, ties by node id,
+    components in order of their lowest unvisited node (pure Python)."""
+    n = g.n
+    nbr = [g.col[g.rowptr[i]:g.rowptr[i + 1]] for i in range(n)]
+
+    def bfs(start, lev0, level):
+        level[start] = lev0
+        front, lev = [start], lev0
+        while front:
+            nxt = []
+            for u in front:
+                for v in nbr[u]:
+                    if level[v] < 0:
+                        level[v] = lev + 1
+                        nxt.append(v)
+            if nxt:
+                lev += 1
+            front = nxt
+        return lev
+
+    if n <= 48:
+        return np.arange(n)
+    level = -np.ones(n, dtype=np.int64)
+    last = bfs(0, 0, level)
+    start = int(np.min(np.nonzero(level == last)[0]))
+    level[:] = -1
+    last = bfs(start, 0, level)
+    while np.any(level < 0):
+        last = bfs(int(np.min(np.nonzero(level < 0)[0])), last + 1, level)
+    return np.argsort(level, kind="stable")
+
+
+@pytest.mark.parametrize("name", ["square_2k", "sphere_3k", "two_squares", "grid_bipartite",
+                                  "star_1500", "tri_mesh", "random_300"])
+def test_solver_order_bit_exact(me, name):
+    g, _ = oracle_ops(name)
+    h = me.build_graph_ops(g)
+    perm = _np(h.order())
+    assert np.array_equal(np.sort(perm), np.arange(g.n))
+    assert np.array_equal(perm, bfs_order_reference(g))
+    h.close()
