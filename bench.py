@@ -68,8 +68,12 @@ def main() -> int:
     ap.add_argument("--workload", default="swiss_roll_100k")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--time-kernel", default="cheb", choices=list(KERNELS))
-    ap.add_argument("--cpu-sample-n", type=int, default=50_000)
+    ap.add_argument("--cheb-degree", type=int, default=32)
+    ap.add_argument("--cpu-sample-n", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device-to-device copies of MIB MiB (the known-size "
+                         "reference for the HBM byte counters) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -80,6 +84,16 @@ def main() -> int:
         return 2
 
     import torch
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}), flush=True)
+        return 0
     import paper_2112_07862_amd as me
     import synthgraphs as sg
 
@@ -90,7 +104,7 @@ def main() -> int:
     dcsr = me.to_device(g)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    opts = dict(precision=args.precision, seed=0)
+    opts = dict(precision=args.precision, seed=0, cheb_degree=args.cheb_degree)
 
     def step():
         X, lam, info = me.embed(dcsr, K, tol=tol, **opts)
@@ -137,13 +151,16 @@ def main() -> int:
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "manifold": kind, "n": n, "knn": knn, "K": K,
-                   "tol": tol, "precision": args.precision, "seed": 0},
+                   "tol": tol, "precision": args.precision, "preconditioner": "chebyshev",
+                   "cheb_degree": args.cheb_degree, "seed": 0},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                        "p99": float(np.percentile(lat, 99) * 1e3)},
         "iterations": int(np.median([i["iterations"] for i in infos])),
         "eps_iterations": int(np.median([i["eps_iterations"] for i in infos])),
         "max_residual": max(i["max_residual"] for i in infos),
         "all_converged": ok,
+        "phases_ms": {"build_incl_eps": float(np.median([i["ms_build"] for i in infos])),
+                      "solve": float(np.median([i["ms_solve"] for i in infos]))},
         "roofline": {
             "kernel": KERNEL_NAMES[args.time_kernel],
             "bound": "hbm",

@@ -81,7 +81,7 @@ typedef struct {
   double eps_tol;     /* relative residual target of the eps solve (default 1e-8)   */
   int check_every;    /* iterations enqueued between host convergence reads (default 16) */
   uint64_t seed;      /* seed of the library's starting blocks (default 0)          */
-  int cheb_degree;    /* Chebyshev preconditioner degree, 2..64 (default 32)        */
+  int cheb_degree;    /* Chebyshev preconditioner degree, 2..256 (default 64)       */
 } me_opts;
 
 /* Per-solve report.  Times are host wall-clock milliseconds of the phases. */
@@ -177,6 +177,29 @@ size_t me_embed_workspace_bytes(const me_graph_ops* ops, int K, const me_opts* o
 int me_embed(const me_graph_ops* ops, int K, double tol, const me_opts* opts,
              const double* X0, void* ws, size_t ws_bytes, double* X, double* lambda,
              me_info* info, void* stream);
+
+/* Embeds G independent graphs in one solve (the method of Section 4 applied
+ * to each graph; a batch is a way to run many of them at once, not a change
+ * of the problem).  Every graph is built as me_build_graph_ops does; then
+ * all eps = lambda_2(Q) solves run together, then all embedding solves run
+ * together: each LOBPCG stage is one launch over every unconverged graph,
+ * and the small dense steps run one workgroup per graph.  A graph's result
+ * does not depend on the other graphs of the batch (its arithmetic is
+ * identical to a batch of one).
+ *   Ws       host array of G input graphs (device CSR, as for me_build_graph_ops).
+ *   Ks       host int[G], 1..16 each (with the block rule of me_embed).
+ *   tol      > 0, the rho target of every graph.
+ *   opts     host, may be NULL.
+ *   Xs       host array of G device pointers, graph g's n_g x K_g output.
+ *   lambdas  host array of G device pointers, K_g values each.
+ *   infos    host me_info[G], may be NULL; per-graph status and report
+ *            (ms_build: time until that graph's operators were ready,
+ *            ms_solve: the embedding phase of the whole batch).
+ * Returns the first negative per-graph status if any graph failed (the other
+ * graphs' outputs are still valid, see infos), else the largest warning, else
+ * ME_OK.  Synchronises `stream`. */
+int me_embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opts* opts,
+                   double* const* Xs, double* const* lambdas, me_info* infos, void* stream);
 
 /* Kernel timing (diagnostic).  me_kernel_timing(kind) starts timing every
  * launch of one kernel kind with HIP events recorded on the launching stream

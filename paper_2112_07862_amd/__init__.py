@@ -4,6 +4,6 @@ first K generalized eigenvectors of (A = L - mu Q + eps I, B) by LOBPCG, all
 in hand-written HIP kernels behind the C ABI of include/membed.h."""
 from ._lib import LIB_PATH, load  # noqa: F401
 from .api import (  # noqa: F401
-    DeviceCSR, GraphOps, MembedError, build_graph_ops, embed, kernel_timing, kernel_timing_read, make_opts,
-    to_device,
+    DeviceCSR, GraphOps, MembedError, build_graph_ops, embed, embed_batch, kernel_timing,
+    kernel_timing_read, make_opts, to_device,
 )

@@ -63,6 +63,9 @@ SIGNATURES = {
     "me_embed_workspace_bytes": (c_size_t, [c_void_p, c_int, ctypes.POINTER(MeOpts)]),
     "me_embed": (c_int, [c_void_p, c_int, c_double, ctypes.POINTER(MeOpts), c_void_p, c_void_p,
                          c_size_t, c_void_p, c_void_p, ctypes.POINTER(MeInfo), c_void_p]),
+    "me_embed_batch": (c_int, [c_int, ctypes.POINTER(MeCsr), ctypes.POINTER(c_int), c_double,
+                               ctypes.POINTER(MeOpts), ctypes.POINTER(c_void_p),
+                               ctypes.POINTER(c_void_p), ctypes.POINTER(MeInfo), c_void_p]),
     "me_graph_ops_destroy": (None, [c_void_p]),
     "me_kernel_timing": (c_int, [c_int]),
     "me_kernel_timing_read": (c_int, [ctypes.POINTER(c_int64), ctypes.POINTER(c_double),

@@ -210,9 +210,46 @@ def embed(graph, K: int, tol: float = 1e-6, X0: torch.Tensor | None = None,
             ops.close()
 
 
+def embed_batch(graphs, Ks, tol: float = 1e-6, stream=None, **opts):
+    """Embeds many graphs in one batched solve.  `graphs`: CSRs (host or
+    DeviceCSR); `Ks`: one K per graph (or a single int).  Returns a list of
+    (X, lambda, info) per graph; graphs that failed carry info["status"] < 0
+    and X, lambda None.  Raises only if the call as a whole is invalid."""
+    lib = L.load()
+    G = len(graphs)
+    if isinstance(Ks, int):
+        Ks = [Ks] * G
+    if len(Ks) != G:
+        raise ValueError("one K per graph")
+    dcsrs = [to_device(g) for g in graphs]
+    o = make_opts(**opts)
+    Xs = [torch.empty((d.n, int(k)), dtype=torch.float64, device=d.rowptr.device)
+          for d, k in zip(dcsrs, Ks)]
+    lams = [torch.empty(max(int(k), 1), dtype=torch.float64, device=d.rowptr.device)
+            for d, k in zip(dcsrs, Ks)]
+    Ws = (L.MeCsr * max(G, 1))(*[d.as_struct() for d in dcsrs])
+    Kc = (ctypes.c_int * max(G, 1))(*[int(k) for k in Ks])
+    Xp = (ctypes.c_void_p * max(G, 1))(*[x.data_ptr() for x in Xs])
+    Lp = (ctypes.c_void_p * max(G, 1))(*[l.data_ptr() for l in lams])
+    infos = (L.MeInfo * max(G, 1))()
+    st = lib.me_embed_batch(G, Ws, Kc, float(tol), ctypes.byref(o), Xp, Lp, infos,
+                            _stream_ptr(stream))
+    if st == -1 and all(infos[i].status == 0 for i in range(G)):
+        _check(st, "embed_batch")
+    out = []
+    for i in range(G):
+        d = infos[i].as_dict()
+        d["status_name"] = L.STATUS_NAMES.get(d["status"], str(d["status"]))
+        if d["status"] < 0:
+            out.append((None, None, d))
+        else:
+            out.append((Xs[i], lams[i][:int(Ks[i])], d))
+    return out
+
+
 def kernel_timing(kind: int) -> None:
     """Start timing one kernel kind (0 off, 1 SpMM of A, 2 Rayleigh-Ritz Gram,
-    3 block combine); clears the totals."""
+    3 block combine, 4 Chebyshev preconditioner step); clears the totals."""
     _check(L.load().me_kernel_timing(int(kind)), "kernel_timing")
 
 

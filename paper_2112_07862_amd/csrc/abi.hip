@@ -7,6 +7,17 @@
 
 using namespace me;
 
+namespace me {
+void free_graph_ops(GraphOps& g) {
+  if (g.mem) (void)hipFree(g.mem);
+  if (g.mem2) (void)hipFree(g.mem2);
+  g.mem = g.mem2 = nullptr;
+}
+}  // namespace me
+
+static void free_ops(GraphOps& g) { free_graph_ops(g); }
+
+
 extern "C" {
 
 void me_opts_default(me_opts* o) {
@@ -18,7 +29,7 @@ void me_opts_default(me_opts* o) {
   o->eps_tol = 1e-8;
   o->check_every = 16;
   o->seed = 0;
-  o->cheb_degree = 32;
+  o->cheb_degree = 64;
 }
 
 const char* me_status_string(int st) {
@@ -40,10 +51,13 @@ const char* me_status_string(int st) {
   }
 }
 
-static void free_ops(GraphOps& g) {
-  if (g.mem) (void)hipFree(g.mem);
-  if (g.mem2) (void)hipFree(g.mem2);
-  g.mem = g.mem2 = nullptr;
+
+static bool opts_valid(const me_opts& o) {
+  return o.max_iter >= 1 && o.eps_max_iter >= 1 && o.check_every >= 1 && o.precond >= 0 &&
+         o.precond <= 2 && (o.precision == ME_FP64 || o.precision == ME_MIXED) &&
+         o.eps_tol > 0 &&
+         (o.precond != ME_PRECOND_CHEBYSHEV ||
+          (o.cheb_degree >= 2 && o.cheb_degree <= kMaxChebDegree));
 }
 
 int me_build_graph_ops(const me_csr* W, const me_opts* opts, void* stream, me_graph_ops** out,
@@ -52,6 +66,7 @@ int me_build_graph_ops(const me_csr* W, const me_opts* opts, void* stream, me_gr
   *out = nullptr;
   me_opts o;
   if (opts) o = *opts; else me_opts_default(&o);
+  if (!opts_valid(o)) return ME_ERR_INVALID_ARG;
   const auto t0 = std::chrono::steady_clock::now();
   auto* h = new (std::nothrow) me_graph_ops();
   if (!h) return ME_ERR_HIP;
@@ -156,10 +171,20 @@ int me_embed(const me_graph_ops* ops, int K, double tol, const me_opts* opts, co
   if (!ops) return ME_ERR_INVALID_ARG;
   me_opts o;
   if (opts) o = *opts; else me_opts_default(&o);
-  if (o.max_iter < 1 || o.check_every < 1 || o.precond < 0 || o.precond > 2 ||
-      (o.precond == ME_PRECOND_CHEBYSHEV && (o.cheb_degree < 2 || o.cheb_degree > 64)))
-    return ME_ERR_INVALID_ARG;
+  if (!opts_valid(o)) return ME_ERR_INVALID_ARG;
   return embed(ops->g, K, tol, &o, X0, ws, ws_bytes, X, lambda, info, (hipStream_t)stream);
+}
+
+int me_embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opts* opts,
+                   double* const* Xs, double* const* lambdas, me_info* infos, void* stream) {
+  if (G < 0 || (G > 0 && (!Ws || !Ks || !Xs || !lambdas)) || !(tol > 0.0))
+    return ME_ERR_INVALID_ARG;
+  if (G == 0) return ME_OK;
+  me_opts o;
+  if (opts) o = *opts; else me_opts_default(&o);
+  if (!opts_valid(o)) return ME_ERR_INVALID_ARG;
+  if (infos) std::memset(infos, 0, sizeof(me_info) * (size_t)G);
+  return embed_batch(G, Ws, Ks, tol, &o, Xs, lambdas, infos, (hipStream_t)stream);
 }
 
 void me_graph_ops_destroy(me_graph_ops* ops) {

@@ -729,8 +729,10 @@ static int read_scalar(const T* dev, T* host, hipStream_t s) {
   return ME_OK;
 }
 
-int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g,
-                    me_info* info) {
+// Everything up to eps: validation, degrees, T, Q, the locality order and
+// the packed operator.  g->needs_eps tells whether eps = lambda_2(Q) must be
+// computed (connected two-hop graph); otherwise eps = 0 (ME_WARN_EPS_ZERO).
+int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   const int64_t n = W->n, nnz = W->nnz;
   if (n < 1 || nnz < 0 || !W->rowptr || (nnz > 0 && (!W->col || !W->val)))
     return ME_ERR_INVALID_ARG;
@@ -785,6 +787,8 @@ int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* 
   int64_t* aoff = ar.take<int64_t>(n + 1);
   int* dflags = ar.take<int>(64);
   if (!dflags) return ME_ERR_HIP;
+  g->scratch_d = scratch_d;
+  g->dflags = dflags;
 
   ME_TRY(hipMemcpyAsync(g->w_rp, W->rowptr, (n + 1) * 8, hipMemcpyDeviceToDevice, s));
   if (nnz > 0) {
@@ -887,20 +891,24 @@ int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* 
   std::memcpy(&maxden, &hmaxden, 8);
   g->maxden = maxden;
 
-  // ---- eps = lambda_2(Q)
-  double eps = 0.0;
-  int eps_iters = 0;
+  g->needs_eps = !(hroots > 1 || n < 2);
+  return ME_OK;
+}
+
+// eps, mu and everything that depends on them: r, b, the Jacobi diagonal.
+int build_post(GraphOps* g, double eps, int eps_iters, hipStream_t s) {
+  const int64_t n = g->n;
   int st = ME_OK;
-  if (hroots > 1 || n < 2) {
-    st = ME_WARN_EPS_ZERO;
-  } else {
-    ME_TRY_STATUS(solve_eps(*g, o, s, &eps, &eps_iters));
-    if (!(eps > 0.0)) st = ME_WARN_EPS_ZERO, eps = 0.0;
-  }
+  if (!g->needs_eps || !(eps > 0.0)) st = ME_WARN_EPS_ZERO, eps = 0.0;
+  const double maxden = g->maxden;
   g->eps = eps;
   g->eps_iters = eps_iters;
   // mu = min_i eps / den_i over den_i > 0 = eps / max_i den_i
   g->mu = (eps > 0.0 && maxden > 0.0) ? eps / maxden : 0.0;
+  double* scratch_d = g->scratch_d;
+  int* dflags = g->dflags;
+  unsigned long long* maxdiag_bits = reinterpret_cast<unsigned long long*>(dflags + 6);
+  unsigned long long* maxratio_bits = reinterpret_cast<unsigned long long*>(dflags + 8);
 
   // ---- r, b, Jacobi diagonal
   const int nparts = (int)std::min<int64_t>(ceil_div(n, kBlock), kPartialBlocks);
@@ -918,7 +926,17 @@ int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* 
   k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->dinv, g->dinv_s,
                                                        g->dinv32_s);
   g->status = st;
-  if (info) {
+  return st;
+}
+
+int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g,
+                    me_info* info) {
+  ME_TRY_STATUS(build_pre(W, o, s, g));
+  double eps = 0.0;
+  int eps_iters = 0;
+  if (g->needs_eps) ME_TRY_STATUS(solve_eps(*g, o, s, &eps, &eps_iters));
+  const int st = build_post(g, eps, eps_iters, s);
+  if (info && st >= 0) {
     info->eps = g->eps;
     info->mu = g->mu;
     info->eps_iterations = eps_iters;

@@ -29,9 +29,22 @@ constexpr int kMaxBlockCols = 16;    // largest LOBPCG block width
 constexpr int kMaxBasis = 48;        // 3 x kMaxBlockCols: Rayleigh-Ritz basis size
 constexpr int kDenseMaxN = 48;       // graphs up to this size are solved densely
 constexpr int kPartialBlocks = 256;  // grid of the reducing streaming kernels
-constexpr int kMaxChebDegree = 64;   // largest Chebyshev preconditioner degree
+constexpr int kMaxChebDegree = 256;  // largest Chebyshev preconditioner degree
+constexpr int kXcd = 8;              // accelerator complex dies (one L2 each)
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Workgroup i of a launch runs on XCD i mod kXcd.  Gathering kernels remap
+// their workgroups so that each XCD runs one contiguous range of logical
+// blocks: rows that are close in the locality order then meet in the same
+// L2.  Launch xcd_grid(nblocks) workgroups; logical blocks >= nblocks exit.
+__host__ __device__ inline int64_t xcd_grid(int64_t nblocks) {
+  return kXcd * ((nblocks + kXcd - 1) / kXcd);
+}
+__device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
+  const int64_t per = (nblocks + kXcd - 1) / kXcd;
+  return (int64_t)(blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
+}
 
 // Bump allocator over one device allocation.
 struct Arena {
@@ -49,9 +62,9 @@ struct Arena {
   static size_t round(size_t bytes) { return (bytes + 255) & ~size_t(255); }
 };
 
-// Device-side control block of one LOBPCG solve.  Written by the
-// single-block finalize kernels, read by every iteration kernel (early exit
-// once `done` is set) and copied to pinned host memory every few iterations.
+// Device-side control block of one LOBPCG solve.  Written by the per-slot
+// finalize kernels, read by every iteration kernel (early exit once `done`)
+// and copied to the host at each convergence check.
 struct Ctrl {
   int done;        // 1 = converged or out of iterations
   int iter;        // iterations completed
@@ -62,20 +75,18 @@ struct Ctrl {
   int nbasis_last; // basis size used by the last Rayleigh-Ritz
   int dropped;     // basis columns dropped by the last Rayleigh-Ritz
   int nonfinite;   // a NaN / Inf was seen
-  int pad;
+  int cheb_deg;    // Chebyshev preconditioner degree (0: none)
   double tol;
   double lam_floor;          // |lambda| below this is treated as zero ...
   double lam_scale;          // ... and replaced by this operator scale in rho
-  double rho[kMaxBlockCols]; // last residuals
-  // Chebyshev preconditioner: spectrum of D^-1 Op taken as [cheb_a, cheb_b];
-  // cheb_a follows the leading Ritz pair (cheb_afac times its D-Rayleigh
-  // quotient).  Step k uses dd <- alpha_k dd + beta_k D^-1 (R - Op y).
-  int cheb_deg;
-  int pad2;
+  // Chebyshev preconditioner: spectrum of D^-1 Op taken as [a, cheb_b];
+  // a follows the leading nonzero Ritz pair (cheb_afac times its
+  // D-Rayleigh quotient).
   double cheb_afac;
-  double cheb_a, cheb_b, cheb_theta;
-  double cheb_alpha[kMaxChebDegree];
-  double cheb_beta[kMaxChebDegree];
+  double cheb_b;
+  double orth;               // max |X^T B X - I| at exit
+  double rho[kMaxBlockCols]; // last residuals
+  double lam[kMaxBlockCols]; // Ritz values of the certificate pass
 };
 
 // Packed graph operators (device pointers into one allocation).
@@ -118,6 +129,9 @@ struct GraphOps {
   int32_t* a_col = nullptr;    // int32[nnz_w + nnz_t]
   double* a_w = nullptr;       // W weights at the W positions (T positions unused)
   float* a_w32 = nullptr;
+  double* scratch_d = nullptr;  // n doubles of build scratch
+  int* dflags = nullptr;        // 64 ints of build flags and reductions
+  bool needs_eps = false;       // two-hop graph connected: eps = lambda_2(Q) > 0
   void* mem = nullptr;   // per-node arrays, W copy
   void* mem2 = nullptr;  // T columns and the merged operator
   size_t mem_bytes = 0;
@@ -126,17 +140,10 @@ struct GraphOps {
 
 // ---- launchers: build.hip -------------------------------------------------
 int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g, me_info* info);
+int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g);
+int build_post(GraphOps* g, double eps, int eps_iters, hipStream_t s);
 
 // ---- launchers: dense.hip -------------------------------------------------
-// Rayleigh-Ritz on a basis of nb blocks of kb columns: ga, gb (m x m,
-// m = nb*kb, row-major, device) -> coef (m x kb) and lam (kb); column-drop
-// threshold `piv_tol` on the normalised Cholesky pivots.
-void launch_rayleigh_ritz(int kb, int nb, const double* ga, const double* gb, double piv_tol,
-                          double* coef, double* lam, Ctrl* ctrl, int final_pass, hipStream_t s);
-// Projected CholQR coefficients for W <- (W - X C) R^-1 from
-// g = [X W]^T B W ((2kb) x kb): writes coef ((2kb) x kb) = [-C R^-1; R^-1].
-void launch_cholqr_coef(int kb, const double* g, double piv_tol, double* coef, const Ctrl* ctrl,
-                        hipStream_t s);
 // Dense generalized eigenproblem for graphs with n <= 48: all n pairs of
 // (a_dense, b_dense), both n x n; vec n x n (column t = pair t), lam ascending.
 void launch_dense_geneig(int n, const double* a_dense, const double* b_dense, double* vec,
@@ -148,46 +155,10 @@ enum OpKind { OP_A = 0, OP_Q = 1 };
 template <typename T>
 void launch_spmm(const GraphOps& g, int kb, OpKind op, const T* x, T* y, const int* done,
                  hipStream_t s);
-// precond: 0 W = R, 1 W = dinv R (Jacobi); dinv (D^-1) is always read
-template <typename T>
-void launch_cheb_first(const GraphOps& g, int kb, const T* r, const T* dinv, const Ctrl* ctrl,
-                       T* y, T* dd, hipStream_t s);
-template <typename T>
-void launch_cheb_step(const GraphOps& g, int kb, OpKind op, int k, const T* r, const T* dinv,
-                      const Ctrl* ctrl, const T* yin, T* yout, T* dd, hipStream_t s);
-template <typename T>
-void launch_resid(int64_t n, int kb, const T* x, const T* ax, const T* bdiag, const T* dinv,
-                  int precond, const double* lam, T* w, double* partials, int nparts,
-                  const int* done, hipStream_t s);
-void launch_resid_finalize(int kb, const double* partials, int nparts, const double* lam,
-                           Ctrl* ctrl, int final_pass, hipStream_t s);
-// G1 = U^T diag(wdiag) V, G2 = U^T V2 (partials per block, G1 then G2)
-template <typename T>
-void launch_gram(int64_t n, int kb, int nu, const T* const* u, int nv, const T* const* v,
-                 const T* wdiag, int nv2, const T* const* v2, double* partials, int nparts,
-                 const int* done, hipStream_t s);
-void launch_reduce_partials(int nparts, int nent, const double* partials, double* out,
-                            const int* done, hipStream_t s);
-template <typename T>
-void launch_combine(int64_t n, int kb, int nin, const T* const* in, int nout, T* const* out,
-                    const double* coef, const int* done, hipStream_t s);
-// Two groups sharing coefficients: group g maps in_g to out_g.
-template <typename T>
-void launch_combine2(int64_t n, int kb, int nin, int ngroup, const T* const* in0,
-                     const T* const* in1, int nout, T* const* out0, T* const* out1,
-                     const double* coef, const int* done, hipStream_t s);
-template <typename T>
-void launch_deflate_ones(int64_t n, int kb, T* x, double* partials, int nparts, double* sums,
-                         const int* done, hipStream_t s);
-// start block in solver order (perm: solver -> user row, may be null)
-void launch_fill_random(int64_t n, int kb, int kcopy, const double* x0, uint64_t seed,
-                        const int32_t* perm, double* x, hipStream_t s);
 // scratch: 64 * kb * 16 bytes; x in solver order, out in user order
 void launch_sign_fix_and_copy(int64_t n, int kb, int k, const double* x, double* out,
                               const double* lam, double* lam_out, double* scratch,
                               const int32_t* perm, const int32_t* iperm, hipStream_t s);
-template <typename Tin, typename Tout>
-void launch_convert(int64_t count, const Tin* in, Tout* out, hipStream_t s);
 void launch_scale_rows(int64_t n, int k, const double* b, const double* x, double* y,
                        hipStream_t s);
 // dense n x n operator (which 0: A, 1: Q) and matching B (diag(b) or I)
@@ -198,15 +169,16 @@ void launch_copy_cols(int64_t n, int ksrc, int kdst, int kcopy, const int32_t* m
 
 // ---- timing.hip -------------------------------------------------------------
 enum KTimeKind { KT_OFF = 0, KT_SPMM_A = 1, KT_GRAM_RR = 2, KT_COMBINE = 3, KT_CHEB = 4 };
-// Records HIP events around one launch when `kind` is the kind being timed.
+// Records HIP events around `launches` back-to-back launches of one kernel
+// (bytes: their algorithmic total) when `kind` is the kind being timed.
 struct KScope {
-  KScope(int kind, hipStream_t s, double bytes, int tag);
+  KScope(int kind, hipStream_t s, double bytes, int tag, int launches = 1);
   ~KScope();
   bool on;
   hipStream_t s_;
   hipEvent_t a_ = nullptr, b_ = nullptr;
   double bytes_ = 0.0;
-  int tag_ = 0, phase_ = 0;
+  int tag_ = 0, phase_ = 0, launches_ = 1;
 };
 int ktimer_kind();
 int ktimer_new_phase();
@@ -219,6 +191,10 @@ int block_width(int K);
 size_t embed_workspace_bytes(const GraphOps& g, int K, const me_opts* o);
 int embed(const GraphOps& g, int K, double tol, const me_opts* o, const double* x0, void* ws,
           size_t ws_bytes, double* X, double* lambda, me_info* info, hipStream_t s);
+int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opts* o,
+                double* const* Xs, double* const* lams, me_info* infos, hipStream_t s);
+// Releases the device memory of a GraphOps (partially built ones too).
+void free_graph_ops(GraphOps& g);
 
 }  // namespace me
 

@@ -14,6 +14,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "engine.h"
 
 namespace me {
 
@@ -398,12 +399,9 @@ __device__ __forceinline__ void write_coef(SmallWS& w, int m, int kout, double* 
 
 // coef holds two (m x kb) matrices: first the P update (rows of the X block
 // zeroed), then the X update C = [C_X; C_W; C_P].
-__global__ void __launch_bounds__(kDenseThreads) k_rayleigh_ritz(int kb, int nb, const double* ga,
-                                                                 const double* gb, double piv_tol,
-                                                                 double* coef, double* lam,
-                                                                 Ctrl* ctrl, int final_pass) {
-  __shared__ SmallWS w;
-  if (!final_pass && ctrl->done) return;
+__device__ __forceinline__ void rr_body(SmallWS& w, int kb, int nb, const double* ga,
+                                        const double* gb, double piv_tol, double* coef,
+                                        double* lam, Ctrl* ctrl) {
   const int m = kb * nb;
   double* cp = coef;
   double* cx = coef + m * kb;
@@ -429,25 +427,41 @@ __global__ void __launch_bounds__(kDenseThreads) k_rayleigh_ritz(int kb, int nb,
   }
 }
 
+// One workgroup per slot of the set; G_B = gram (m x m), G_A = gram + m^2.
+__global__ void __launch_bounds__(kDenseThreads) k_sl_rayleigh_ritz(const SlotDev* sl,
+                                                                    const int32_t* slots, int kb,
+                                                                    int nb, double piv_tol,
+                                                                    int final_pass) {
+  __shared__ SmallWS w;
+  const SlotDev& d = sl[slots[blockIdx.x]];
+  if (!final_pass && d.ctrl->done) return;
+  const int m = kb * nb;
+  rr_body(w, kb, nb, d.gram + m * m, d.gram, piv_tol, d.coef, d.lam, d.ctrl);
+}
+
 // One wave suffices (and avoids cross-wave barriers) for bases up to 16.
 static int dense_threads(int m) { return m <= 16 ? kWave : kDenseThreads; }
 
-void launch_rayleigh_ritz(int kb, int nb, const double* ga, const double* gb, double piv_tol,
-                          double* coef, double* lam, Ctrl* ctrl, int final_pass, hipStream_t s) {
-  k_rayleigh_ritz<<<1, dense_threads(kb * nb), 0, s>>>(kb, nb, ga, gb, piv_tol, coef, lam, ctrl,
-                                                       final_pass);
+void sl_rayleigh_ritz(const SlotDev* sl, const TileSet& ts, int nb, double piv_tol,
+                      int final_pass, hipStream_t s) {
+  if (ts.nslots == 0) return;
+  k_sl_rayleigh_ritz<<<ts.nslots, dense_threads(ts.kb * nb), 0, s>>>(sl, ts.slots, ts.kb, nb,
+                                                                      piv_tol, final_pass);
 }
 
 // CholQR coefficients for W <- (W - X C) D R^-1, from g = [C; G] where
 // C = X^T B W and G = W^T B W (both kb x kb, row-major, stacked).  The
 // projected Gram is G - C^T C (X^T B X = I).  Columns whose projected norm
 // or Cholesky pivot is below piv_tol (relative) become zero.
-__global__ void __launch_bounds__(kDenseThreads) k_cholqr_coef(int kb, const double* g,
-                                                               double piv_tol, double* coef,
-                                                               const Ctrl* ctrl) {
+__global__ void __launch_bounds__(kWave) k_sl_cholqr_coef(const SlotDev* sl,
+                                                          const int32_t* slots, int kb,
+                                                          double piv_tol) {
   __shared__ SmallWS w;
   __shared__ double Gp[kMaxBlockCols][kMaxBlockCols + 1];
-  if (ctrl && ctrl->done) return;
+  const SlotDev& d = sl[slots[blockIdx.x]];
+  if (d.ctrl->done) return;
+  const double* g = d.gram;
+  double* coef = d.coefw;
   const int tid = threadIdx.x;
   const double* C = g;
   const double* G = g + kb * kb;
@@ -500,9 +514,9 @@ __global__ void __launch_bounds__(kDenseThreads) k_cholqr_coef(int kb, const dou
   }
 }
 
-void launch_cholqr_coef(int kb, const double* g, double piv_tol, double* coef, const Ctrl* ctrl,
-                        hipStream_t s) {
-  k_cholqr_coef<<<1, kWave, 0, s>>>(kb, g, piv_tol, coef, ctrl);
+void sl_cholqr_coef(const SlotDev* sl, const TileSet& ts, double piv_tol, hipStream_t s) {
+  if (ts.nslots == 0) return;
+  k_sl_cholqr_coef<<<ts.nslots, kWave, 0, s>>>(sl, ts.slots, ts.kb, piv_tol);
 }
 
 // Dense generalized problem for graphs with n <= 48: all n pairs.

@@ -1,0 +1,511 @@
+// Host side of the multi-problem LOBPCG engine (Section 4.3 asks for the
+// first K generalized eigenpairs by LOBPCG and gives no algorithm text; the
+// iteration is the block method of Knyazev (2001): Rayleigh-Ritz on the
+// basis [X W P], CholQR B-orthonormalisation of the preconditioned residual
+// block W, column dropping instead of an explicit restart, and an FP64
+// certificate pass before a solve is accepted).
+//
+// Per iteration, for every active slot, all on the caller's stream:
+//   R = A X - B X Lambda, rho_j, convergence           sl_resid + finalize
+//   W = T R  (T = I, Jacobi, or Chebyshev)             (+ sl_cheb_*)
+//   W <- (W - X X^T B W) R^-1   (CholQR)                Gram, Cholesky, combine
+//   AW = A W                                            difference-form product
+//   G_B = S^T B S, G_A = S^T A S, S = [X W P]           MFMA Gram + tile sums
+//   Rayleigh-Ritz in FP64                               one workgroup per slot
+//   P <- W C_W + P C_P,  X <- X C_X + P                 combine (also AX, AP)
+// Kernels skip slots whose device `done` flag is set, so the host enqueues
+// `check_every` iterations between reads of the flags.  A slot that stops
+// is certified (fresh A X, Rayleigh-Ritz on X, FP64 residuals); if the
+// certificate misses the tolerance the slot iterates again (at most three
+// times).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "engine.h"
+
+namespace me {
+
+int block_width(int K) {
+  if (K <= 4) return 4;
+  if (K <= 8) return 8;
+  return 16;
+}
+
+int partial_tiles(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kPartialBlocks, ceil_div(n, 64)));
+}
+
+// Drop threshold on the pivots of the unit-diagonal basis Gram (squared sine
+// of the angle between a column and the span of the earlier ones).  Small
+// thresholds let the inverse Cholesky factor grow without bound on nearly
+// dependent bases; 1e-4 keeps it bounded and costs no iterations.
+constexpr double kRrPivot = 1e-4;
+
+static int lpr64(int kb) { return kb / std::min(2, kb); }
+static int lpr32(int kb) { return kb / std::min(4, kb); }
+
+size_t Engine::slot_bytes(int64_t n, int kb) {
+  const int m = 3 * kb;
+  const int np = partial_tiles(n);
+  size_t b = kNumBlk64 * Arena::round((size_t)n * kb * 8);
+  b += kNumBlk32 * Arena::round((size_t)n * kb * 4);
+  b += Arena::round((size_t)np * 2 * m * m * 8);
+  b += Arena::round((size_t)2 * m * m * 8) + Arena::round((size_t)2 * m * kb * 8);
+  b += Arena::round((size_t)2 * kb * kb * 8) + 2 * Arena::round((size_t)kb * 8);
+  b += Arena::round((size_t)np * kb * 16);
+  return b;
+}
+
+Engine::Engine(hipStream_t s, const me_opts& o, int capacity, bool timed)
+    : s_(s), o_(o), cap_(capacity), timed_(timed) {
+  cheb_ = o.precond == ME_PRECOND_CHEBYSHEV;
+  cheb32_ = cheb_ && o.precision == ME_MIXED;
+}
+
+int Engine::init() {
+  sh_.assign(cap_, SlotHost());
+  res_.assign(cap_, SlotResult());
+  hdev_.assign(cap_, SlotDev());
+  ME_TRY(hipMallocAsync((void**)&d_slots_, sizeof(SlotDev) * cap_, s_));
+  ME_TRY(hipMallocAsync((void**)&d_ctrl_, sizeof(Ctrl) * cap_, s_));
+  ME_TRY(hipMallocAsync((void**)&d_cheb_, sizeof(ChebCoef) * cap_, s_));
+  ME_TRY(hipHostMalloc((void**)&h_ctrl_, sizeof(Ctrl) * cap_, hipHostMallocDefault));
+  std::memset(h_ctrl_, 0, sizeof(Ctrl) * cap_);
+  return ME_OK;
+}
+
+Engine::~Engine() {
+  (void)hipStreamSynchronize(s_);
+  free_sets(&sets_);
+  for (auto& h : sh_)
+    if (h.used && h.own_ws && h.ws) (void)hipFreeAsync(h.ws, s_);
+  if (d_slots_) (void)hipFreeAsync(d_slots_, s_);
+  if (d_ctrl_) (void)hipFreeAsync(d_ctrl_, s_);
+  if (d_cheb_) (void)hipFreeAsync(d_cheb_, s_);
+  (void)hipStreamSynchronize(s_);
+  if (h_ctrl_) (void)hipHostFree(h_ctrl_);
+}
+
+bool Engine::idle() const {
+  for (const auto& h : sh_)
+    if (h.used && !h.finished) return false;
+  return true;
+}
+
+int Engine::active() const {
+  int c = 0;
+  for (const auto& h : sh_) c += h.used && !h.finished;
+  return c;
+}
+
+int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
+  int id = -1;
+  for (int i = 0; i < cap_; ++i)
+    if (!sh_[i].used) {
+      id = i;
+      break;
+    }
+  if (id < 0) return ME_ERR_INVALID_ARG;
+  const GraphOps& g = *sp.g;
+  const int64_t n = g.n;
+  const int kb = sp.kb;
+  const size_t need = slot_bytes(n, kb);
+  bool own = false;
+  if (!ws) {
+    ME_TRY(hipMallocAsync(&ws, need, s_));
+    own = true;
+  } else if (ws_bytes < need) {
+    return ME_ERR_WORKSPACE;
+  }
+  SlotHost& h = sh_[id];
+  h = SlotHost();
+  h.used = true;
+  h.own_ws = own;
+  h.ws = ws;
+  h.ws_bytes = need;
+  h.sp = sp;
+  bytes_in_use_ += need;
+  res_[id] = SlotResult();
+
+  SlotDev d{};
+  Arena a{(char*)ws, need, 0};
+  for (int b = 0; b < kNumBlk64; ++b) d.b64[b] = a.take<double>((size_t)n * kb);
+  for (int b = 0; b < kNumBlk32; ++b) d.b32[b] = a.take<float>((size_t)n * kb);
+  const int m = 3 * kb;
+  const int np = partial_tiles(n);
+  d.partials = a.take<double>((size_t)np * 2 * m * m);
+  d.gram = a.take<double>((size_t)2 * m * m);
+  d.coef = a.take<double>((size_t)2 * m * kb);
+  d.coefw = a.take<double>((size_t)2 * kb * kb);
+  d.lam = a.take<double>(kb);
+  d.sums = a.take<double>(kb);
+  d.scratch = a.take<double>((size_t)np * kb * 2);
+  if (!d.scratch) return ME_ERR_WORKSPACE;
+  d.n = n;
+  d.nparts = np;
+  d.per = ((ceil_div(n, np) + 15) / 16) * 16;
+  d.need = sp.need;
+  d.deflate = sp.deflate;
+  d.skip_w = sp.op == OP_Q;
+  d.kcopy = sp.x0 ? sp.kcopy : 0;
+  d.k_out = sp.k_out;
+  d.a_rp = g.a_rp;
+  d.a_split = g.a_split;
+  d.a_col = g.a_col;
+  d.a_w = g.a_w;
+  d.a_w32 = g.a_w32;
+  if (sp.op == OP_A) {
+    d.invt = g.invt_s;
+    d.invt32 = g.invt32_s;
+    d.c_t = -g.mu;
+    d.s_diag = g.eps;
+    d.bdiag = g.b_s;
+    d.dinv = g.dinv_s;
+    d.dinv32 = g.dinv32_s;
+  } else {
+    d.invt = g.invt_s;
+    d.invt32 = g.invt32_s;
+    d.c_t = 1.0;
+    d.s_diag = 0.0;
+    d.bdiag = nullptr;
+    d.dinv = g.qinv_s;
+    d.dinv32 = g.qinv32_s;
+  }
+  d.perm = g.perm;
+  d.iperm = g.iperm;
+  d.x0 = sp.x0;
+  d.seed = sp.seed;
+  d.out_x = sp.out_x;
+  d.out_lam = sp.out_lam;
+  d.ctrl = d_ctrl_ + id;
+  d.cheb = d_cheb_ + id;
+  hdev_[id] = d;
+
+  Ctrl& c = h_ctrl_[id];
+  std::memset(&c, 0, sizeof(Ctrl));
+  c.max_iter = sp.max_iter;
+  c.need = sp.need;
+  c.kb = kb;
+  c.tol = sp.tol;
+  c.lam_scale = sp.lam_scale > 0 ? sp.lam_scale : 1.0;
+  c.lam_floor = 1e-8 * c.lam_scale;
+  c.cheb_deg = cheb_ ? o_.cheb_degree : 0;
+  c.cheb_afac = 0.5;
+  c.cheb_b = sp.cheb_b;
+  ME_TRY(hipMemcpyAsync(d_slots_ + id, &hdev_[id], sizeof(SlotDev), hipMemcpyHostToDevice, s_));
+  ME_TRY(hipMemcpyAsync(d_ctrl_ + id, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s_));
+  // the pageable SlotDev copy and the pinned Ctrl must not change before the
+  // copies complete: callers add between synchronised rounds
+  ME_TRY(hipStreamSynchronize(s_));
+  *id_out = id;
+  return ME_OK;
+}
+
+void Engine::release(int id) {
+  if (id < 0 || id >= cap_ || !sh_[id].used) return;
+  SlotHost& h = sh_[id];
+  if (h.own_ws && h.ws) (void)hipFreeAsync(h.ws, s_);
+  bytes_in_use_ -= h.ws_bytes;
+  h = SlotHost();
+}
+
+// Work lists of the slots `ids` (all of block width kb).
+int Engine::build_set(const std::vector<int>& ids, int kb, TileSet* ts) {
+  ts->kb = kb;
+  ts->nslots = (int)ids.size();
+  ts->ids = ids;
+  const int rb64 = kBlock / lpr64(kb), rb32 = kBlock / lpr32(kb);
+  std::vector<Tile> gat, e64, e32, red;
+  for (int id : ids) {
+    const SlotDev& d = hdev_[id];
+    for (int64_t b = 0; b < ceil_div(d.n, kGatherRows); ++b) gat.push_back({id, (int32_t)b});
+    for (int64_t b = 0; b < ceil_div(d.n, rb64); ++b) e64.push_back({id, (int32_t)b});
+    for (int64_t b = 0; b < ceil_div(d.n, rb32); ++b) e32.push_back({id, (int32_t)b});
+    for (int b = 0; b < d.nparts; ++b) red.push_back({id, b});
+  }
+  ts->n_gather = (int64_t)gat.size();
+  ts->n_elem64 = (int64_t)e64.size();
+  ts->n_elem32 = (int64_t)e32.size();
+  ts->n_red = (int64_t)red.size();
+  const size_t nt = gat.size() + e64.size() + e32.size() + red.size();
+  const size_t bytes = Arena::round(ids.size() * 4) + nt * sizeof(Tile) + 4 * 256;
+  ts->host.assign(bytes, 0);
+  size_t off = 0;
+  auto put = [&](const void* src, size_t sz) {
+    std::memcpy(ts->host.data() + off, src, sz);
+    const size_t at = off;
+    off = Arena::round(off + sz);
+    return at;
+  };
+  const size_t o_sl = put(ids.data(), ids.size() * 4);
+  const size_t o_g = put(gat.data(), gat.size() * sizeof(Tile));
+  const size_t o_e64 = put(e64.data(), e64.size() * sizeof(Tile));
+  const size_t o_e32 = put(e32.data(), e32.size() * sizeof(Tile));
+  const size_t o_r = put(red.data(), red.size() * sizeof(Tile));
+  ME_TRY(hipMallocAsync(&ts->mem, off > 0 ? off : 256, s_));
+  ME_TRY(hipMemcpyAsync(ts->mem, ts->host.data(), off, hipMemcpyHostToDevice, s_));
+  char* base = (char*)ts->mem;
+  ts->slots = (const int32_t*)(base + o_sl);
+  ts->gather = (const Tile*)(base + o_g);
+  ts->elem64 = (const Tile*)(base + o_e64);
+  ts->elem32 = (const Tile*)(base + o_e32);
+  ts->red = (const Tile*)(base + o_r);
+  return ME_OK;
+}
+
+void Engine::free_set(TileSet* ts) {
+  if (ts->mem) (void)hipFreeAsync(ts->mem, s_);
+  *ts = TileSet();
+}
+
+int Engine::sets_for(const std::vector<int>& ids, std::vector<TileSet>* sets) {
+  for (int kb : {4, 8, 16}) {
+    std::vector<int> sub;
+    for (int id : ids)
+      if (sh_[id].sp.kb == kb) sub.push_back(id);
+    if (sub.empty()) continue;
+    sets->emplace_back();
+    ME_TRY_STATUS(build_set(sub, kb, &sets->back()));
+  }
+  return ME_OK;
+}
+
+void Engine::free_sets(std::vector<TileSet>* sets) {
+  for (auto& t : *sets) free_set(&t);
+  sets->clear();
+}
+
+int Engine::read_ctrl() {
+  ME_TRY(hipGetLastError());
+  ME_TRY(hipMemcpyAsync(h_ctrl_, d_ctrl_, sizeof(Ctrl) * cap_, hipMemcpyDeviceToHost, s_));
+  ME_TRY(hipStreamSynchronize(s_));
+  return ME_OK;
+}
+
+// Rayleigh-Ritz on [X] alone (start and certificate): X, AX rotated to
+// B-orthonormal Ritz vectors, lam set.
+void Engine::rr_x(const TileSet& ts, int final_pass) {
+  const int kb = ts.kb;
+  sl_spmm<double>(d_slots_, ts, BX, BAX, 1, s_);
+  const int u[1] = {BX}, v2[1] = {BAX};
+  sl_gram(d_slots_, ts, 1, u, 1, u, 1, v2, 1, 1, s_);
+  sl_reduce(d_slots_, ts, 2 * kb * kb, 1, s_);
+  sl_rayleigh_ritz(d_slots_, ts, 1, 1e-14, final_pass, s_);
+  const int ix[1] = {BX}, ia[1] = {BAX};
+  sl_combine(d_slots_, ts, 1, 2, ix, ia, 1, ix, ia, 0, kb * kb, 1, s_);
+}
+
+void Engine::start_pass(const TileSet& ts) {
+  sl_fill_start(d_slots_, ts, s_);
+  sl_zero(d_slots_, ts, BP, s_);
+  sl_zero(d_slots_, ts, BAP, s_);
+  sl_deflate(d_slots_, ts, BX, 1, s_);
+  rr_x(ts, 0);
+}
+
+void Engine::iteration(const TileSet& ts) {
+  const int kb = ts.kb;
+  ++tag_;
+  const bool tm = timed_;
+  // residual, preconditioned W, convergence test
+  sl_resid(d_slots_, ts, cheb_ ? BR : BW, o_.precond == ME_PRECOND_JACOBI ? 1 : 0, 0, s_);
+  sl_resid_finalize(d_slots_, ts, 0, s_);
+  if (cheb_) {
+    const int deg = o_.cheb_degree;
+    double cb = 0.0;
+    if (tm) {
+      for (int id : ts.ids) {
+        const GraphOps& g = *sh_[id].sp.g;
+        const double sz = cheb32_ ? 4.0 : 8.0;
+        cb += 4.0 * (double)(g.nnz_w + g.nnz_t) + sz * (double)g.nnz_w +
+              (double)g.n * (8.0 + sz) + 6.0 * (double)g.n * kb * sz;
+      }
+    }
+    const int w = cheb32_ ? BW32 : BW, y = cheb32_ ? BY32 : BY, dd = cheb32_ ? BDD32 : BDD;
+    const int r = cheb32_ ? BR32 : BR;
+    int cur = ((deg - 1) % 2 == 0) ? w : y;
+    int nxt = cur == w ? y : w;
+    if (cheb32_) {
+      sl_to32(d_slots_, ts, BR, BR32, s_);
+      sl_cheb_first<float>(d_slots_, ts, r, cur, dd, s_);
+    } else {
+      sl_cheb_first<double>(d_slots_, ts, r, cur, dd, s_);
+    }
+    {
+      KScope ks(tm ? KT_CHEB : -1, s_, (deg - 1) * cb, tag_, deg - 1);
+      for (int k = 1; k < deg; ++k) {
+        if (cheb32_) sl_cheb_step<float>(d_slots_, ts, k, r, cur, nxt, dd, s_);
+        else sl_cheb_step<double>(d_slots_, ts, k, r, cur, nxt, dd, s_);
+        std::swap(cur, nxt);
+      }
+    }
+    if (cheb32_) sl_to64(d_slots_, ts, BW32, BW, s_);
+  }
+  sl_deflate(d_slots_, ts, BW, 0, s_);
+  // W <- (W - X C) R^-1
+  {
+    const int u[2] = {BX, BW}, v[1] = {BW}, o[1] = {BW};
+    sl_gram(d_slots_, ts, 2, u, 1, v, 0, nullptr, 1, 0, s_);
+    sl_reduce(d_slots_, ts, 2 * kb * kb, 0, s_);
+    sl_cholqr_coef(d_slots_, ts, 1e-10, s_);
+    sl_combine(d_slots_, ts, 2, 1, u, nullptr, 1, o, nullptr, 1, 0, 0, s_);
+  }
+  double sb = 0.0, blk = 0.0;
+  if (tm) {
+    for (int id : ts.ids) {
+      const GraphOps& g = *sh_[id].sp.g;
+      sb += 4.0 * (double)(g.nnz_w + g.nnz_t) + 8.0 * (double)g.nnz_w + (double)g.n * 16.0 +
+            2.0 * (double)g.n * kb * 8.0;
+      blk += (double)g.n * kb * 8.0;
+    }
+  }
+  {
+    KScope ks(tm ? KT_SPMM_A : -1, s_, sb, tag_);
+    sl_spmm<double>(d_slots_, ts, BW, BAW, 0, s_);
+  }
+  const int m = 3 * kb;
+  const int S[3] = {BX, BW, BP}, AS[3] = {BAX, BAW, BAP};
+  {
+    KScope ks(tm ? KT_GRAM_RR : -1, s_, 6.0 * blk + blk / kb, tag_);
+    sl_gram(d_slots_, ts, 3, S, 3, S, 3, AS, 1, 0, s_);
+  }
+  sl_reduce(d_slots_, ts, 2 * m * m, 0, s_);
+  sl_rayleigh_ritz(d_slots_, ts, 3, kRrPivot, 0, s_);
+  const int ox[2] = {BP, BX}, oa[2] = {BAP, BAX};
+  {
+    KScope ks(tm ? KT_COMBINE : -1, s_, 2.0 * 5.0 * blk, tag_);
+    sl_combine(d_slots_, ts, 3, 2, S, AS, 2, ox, oa, 0, 0, 0, s_);
+  }
+}
+
+int Engine::certify(const std::vector<int>& ids, std::vector<int>* finished) {
+  std::vector<TileSet> cs;
+  ME_TRY_STATUS(sets_for(ids, &cs));
+  for (auto& ts : cs) {
+    rr_x(ts, 1);
+    sl_resid(d_slots_, ts, -1, 0, 1, s_);
+    sl_resid_finalize(d_slots_, ts, 1, s_);
+  }
+  int st = read_ctrl();
+  free_sets(&cs);
+  if (st < 0) return st;
+  std::vector<int> fin, again;
+  for (int id : ids) {
+    const Ctrl& c = h_ctrl_[id];
+    SlotHost& h = sh_[id];
+    SlotResult& r = res_[id];
+    double worst = 0.0;
+    for (int j = 0; j < h.sp.need; ++j) worst = std::max(worst, c.rho[j]);
+    r.iterations = c.iter;
+    r.worst = worst;
+    for (int j = 0; j < h.sp.kb && j < kMaxBlockCols; ++j) r.lam[j] = c.lam[j];
+    if (c.nonfinite || !std::isfinite(worst)) {
+      r.status = ME_ERR_BREAKDOWN;
+      h.finished = true;
+      continue;
+    }
+    if (worst <= h.sp.tol || c.iter >= h.sp.max_iter || h.reentries >= 3) {
+      r.status = worst <= h.sp.tol ? ME_OK : ME_WARN_NOT_CONVERGED;
+      fin.push_back(id);
+    } else {
+      // drift between the recurrences and a fresh product: iterate again
+      ++h.reentries;
+      again.push_back(id);
+    }
+  }
+  if (!fin.empty()) {
+    ME_TRY_STATUS(sets_for(fin, &cs));
+    for (auto& ts : cs) {
+      const int u[1] = {BX};
+      sl_gram(d_slots_, ts, 1, u, 1, u, 0, nullptr, 1, 1, s_);
+      sl_reduce(d_slots_, ts, ts.kb * ts.kb, 1, s_);
+      sl_orth(d_slots_, ts, s_);
+      sl_output(d_slots_, ts, s_);
+    }
+    st = read_ctrl();
+    free_sets(&cs);
+    if (st < 0) return st;
+    for (int id : fin) {
+      res_[id].orth = h_ctrl_[id].orth;
+      sh_[id].finished = true;
+    }
+  }
+  if (!again.empty()) {
+    ME_TRY_STATUS(sets_for(again, &cs));
+    for (auto& ts : cs) {
+      sl_reenter(d_slots_, ts, s_);
+      sl_zero(d_slots_, ts, BP, s_);
+      sl_zero(d_slots_, ts, BAP, s_);
+    }
+    ME_TRY(hipStreamSynchronize(s_));
+    free_sets(&cs);
+    for (int id : again) h_ctrl_[id].done = 0;
+  }
+  for (int id : ids)
+    if (sh_[id].finished && finished) finished->push_back(id);
+  return ME_OK;
+}
+
+int Engine::step(std::vector<int>* finished) {
+  // start the slots added since the last round
+  std::vector<int> fresh;
+  for (int id = 0; id < cap_; ++id)
+    if (sh_[id].used && !sh_[id].started) fresh.push_back(id);
+  if (!fresh.empty()) {
+    std::vector<TileSet> cs;
+    ME_TRY_STATUS(sets_for(fresh, &cs));
+    for (auto& ts : cs) start_pass(ts);
+    ME_TRY(hipStreamSynchronize(s_));
+    free_sets(&cs);
+    for (int id : fresh) {
+      sh_[id].started = true;
+      active_.push_back(id);
+    }
+    sets_dirty_ = true;
+  }
+  if (active_.empty()) return ME_OK;
+  if (sets_dirty_) {
+    ME_TRY(hipStreamSynchronize(s_));
+    free_sets(&sets_);
+    std::sort(active_.begin(), active_.end());
+    ME_TRY_STATUS(sets_for(active_, &sets_));
+    sets_dirty_ = false;
+  }
+  std::vector<int> iter0(active_.size());
+  for (size_t q = 0; q < active_.size(); ++q) iter0[q] = h_ctrl_[active_[q]].iter;
+  if (timed_) phase_ = ktimer_new_phase();
+  tag_ = 0;
+  const int ce = o_.check_every > 0 ? o_.check_every : 16;
+  for (int q = 0; q < ce; ++q)
+    for (auto& ts : sets_) iteration(ts);
+  ME_TRY_STATUS(read_ctrl());
+  int adv = 0;
+  std::vector<int> stopped;
+  for (size_t q = 0; q < active_.size(); ++q) {
+    const int id = active_[q];
+    adv = std::max(adv, h_ctrl_[id].iter - iter0[q]);
+    if (h_ctrl_[id].done) stopped.push_back(id);
+  }
+  // launches of the round after every slot had stopped did no work
+  if (timed_) ktimer_drop_after(phase_, adv * (int)sets_.size());
+  if (!stopped.empty()) {
+    ME_TRY_STATUS(certify(stopped, finished));
+    std::vector<int> keep;
+    for (int id : active_)
+      if (!sh_[id].finished) keep.push_back(id);
+    if (keep.size() != active_.size()) {
+      active_.swap(keep);
+      sets_dirty_ = true;
+    }
+  }
+  return ME_OK;
+}
+
+int Engine::run() {
+  while (!idle()) ME_TRY_STATUS(step(nullptr));
+  if (timed_) ktimer_collect();
+  return ME_OK;
+}
+
+}  // namespace me

@@ -1,0 +1,917 @@
+// Row-streaming kernels of the LOBPCG engine.  Every launch covers one set
+// of slots with a common block width KB through a work list of tiles; a
+// tile belongs to one slot, so all lanes of a workgroup share the slot's
+// pointers (scalar loads) and its early-exit flag.
+//
+// Blocks are row-major n x KB.  Elementwise kernels give each row
+// LPR = KB / VEC lanes with one 16-byte vector each; the gathering kernels
+// (operator products) give each row 8 lanes that split the row's entries.
+//
+// Difference-form operator (eq. (obj2) with the Laplacian identity of
+// Section 3.1): with the merged row [W columns | T columns],
+//   (A x)_i = sum_{j in N(i)} w_ij (x_i - x_j)
+//             - mu sum_{j in T_i} (1/T_i + 1/T_j) (x_i - x_j) + eps x_i
+//   (Q x)_i = sum_{j in T_i} (1/T_i + 1/T_j) (x_i - x_j)
+#include <cmath>
+
+#include "common.h"
+#include "engine.h"
+#include "rowops.h"
+
+namespace me {
+
+template <typename T>
+struct SB;
+template <>
+struct SB<double> {
+  static __device__ __forceinline__ double* blk(const SlotDev& d, int id) { return d.b64[id]; }
+  static __device__ __forceinline__ const double* w(const SlotDev& d) { return d.a_w; }
+  static __device__ __forceinline__ const double* invt(const SlotDev& d) { return d.invt; }
+  static __device__ __forceinline__ const double* dinv(const SlotDev& d) { return d.dinv; }
+};
+template <>
+struct SB<float> {
+  static __device__ __forceinline__ float* blk(const SlotDev& d, int id) { return d.b32[id]; }
+  static __device__ __forceinline__ const float* w(const SlotDev& d) { return d.a_w32; }
+  static __device__ __forceinline__ const float* invt(const SlotDev& d) { return d.invt32; }
+  static __device__ __forceinline__ const float* dinv(const SlotDev& d) { return d.dinv32; }
+};
+
+// rows per tile of the elementwise kernels
+template <typename T, int KB>
+struct ElemCfg {
+  using L = Lay<T, KB>;
+  static constexpr int VEC = L::VEC, LPR = L::LPR, RB = kBlock / LPR;
+};
+
+__device__ __forceinline__ bool skip_slot(const SlotDev& d, int cert) {
+  return !cert && d.ctrl->done;
+}
+
+// ---------------------------------------------------------------------------
+// Operator product Y = Op X (gathering; XCD-aware tile order)
+// ---------------------------------------------------------------------------
+
+template <typename T, int KB>
+__global__ void __launch_bounds__(kBlock) k_sl_spmm(const SlotDev* __restrict__ sl,
+                                                    const Tile* __restrict__ tiles,
+                                                    int64_t ntiles, int in, int out, int cert) {
+  using C = RowCfg<T, KB>;
+  const int64_t b = xcd_block(ntiles);
+  if (b >= ntiles) return;
+  const Tile t = tiles[b];
+  const SlotDev& d = sl[t.slot];
+  if (skip_slot(d, cert)) return;
+  const int64_t row = (int64_t)t.blk * kGatherRows + threadIdx.x / C::G;
+  const int q = threadIdx.x % C::G;
+  const bool live = row < d.n;
+  const T* x = SB<T>::blk(d, in);
+  T xi[KB];
+#pragma unroll
+  for (int v = 0; v < KB; ++v) xi[v] = 0;
+  if (live) load_row<T, KB>(x + row * KB, xi);
+  T acc[KB];
+  spmm_row<T, KB>(live, row, q, d.a_rp, d.a_split, d.a_col, SB<T>::w(d), SB<T>::invt(d),
+                  (T)d.c_t, d.skip_w, x, xi, acc);
+  if (!live || q >= C::NLD) return;
+  T* y = SB<T>::blk(d, out);
+  const T sd = (T)d.s_diag;
+#pragma unroll
+  for (int l = 0; l < C::NLD; ++l) {
+    if (q == l) {
+      VecT<T, C::V16> o;
+#pragma unroll
+      for (int v = 0; v < C::V16; ++v) o.v[v] = acc[l * C::V16 + v] + sd * xi[l * C::V16 + v];
+      stv<T, C::V16>(y + row * KB + l * C::V16, o);
+    }
+  }
+}
+
+template <typename T>
+void sl_spmm(const SlotDev* sl, const TileSet& ts, int in, int out, int cert, hipStream_t s) {
+  if (ts.n_gather == 0) return;
+  ME_DISPATCH_KB(ts.kb, {
+    k_sl_spmm<T, KB><<<xcd_grid(ts.n_gather), kBlock, 0, s>>>(sl, ts.gather, ts.n_gather, in,
+                                                               out, cert);
+  });
+}
+template void sl_spmm<double>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Chebyshev preconditioner: approximate solve of Op y = R with Jacobi
+// scaling D, spectrum of D^-1 Op taken as [a, b], theta = (a + b) / 2:
+//   y_1 = dd_1 = D^-1 R / theta,
+//   dd_{k+1} = alpha_k dd_k + beta_k D^-1 (R - Op y_k),  y_{k+1} = y_k + dd_{k+1}.
+// ---------------------------------------------------------------------------
+
+template <typename T, int KB>
+__global__ void __launch_bounds__(kBlock) k_sl_cheb_first(const SlotDev* __restrict__ sl,
+                                                          const Tile* __restrict__ tiles, int r,
+                                                          int y, int dd) {
+  using E = ElemCfg<T, KB>;
+  const Tile t = tiles[blockIdx.x];
+  const SlotDev& d = sl[t.slot];
+  if (d.ctrl->done) return;
+  const int64_t row = (int64_t)t.blk * E::RB + threadIdx.x / E::LPR;
+  const int sub = threadIdx.x % E::LPR;
+  if (row >= d.n) return;
+  const T sc = (T)(1.0 / d.cheb->theta) * SB<T>::dinv(d)[row];
+  const int64_t o = row * KB + sub * E::VEC;
+  auto v = ldv<T, E::VEC>(SB<T>::blk(d, r) + o);
+#pragma unroll
+  for (int q = 0; q < E::VEC; ++q) v.v[q] *= sc;
+  stv<T, E::VEC>(SB<T>::blk(d, y) + o, v);
+  stv<T, E::VEC>(SB<T>::blk(d, dd) + o, v);
+}
+
+template <typename T, int KB>
+__global__ void __launch_bounds__(kBlock) k_sl_cheb_step(const SlotDev* __restrict__ sl,
+                                                         const Tile* __restrict__ tiles,
+                                                         int64_t ntiles, int k, int r, int yin,
+                                                         int yout, int ddb) {
+  using C = RowCfg<T, KB>;
+  const int64_t b = xcd_block(ntiles);
+  if (b >= ntiles) return;
+  const Tile t = tiles[b];
+  const SlotDev& d = sl[t.slot];
+  if (d.ctrl->done) return;
+  const int64_t row = (int64_t)t.blk * kGatherRows + threadIdx.x / C::G;
+  const int q = threadIdx.x % C::G;
+  const bool live = row < d.n;
+  const T* yi_p = SB<T>::blk(d, yin);
+  T yi[KB];
+#pragma unroll
+  for (int v = 0; v < KB; ++v) yi[v] = 0;
+  if (live) load_row<T, KB>(yi_p + row * KB, yi);
+  T acc[KB];
+  spmm_row<T, KB>(live, row, q, d.a_rp, d.a_split, d.a_col, SB<T>::w(d), SB<T>::invt(d),
+                  (T)d.c_t, d.skip_w, yi_p, yi, acc);
+  if (!live || q >= C::NLD) return;
+  const T sd = (T)d.s_diag;
+  const T alpha = (T)d.cheb->alpha[k];
+  const T beta = (T)d.cheb->beta[k] * SB<T>::dinv(d)[row];
+  const T* rp = SB<T>::blk(d, r);
+  T* dp = SB<T>::blk(d, ddb);
+  T* yo_p = SB<T>::blk(d, yout);
+#pragma unroll
+  for (int l = 0; l < C::NLD; ++l) {
+    if (q == l) {
+      const int64_t o = row * KB + l * C::V16;
+      const auto ri = ldv<T, C::V16>(rp + o);
+      auto di = ldv<T, C::V16>(dp + o);
+      VecT<T, C::V16> yo;
+#pragma unroll
+      for (int v = 0; v < C::V16; ++v) {
+        const int c = l * C::V16 + v;
+        const T res = ri.v[v] - (acc[c] + sd * yi[c]);
+        di.v[v] = alpha * di.v[v] + beta * res;
+        yo.v[v] = yi[c] + di.v[v];
+      }
+      stv<T, C::V16>(dp + o, di);
+      stv<T, C::V16>(yo_p + o, yo);
+    }
+  }
+}
+
+template <typename T>
+void sl_cheb_first(const SlotDev* sl, const TileSet& ts, int r, int y, int dd, hipStream_t s) {
+  const Tile* tl = sizeof(T) == 8 ? ts.elem64 : ts.elem32;
+  const int64_t nt = sizeof(T) == 8 ? ts.n_elem64 : ts.n_elem32;
+  if (nt == 0) return;
+  ME_DISPATCH_KB(ts.kb, { k_sl_cheb_first<T, KB><<<nt, kBlock, 0, s>>>(sl, tl, r, y, dd); });
+}
+template <typename T>
+void sl_cheb_step(const SlotDev* sl, const TileSet& ts, int k, int r, int yin, int yout, int dd,
+                  hipStream_t s) {
+  if (ts.n_gather == 0) return;
+  ME_DISPATCH_KB(ts.kb, {
+    k_sl_cheb_step<T, KB><<<xcd_grid(ts.n_gather), kBlock, 0, s>>>(sl, ts.gather, ts.n_gather, k,
+                                                                    r, yin, yout, dd);
+  });
+}
+template void sl_cheb_first<double>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
+template void sl_cheb_first<float>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
+template void sl_cheb_step<double>(const SlotDev*, const TileSet&, int, int, int, int, int,
+                                   hipStream_t);
+template void sl_cheb_step<float>(const SlotDev*, const TileSet&, int, int, int, int, int,
+                                  hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Residual R = AX - B X Lambda; W = R or D^-1 R (Jacobi); per tile: column
+// sums of |r|^2, |B x|^2 and x^T D x (3 KB partials).
+// ---------------------------------------------------------------------------
+
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_sl_resid(const SlotDev* __restrict__ sl,
+                                                     const Tile* __restrict__ tiles, int wblk,
+                                                     int jacobi, int cert) {
+  using E = ElemCfg<double, KB>;
+  constexpr int VEC = E::VEC, LPR = E::LPR, NE = 3 * KB;
+  __shared__ double sh[kBlock / kWave][NE];
+  const Tile t = tiles[blockIdx.x];
+  const SlotDev& d = sl[t.slot];
+  if (skip_slot(d, cert)) return;
+  const int tid = threadIdx.x, sub = tid % LPR;
+  const int64_t r0 = (int64_t)t.blk * d.per;
+  const int64_t r1 = r0 + d.per < d.n ? r0 + d.per : d.n;
+  const double* x = d.b64[BX];
+  const double* ax = d.b64[BAX];
+  double* w = wblk >= 0 ? d.b64[wblk] : nullptr;
+  double r2[VEC], b2[VEC], xd[VEC], lm[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    r2[v] = b2[v] = xd[v] = 0.0;
+    lm[v] = d.lam[sub * VEC + v];
+  }
+  for (int64_t row = r0 + tid / LPR; row < r1; row += E::RB) {
+    const int64_t o = row * KB + sub * VEC;
+    const auto xi = ldv<double, VEC>(x + o);
+    const auto ai = ldv<double, VEC>(ax + o);
+    const double bi = d.bdiag ? d.bdiag[row] : 1.0;
+    const double dv = d.dinv[row];
+    const double di = jacobi ? dv : 1.0;
+    const double rdv = 1.0 / dv;
+    VecT<double, VEC> wv;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const double bx = bi * xi.v[v];
+      const double r = ai.v[v] - lm[v] * bx;
+      r2[v] += r * r;
+      b2[v] += bx * bx;
+      xd[v] += xi.v[v] * xi.v[v] * rdv;
+      wv.v[v] = di * r;
+    }
+    if (w) stv<double, VEC>(w + o, wv);
+  }
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    for (int off = kWave / 2; off >= LPR; off >>= 1) {
+      r2[v] += __shfl_xor(r2[v], off);
+      b2[v] += __shfl_xor(b2[v], off);
+      xd[v] += __shfl_xor(xd[v], off);
+    }
+  }
+  const int lane = tid % kWave, wv_ = tid / kWave;
+  if (lane < LPR) {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      sh[wv_][lane * VEC + v] = r2[v];
+      sh[wv_][KB + lane * VEC + v] = b2[v];
+      sh[wv_][2 * KB + lane * VEC + v] = xd[v];
+    }
+  }
+  __syncthreads();
+  if (tid < NE) {
+    double acc = 0;
+    for (int q = 0; q < kBlock / kWave; ++q) acc += sh[q][tid];
+    d.partials[(int64_t)t.blk * NE + tid] = acc;
+  }
+}
+
+void sl_resid(const SlotDev* sl, const TileSet& ts, int w, int jacobi, int cert, hipStream_t s) {
+  if (ts.n_red == 0) return;
+  ME_DISPATCH_KB(ts.kb, {
+    k_sl_resid<KB><<<ts.n_red, kBlock, 0, s>>>(sl, ts.red, w, jacobi, cert);
+  });
+}
+
+// rho_j = |r_j| / (|lambda_j| |B x_j|), with |lambda_j| replaced by the
+// operator scale when it is below the zero threshold; convergence
+// bookkeeping; Chebyshev interval and coefficients for this iteration.
+// One wave per slot: lane l sums tiles l, l + 64, ...; then a fixed xor tree.
+template <int KB>
+__global__ void __launch_bounds__(kWave) k_sl_resid_finalize(const SlotDev* __restrict__ sl,
+                                                             const int32_t* __restrict__ slots,
+                                                             int final_pass) {
+  constexpr int NE = 3 * KB;
+  __shared__ double tot[NE];
+  const SlotDev& d = sl[slots[blockIdx.x]];
+  Ctrl* ctrl = d.ctrl;
+  if (!final_pass && ctrl->done) return;
+  const int lane = threadIdx.x;
+  double acc[NE];
+#pragma unroll
+  for (int e = 0; e < NE; ++e) acc[e] = 0.0;
+  for (int p = lane; p < d.nparts; p += kWave) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) acc[e] += d.partials[(int64_t)p * NE + e];
+  }
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    double v = acc[e];
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) tot[e] = v;
+  }
+  __syncthreads();
+  const double* lam = d.lam;
+  int conv = 0, bad = 0;
+  if (lane < KB) {
+    const double al = fabs(lam[lane]);
+    const double den = (al >= ctrl->lam_floor ? al : ctrl->lam_scale) * sqrt(tot[KB + lane]);
+    const double rho = sqrt(tot[lane]) / den;
+    ctrl->rho[lane] = rho;
+    if (final_pass) ctrl->lam[lane] = lam[lane];
+    conv = (lane < ctrl->need) && (rho <= ctrl->tol);
+    bad = !isfinite(rho);
+  }
+  const int nc = __popcll(__ballot(conv));
+  const int nb = __popcll(__ballot(bad));
+  if (lane == 0) {
+    ctrl->nconv = nc;
+    if (nb) ctrl->nonfinite = 1;
+    if (!final_pass) {
+      if (nc >= ctrl->need || nb || ctrl->iter >= ctrl->max_iter) ctrl->done = 1;
+      else ctrl->iter += 1;
+    }
+  }
+  const int deg = ctrl->cheb_deg;
+  if (final_pass || deg < 2) return;
+  // [a, b]: a = afac * (x_j^T A x_j) / (x_j^T D x_j) with x_j^T B x_j = 1,
+  // j the leading Ritz pair with a nonzero value (the eps = 0 case has
+  // lambda_1 = 0)
+  const double b = ctrl->cheb_b;
+  double a = -1.0;
+  for (int j = 0; j < KB; ++j) {
+    if (fabs(lam[j]) >= ctrl->lam_floor) {
+      a = ctrl->cheb_afac * fabs(lam[j]) / tot[2 * KB + j];
+      break;
+    }
+  }
+  if (!(a > 0.0) || !isfinite(a)) a = 1e-3 * b;
+  a = fmin(fmax(a, 1e-9 * b), 0.5 * b);
+  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a);
+  const double phi = acosh(theta / delta);
+  // rho_k = T_k(sigma) / T_{k+1}(sigma) = cosh(k phi) / cosh((k+1) phi),
+  // written with decaying exponentials so that no cosh overflows
+  const double e1 = exp(-phi);
+  ChebCoef* cc = d.cheb;
+  for (int k = lane + 1; k < deg; k += kWave) {
+    const double rk = e1 * (1.0 + exp(-2.0 * k * phi)) / (1.0 + exp(-2.0 * (k + 1) * phi));
+    const double rkm = e1 * (1.0 + exp(-2.0 * (k - 1) * phi)) / (1.0 + exp(-2.0 * k * phi));
+    cc->alpha[k] = rk * rkm;
+    cc->beta[k] = 2.0 * rk / delta;
+  }
+  if (lane == 0) {
+    cc->a = a;
+    cc->theta = theta;
+  }
+}
+
+void sl_resid_finalize(const SlotDev* sl, const TileSet& ts, int final_pass, hipStream_t s) {
+  if (ts.nslots == 0) return;
+  ME_DISPATCH_KB(ts.kb, {
+    k_sl_resid_finalize<KB><<<ts.nslots, kWave, 0, s>>>(sl, ts.slots, final_pass);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Tall-skinny Gram products on MFMA (FP64):
+//   G1 = U^T diag(b) V ((nu KB) x (nv KB)),  G2 = U^T V2 ((nu KB) x (nv2 KB))
+// per reduction tile of a slot.  Each 16x16x4 step consumes 4 rows; lane l
+// supplies U[row + l/16][16a + l%16] (A operand) and V[row + l/16][16b + l%16]
+// (B operand).  Tiles write partial Grams; sl_reduce sums them in tile order.
+// ---------------------------------------------------------------------------
+
+struct Ids {
+  int v[3];
+};
+
+template <int KB>
+__device__ __forceinline__ double load_cat(const SlotDev& d, const Ids& ids, int nblk,
+                                           int64_t row, int col, int64_t r1) {
+  const int blk = col / KB;
+  if (row >= r1 || blk >= nblk) return 0.0;
+  return d.b64[ids.v[blk]][row * KB + (col % KB)];
+}
+
+template <int KB, int NU, int NV, int NV2>
+__global__ void __launch_bounds__(kBlock) k_sl_gram(const SlotDev* __restrict__ sl,
+                                                    const Tile* __restrict__ tiles, Ids u, Ids v,
+                                                    Ids v2, int use_b, int cert) {
+  constexpr int MU = NU * KB, MV = NV * KB, MV2 = NV2 * KB;
+  constexpr int TU = (MU + 15) / 16, TV = (MV + 15) / 16, TV2 = (MV2 + 15) / 16;
+  constexpr int E1 = MU * MV, E2 = MU * MV2;
+  using Acc = typename Mfma<double>::Acc;
+  __shared__ double sh[E1 + E2];
+  const Tile t = tiles[blockIdx.x];
+  const SlotDev& d = sl[t.slot];
+  if (skip_slot(d, cert)) return;
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  Acc acc1[TU][TV > 0 ? TV : 1];
+  Acc acc2[TU][TV2 > 0 ? TV2 : 1];
+#pragma unroll
+  for (int a = 0; a < TU; ++a) {
+#pragma unroll
+    for (int b = 0; b < TV; ++b) acc1[a][b] = Acc{0, 0, 0, 0};
+#pragma unroll
+    for (int b = 0; b < TV2; ++b) acc2[a][b] = Acc{0, 0, 0, 0};
+  }
+  const int64_t r0 = (int64_t)t.blk * d.per;
+  const int64_t r1 = r0 + d.per < d.n ? r0 + d.per : d.n;
+  const double* wd = use_b ? d.bdiag : nullptr;
+  const int li = lane % 16, lk = lane / 16;
+  constexpr int NW = kBlock / kWave;
+  for (int64_t base = r0 + 16 * wave; base < r1; base += 16 * NW) {
+    double ua[4][TU], vb[4][TV > 0 ? TV : 1], v2b[4][TV2 > 0 ? TV2 : 1];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int64_t row = base + 4 * ks + lk;
+      const bool ok = row < r1;
+#pragma unroll
+      for (int a = 0; a < TU; ++a) ua[ks][a] = ok ? load_cat<KB>(d, u, NU, row, 16 * a + li, r1) : 0.0;
+      const double wr = (ok && TV > 0) ? (wd ? wd[row] : 1.0) : 0.0;
+#pragma unroll
+      for (int b = 0; b < TV; ++b) vb[ks][b] = ok ? wr * load_cat<KB>(d, v, NV, row, 16 * b + li, r1) : 0.0;
+#pragma unroll
+      for (int b = 0; b < TV2; ++b) v2b[ks][b] = ok ? load_cat<KB>(d, v2, NV2, row, 16 * b + li, r1) : 0.0;
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+#pragma unroll
+      for (int a = 0; a < TU; ++a) {
+#pragma unroll
+        for (int b = 0; b < TV; ++b) acc1[a][b] = Mfma<double>::step(ua[ks][a], vb[ks][b], acc1[a][b]);
+#pragma unroll
+        for (int b = 0; b < TV2; ++b) acc2[a][b] = Mfma<double>::step(ua[ks][a], v2b[ks][b], acc2[a][b]);
+      }
+    }
+  }
+  for (int wv = 0; wv < NW; ++wv) {
+    if (wave == wv) {
+#pragma unroll
+      for (int a = 0; a < TU; ++a) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = 16 * a + Mfma<double>::row(lk, q);
+          if (i >= MU) continue;
+#pragma unroll
+          for (int b = 0; b < TV; ++b) {
+            const int j = 16 * b + li;
+            if (j < MV) {
+              const double val = acc1[a][b][q];
+              if (wv == 0) sh[i * MV + j] = val; else sh[i * MV + j] += val;
+            }
+          }
+#pragma unroll
+          for (int b = 0; b < TV2; ++b) {
+            const int j = 16 * b + li;
+            if (j < MV2) {
+              const double val = acc2[a][b][q];
+              if (wv == 0) sh[E1 + i * MV2 + j] = val; else sh[E1 + i * MV2 + j] += val;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* out = d.partials + (int64_t)t.blk * (E1 + E2);
+  for (int e = tid; e < E1 + E2; e += kBlock) out[e] = sh[e];
+}
+
+void sl_gram(const SlotDev* sl, const TileSet& ts, int nu, const int* u, int nv, const int* v,
+             int nv2, const int* v2, int use_b, int cert, hipStream_t s) {
+  if (ts.n_red == 0) return;
+  Ids iu{{0, 0, 0}}, iv{{0, 0, 0}}, iv2{{0, 0, 0}};
+  for (int i = 0; i < nu; ++i) iu.v[i] = u[i];
+  for (int i = 0; i < nv; ++i) iv.v[i] = v[i];
+  for (int i = 0; i < nv2; ++i) iv2.v[i] = v2[i];
+#define ME_SL_GRAM(NU_, NV_, NV2_)                                                           \
+  if (nu == NU_ && nv == NV_ && nv2 == NV2_) {                                               \
+    ME_DISPATCH_KB(ts.kb, {                                                                  \
+      k_sl_gram<KB, NU_, NV_, NV2_><<<ts.n_red, kBlock, 0, s>>>(sl, ts.red, iu, iv, iv2,     \
+                                                                use_b, cert);                \
+    });                                                                                      \
+    return;                                                                                  \
+  }
+  ME_SL_GRAM(2, 1, 0)  // [X W]^T B W
+  ME_SL_GRAM(1, 1, 1)  // X^T B X, X^T AX
+  ME_SL_GRAM(3, 3, 3)  // [X W P] pair
+  ME_SL_GRAM(1, 1, 0)  // X^T B X
+#undef ME_SL_GRAM
+}
+
+// out[e] = sum_p partials[p][e], p ascending, per slot (target 0: gram,
+// 1: sums, only for slots that deflate).
+__global__ void __launch_bounds__(kBlock) k_sl_reduce(const SlotDev* __restrict__ sl,
+                                                      const int32_t* __restrict__ slots, int nent,
+                                                      int target, int cert) {
+  __shared__ double sh[8][33];
+  const SlotDev& d = sl[slots[blockIdx.y]];
+  if (skip_slot(d, cert)) return;
+  if (target == 1 && !d.deflate) return;
+  const int el = threadIdx.x % 32, pl = threadIdx.x / 32;
+  const int e = blockIdx.x * 32 + el;
+  double s = 0;
+  if (e < nent) {
+    for (int p = pl; p < d.nparts; p += 8) s += d.partials[(int64_t)p * nent + e];
+  }
+  sh[pl][el] = s;
+  __syncthreads();
+  if (pl == 0 && e < nent) {
+    double t = 0;
+    for (int q = 0; q < 8; ++q) t += sh[q][el];
+    (target == 0 ? d.gram : d.sums)[e] = t;
+  }
+}
+
+void sl_reduce(const SlotDev* sl, const TileSet& ts, int nent, int cert, hipStream_t s) {
+  if (ts.nslots == 0) return;
+  k_sl_reduce<<<dim3(ceil_div(nent, 32), ts.nslots), kBlock, 0, s>>>(sl, ts.slots, nent, 0, cert);
+}
+
+// ---------------------------------------------------------------------------
+// Block combination: out_o = sum_s in_s C_o.  Each tile stages its rows in
+// LDS (coalesced), then every lane forms VEC output columns.  Outputs may
+// alias inputs: a tile reads all of its rows before writing any.
+// ---------------------------------------------------------------------------
+
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_sl_combine(const SlotDev* __restrict__ sl,
+                                                       const Tile* __restrict__ tiles, int nin,
+                                                       int ngroup, Ids in0, Ids in1, int nout,
+                                                       Ids out0, Ids out1, int which, int off,
+                                                       int cert) {
+  using E = ElemCfg<double, KB>;
+  constexpr int VEC = E::VEC, LPR = E::LPR, RB = E::RB;
+  __shared__ double rows[2][RB][3 * KB + 1];
+  __shared__ double cf[2][3 * KB][KB];
+  const Tile t = tiles[blockIdx.x];
+  const SlotDev& d = sl[t.slot];
+  if (skip_slot(d, cert)) return;
+  const int tid = threadIdx.x;
+  const int m = nin * KB;
+  const double* coef = (which == 0 ? d.coef : d.coefw) + off;
+  for (int u = tid; u < nout * m * KB; u += kBlock) {
+    const int o = u / (m * KB), rem = u % (m * KB);
+    cf[o][rem / KB][rem % KB] = coef[u];
+  }
+  const int rloc = tid / LPR, sub = tid % LPR;
+  const int64_t row = (int64_t)t.blk * RB + rloc;
+  if (row < d.n) {
+    for (int g = 0; g < ngroup; ++g) {
+      const Ids& in = g == 0 ? in0 : in1;
+      for (int sidx = 0; sidx < nin; ++sidx) {
+        const auto v = ldv<double, VEC>(d.b64[in.v[sidx]] + row * KB + sub * VEC);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) rows[g][rloc][sidx * KB + sub * VEC + q] = v.v[q];
+      }
+    }
+  }
+  __syncthreads();
+  if (row >= d.n) return;
+  for (int g = 0; g < ngroup; ++g) {
+    const Ids& out = g == 0 ? out0 : out1;
+    for (int o = 0; o < nout; ++o) {
+      double acc[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) acc[q] = 0;
+      for (int k = 0; k < m; ++k) {
+        const double a = rows[g][rloc][k];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) acc[q] += a * cf[o][k][sub * VEC + q];
+      }
+      VecT<double, VEC> ov;
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) ov.v[q] = acc[q];
+      stv<double, VEC>(d.b64[out.v[o]] + row * KB + sub * VEC, ov);
+    }
+  }
+}
+
+void sl_combine(const SlotDev* sl, const TileSet& ts, int nin, int ngroup, const int* in0,
+                const int* in1, int nout, const int* out0, const int* out1, int which, int off,
+                int cert, hipStream_t s) {
+  if (ts.n_elem64 == 0) return;
+  Ids a{{0, 0, 0}}, b{{0, 0, 0}}, c{{0, 0, 0}}, e{{0, 0, 0}};
+  for (int i = 0; i < nin; ++i) {
+    a.v[i] = in0[i];
+    if (ngroup > 1) b.v[i] = in1[i];
+  }
+  for (int i = 0; i < nout; ++i) {
+    c.v[i] = out0[i];
+    if (ngroup > 1) e.v[i] = out1[i];
+  }
+  ME_DISPATCH_KB(ts.kb, {
+    k_sl_combine<KB><<<ts.n_elem64, kBlock, 0, s>>>(sl, ts.elem64, nin, ngroup, a, b, nout, c, e,
+                                                    which, off, cert);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Deflation of the constant vector (slots with `deflate`): x <- x - mean(x)
+// per column.
+// ---------------------------------------------------------------------------
+
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_sl_colsum(const SlotDev* __restrict__ sl,
+                                                      const Tile* __restrict__ tiles, int blk,
+                                                      int cert) {
+  using E = ElemCfg<double, KB>;
+  constexpr int VEC = E::VEC, LPR = E::LPR;
+  __shared__ double sh[kBlock / kWave][KB];
+  const Tile t = tiles[blockIdx.x];
+  const SlotDev& d = sl[t.slot];
+  if (skip_slot(d, cert) || !d.deflate) return;
+  const int tid = threadIdx.x, sub = tid % LPR;
+  const int64_t r0 = (int64_t)t.blk * d.per;
+  const int64_t r1 = r0 + d.per < d.n ? r0 + d.per : d.n;
+  const double* x = d.b64[blk];
+  double acc[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) acc[v] = 0;
+  for (int64_t row = r0 + tid / LPR; row < r1; row += E::RB) {
+    const auto xv = ldv<double, VEC>(x + row * KB + sub * VEC);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] += xv.v[v];
+  }
+#pragma unroll
+  for (int v = 0; v < VEC; ++v)
+    for (int off = kWave / 2; off >= LPR; off >>= 1) acc[v] += __shfl_xor(acc[v], off);
+  const int lane = tid % kWave, wv = tid / kWave;
+  if (lane < LPR)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) sh[wv][lane * VEC + v] = acc[v];
+  __syncthreads();
+  if (tid < KB) {
+    double s = 0;
+    for (int q = 0; q < kBlock / kWave; ++q) s += sh[q][tid];
+    d.partials[(int64_t)t.blk * KB + tid] = s;
+  }
+}
+
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_sl_sub_mean(const SlotDev* __restrict__ sl,
+                                                        const Tile* __restrict__ tiles, int blk,
+                                                        int cert) {
+  using E = ElemCfg<double, KB>;
+  constexpr int VEC = E::VEC, LPR = E::LPR;
+  const Tile t = tiles[blockIdx.x];
+  const SlotDev& d = sl[t.slot];
+  if (skip_slot(d, cert) || !d.deflate) return;
+  const int64_t row = (int64_t)t.blk * E::RB + threadIdx.x / LPR;
+  const int sub = threadIdx.x % LPR;
+  if (row >= d.n) return;
+  double* p = d.b64[blk] + row * KB + sub * VEC;
+  auto xv = ldv<double, VEC>(p);
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) xv.v[v] -= d.sums[sub * VEC + v] / (double)d.n;
+  stv<double, VEC>(p, xv);
+}
+
+void sl_deflate(const SlotDev* sl, const TileSet& ts, int blk, int cert, hipStream_t s) {
+  if (ts.n_red == 0) return;
+  ME_DISPATCH_KB(ts.kb, {
+    k_sl_colsum<KB><<<ts.n_red, kBlock, 0, s>>>(sl, ts.red, blk, cert);
+    k_sl_reduce<<<dim3(1, ts.nslots), kBlock, 0, s>>>(sl, ts.slots, KB, 1, cert);
+    k_sl_sub_mean<KB><<<ts.n_elem64, kBlock, 0, s>>>(sl, ts.elem64, blk, cert);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// FP64 <-> FP32 copies of a block (mixed-precision preconditioner)
+// ---------------------------------------------------------------------------
+
+template <int KB, bool TO32>
+__global__ void __launch_bounds__(kBlock) k_sl_convert(const SlotDev* __restrict__ sl,
+                                                       const Tile* __restrict__ tiles, int b64,
+                                                       int b32) {
+  using E = ElemCfg<float, KB>;
+  constexpr int VEC = E::VEC, LPR = E::LPR;
+  const Tile t = tiles[blockIdx.x];
+  const SlotDev& d = sl[t.slot];
+  if (d.ctrl->done) return;
+  const int64_t row = (int64_t)t.blk * E::RB + threadIdx.x / LPR;
+  const int sub = threadIdx.x % LPR;
+  if (row >= d.n) return;
+  const int64_t o = row * KB + sub * VEC;
+  double* p64 = d.b64[b64] + o;
+  float* p32 = d.b32[b32] + o;
+  if (TO32) {
+    VecT<float, VEC> f;
+#pragma unroll
+    for (int h = 0; h < VEC / 2; ++h) {
+      const auto v = ldv<double, 2>(p64 + 2 * h);
+      f.v[2 * h] = (float)v.v[0];
+      f.v[2 * h + 1] = (float)v.v[1];
+    }
+    stv<float, VEC>(p32, f);
+  } else {
+    const auto f = ldv<float, VEC>(p32);
+#pragma unroll
+    for (int h = 0; h < VEC / 2; ++h) {
+      VecT<double, 2> v;
+      v.v[0] = (double)f.v[2 * h];
+      v.v[1] = (double)f.v[2 * h + 1];
+      stv<double, 2>(p64 + 2 * h, v);
+    }
+  }
+}
+
+void sl_to32(const SlotDev* sl, const TileSet& ts, int from64, int to32, hipStream_t s) {
+  if (ts.n_elem32 == 0) return;
+  ME_DISPATCH_KB(ts.kb, {
+    k_sl_convert<KB, true><<<ts.n_elem32, kBlock, 0, s>>>(sl, ts.elem32, from64, to32);
+  });
+}
+void sl_to64(const SlotDev* sl, const TileSet& ts, int from32, int to64, hipStream_t s) {
+  if (ts.n_elem32 == 0) return;
+  ME_DISPATCH_KB(ts.kb, {
+    k_sl_convert<KB, false><<<ts.n_elem32, kBlock, 0, s>>>(sl, ts.elem32, to64, from32);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Starting block: copies x0 (user order, n x kcopy) and fills the remaining
+// columns with a counter-based generator (SplitMix64 of seed and element
+// index, Steele, Lea & Flood 2014), uniform in [-1, 1).  Values depend only
+// on (seed, user row, column), not on the solver's node order.
+// ---------------------------------------------------------------------------
+
+__device__ inline uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_sl_fill_start(const SlotDev* __restrict__ sl,
+                                                          const Tile* __restrict__ tiles) {
+  using E = ElemCfg<double, KB>;
+  constexpr int VEC = E::VEC, LPR = E::LPR;
+  const Tile t = tiles[blockIdx.x];
+  const SlotDev& d = sl[t.slot];
+  const int64_t row = (int64_t)t.blk * E::RB + threadIdx.x / LPR;
+  const int sub = threadIdx.x % LPR;
+  if (row >= d.n) return;
+  const int64_t u = d.perm ? d.perm[row] : row;
+  VecT<double, VEC> v;
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) {
+    const int j = sub * VEC + q;
+    if (d.x0 && j < d.kcopy) {
+      v.v[q] = d.x0[u * d.kcopy + j];
+    } else {
+      const uint64_t h = splitmix64(d.seed * 0x2545F4914F6CDD1Dull + (uint64_t)(u * KB + j));
+      v.v[q] = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    }
+  }
+  stv<double, VEC>(d.b64[BX] + row * KB + sub * VEC, v);
+}
+
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_sl_zero(const SlotDev* __restrict__ sl,
+                                                    const Tile* __restrict__ tiles, int blk) {
+  using E = ElemCfg<double, KB>;
+  constexpr int VEC = E::VEC, LPR = E::LPR;
+  const Tile t = tiles[blockIdx.x];
+  const SlotDev& d = sl[t.slot];
+  const int64_t row = (int64_t)t.blk * E::RB + threadIdx.x / LPR;
+  const int sub = threadIdx.x % LPR;
+  if (row >= d.n) return;
+  VecT<double, VEC> v;
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) v.v[q] = 0.0;
+  stv<double, VEC>(d.b64[blk] + row * KB + sub * VEC, v);
+}
+
+void sl_fill_start(const SlotDev* sl, const TileSet& ts, hipStream_t s) {
+  if (ts.n_elem64 == 0) return;
+  ME_DISPATCH_KB(ts.kb, { k_sl_fill_start<KB><<<ts.n_elem64, kBlock, 0, s>>>(sl, ts.elem64); });
+}
+void sl_zero(const SlotDev* sl, const TileSet& ts, int blk, hipStream_t s) {
+  if (ts.n_elem64 == 0) return;
+  ME_DISPATCH_KB(ts.kb, { k_sl_zero<KB><<<ts.n_elem64, kBlock, 0, s>>>(sl, ts.elem64, blk); });
+}
+
+// ---------------------------------------------------------------------------
+// Per-slot bookkeeping
+// ---------------------------------------------------------------------------
+
+// ctrl->orth = max |G_ij - delta_ij| over i, j < need, G = X^T B X (gram)
+__global__ void __launch_bounds__(kWave) k_sl_orth(const SlotDev* __restrict__ sl,
+                                                   const int32_t* __restrict__ slots, int kb) {
+  const SlotDev& d = sl[slots[blockIdx.x]];
+  const int need = d.need;
+  double e = 0.0;
+  for (int u = threadIdx.x; u < need * need; u += kWave) {
+    const int i = u / need, j = u % need;
+    e = fmax(e, fabs(d.gram[i * kb + j] - (i == j ? 1.0 : 0.0)));
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) e = fmax(e, __shfl_xor(e, o));
+  if (threadIdx.x == 0) d.ctrl->orth = e;
+}
+
+void sl_orth(const SlotDev* sl, const TileSet& ts, hipStream_t s) {
+  if (ts.nslots == 0) return;
+  k_sl_orth<<<ts.nslots, kWave, 0, s>>>(sl, ts.slots, ts.kb);
+}
+
+__global__ void k_sl_reenter(const SlotDev* __restrict__ sl, const int32_t* __restrict__ slots) {
+  if (threadIdx.x == 0) sl[slots[blockIdx.x]].ctrl->done = 0;
+}
+
+void sl_reenter(const SlotDev* sl, const TileSet& ts, hipStream_t s) {
+  if (ts.nslots == 0) return;
+  k_sl_reenter<<<ts.nslots, kWave, 0, s>>>(sl, ts.slots);
+}
+
+// Output: sign convention (largest |x| of each column positive, lowest user
+// row on ties) and the copy of the first k_out columns in user order.
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_sl_col_argmax(const SlotDev* __restrict__ sl,
+                                                          const Tile* __restrict__ tiles) {
+  __shared__ double sv[kBlock];
+  __shared__ int64_t si[kBlock];
+  const Tile t = tiles[blockIdx.x];
+  const SlotDev& d = sl[t.slot];
+  const int64_t r0 = (int64_t)t.blk * d.per;
+  const int64_t r1 = r0 + d.per < d.n ? r0 + d.per : d.n;
+  const double* x = d.b64[BX];
+  double* pval = d.scratch;
+  int64_t* pidx = reinterpret_cast<int64_t*>(d.scratch + (int64_t)d.nparts * KB);
+  for (int j = 0; j < KB; ++j) {
+    double best = -1.0;
+    int64_t bi = INT64_MAX;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
+      const double a = fabs(x[i * KB + j]);
+      const int64_t u = d.perm ? d.perm[i] : i;
+      if (a > best || (a == best && u < bi)) {
+        best = a;
+        bi = u;
+      }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) {
+        const double ov = sv[threadIdx.x + st];
+        const int64_t oi = si[threadIdx.x + st];
+        if (ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+          sv[threadIdx.x] = ov;
+          si[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      pval[(int64_t)t.blk * KB + j] = sv[0];
+      pidx[(int64_t)t.blk * KB + j] = si[0];
+    }
+    __syncthreads();
+  }
+}
+
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_sl_signed_copy(const SlotDev* __restrict__ sl,
+                                                           const Tile* __restrict__ tiles) {
+  using E = ElemCfg<double, KB>;
+  constexpr int VEC = E::VEC, LPR = E::LPR;
+  __shared__ double sgn[KB];
+  const Tile t = tiles[blockIdx.x];
+  const SlotDev& d = sl[t.slot];
+  const double* x = d.b64[BX];
+  if (threadIdx.x < KB) {
+    const int j = threadIdx.x;
+    const double* pval = d.scratch;
+    const int64_t* pidx = reinterpret_cast<const int64_t*>(d.scratch + (int64_t)d.nparts * KB);
+    double best = -1.0;
+    int64_t bi = INT64_MAX;
+    for (int p = 0; p < d.nparts; ++p) {
+      const double v = pval[p * KB + j];
+      const int64_t ii = pidx[p * KB + j];
+      if (v > best || (v == best && ii < bi)) {
+        best = v;
+        bi = ii;
+      }
+    }
+    double val = 1.0;
+    if (bi < d.n) val = x[(d.iperm ? (int64_t)d.iperm[bi] : bi) * KB + j];
+    sgn[j] = val < 0.0 ? -1.0 : 1.0;
+    if (t.blk == 0 && j < d.k_out && d.out_lam) d.out_lam[j] = d.lam[j];
+  }
+  __syncthreads();
+  if (!d.out_x) return;
+  const int64_t u = (int64_t)t.blk * E::RB + threadIdx.x / LPR;
+  const int sub = threadIdx.x % LPR;
+  if (u >= d.n) return;
+  const int64_t i = d.iperm ? d.iperm[u] : u;
+  const auto v = ldv<double, VEC>(x + i * KB + sub * VEC);
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) {
+    const int j = sub * VEC + q;
+    if (j < d.k_out) d.out_x[u * d.k_out + j] = sgn[j] * v.v[q];
+  }
+}
+
+void sl_output(const SlotDev* sl, const TileSet& ts, hipStream_t s) {
+  if (ts.n_red == 0) return;
+  ME_DISPATCH_KB(ts.kb, {
+    k_sl_col_argmax<KB><<<ts.n_red, kBlock, 0, s>>>(sl, ts.red);
+    k_sl_signed_copy<KB><<<ts.n_elem64, kBlock, 0, s>>>(sl, ts.elem64);
+  });
+}
+
+}  // namespace me

@@ -1,5 +1,8 @@
 // Diagnostic kernel timing: HIP events recorded around the launches of one
 // kernel kind on the stream that launches them, summed when a solve ends.
+// A run of back-to-back launches of the kind is bracketed by one event pair
+// (an event record between two kernels costs several microseconds of GPU
+// time, so per-launch pairs would distort what they measure).
 // Launches that found the solve already converged (early exit) are dropped
 // so that the totals cover only launches that did the work.
 #include <mutex>
@@ -13,7 +16,7 @@ namespace {
 struct Pending {
   hipEvent_t a, b;
   double bytes;
-  int phase, tag;
+  int phase, tag, launches;
 };
 struct KTimer {
   std::mutex mu;
@@ -47,7 +50,8 @@ int ktimer_new_phase() {
   return ++kt().phase;
 }
 
-KScope::KScope(int kind, hipStream_t s, double bytes, int tag) : on(false), s_(s) {
+KScope::KScope(int kind, hipStream_t s, double bytes, int tag, int launches)
+    : on(false), s_(s) {
   KTimer& t = kt();
   if (t.kind == 0 || kind != t.kind) return;
   std::lock_guard<std::mutex> l(t.mu);
@@ -57,6 +61,7 @@ KScope::KScope(int kind, hipStream_t s, double bytes, int tag) : on(false), s_(s
   on = true;
   bytes_ = bytes;
   tag_ = tag;
+  launches_ = launches;
   phase_ = t.phase;
   (void)hipEventRecord(a_, s_);
 }
@@ -66,7 +71,7 @@ KScope::~KScope() {
   (void)hipEventRecord(b_, s_);
   KTimer& t = kt();
   std::lock_guard<std::mutex> l(t.mu);
-  t.pending.push_back({a_, b_, bytes_, phase_, tag_});
+  t.pending.push_back({a_, b_, bytes_, phase_, tag_, launches_});
 }
 
 // Launches of `phase` with tag > last_real did no work (early exit).
@@ -94,7 +99,7 @@ void ktimer_collect() {
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       t.ms += ms;
       t.bytes += p.bytes;
-      t.launches += 1;
+      t.launches += p.launches;
     }
     t.pool.push_back(p.a);
     t.pool.push_back(p.b);

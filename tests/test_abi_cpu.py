@@ -45,6 +45,22 @@ def test_host_only_entry_points():
     assert lib.me_graph_ops_bytes(None) == 0
 
 
+def test_invalid_options_rejected_before_device_work():
+    """Option checks run on the host before any device call."""
+    from paper_2112_07862_amd import _lib
+    lib = _lib.load()
+    W = _lib.MeCsr()
+    h = ctypes.c_void_p()
+    for field, val in [("cheb_degree", 1), ("cheb_degree", 257), ("precond", 3),
+                       ("precision", 2), ("max_iter", 0), ("check_every", 0),
+                       ("eps_tol", 0.0)]:
+        o = _lib.MeOpts()
+        lib.me_opts_default(ctypes.byref(o))
+        setattr(o, field, val)
+        st = lib.me_build_graph_ops(ctypes.byref(W), ctypes.byref(o), None, ctypes.byref(h), None)
+        assert _lib.STATUS_NAMES[st] == "ME_ERR_INVALID_ARG", (field, val, st)
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     from paper_2112_07862_amd import _lib
     monkeypatch.setattr(_lib, "_lib", None)

@@ -214,7 +214,7 @@ def test_k_range_errors(me):
 
 @pytest.mark.parametrize("name,K", [("square_2k", 4), ("sphere_3k", 16), ("torus_2500", 8)])
 @pytest.mark.parametrize("precond,deg", [("none", None), ("jacobi", None), ("chebyshev", 8),
-                                         ("chebyshev", 48)])
+                                         ("chebyshev", 48), ("chebyshev", 256)])
 def test_embed_preconditioners(me, name, K, precond, deg):
     """Every preconditioner reaches the same pairs (the converged result
     does not depend on the preconditioner)."""
