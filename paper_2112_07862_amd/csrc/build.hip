@@ -370,40 +370,98 @@ __global__ void k_uf_count_roots(int64_t n, int32_t* parent, int* roots) {
 // level, so the permutation is deterministic.
 // ---------------------------------------------------------------------------
 
-__global__ void k_fill_i32(int64_t n, int32_t* a, int32_t v) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) a[i] = v;
-}
 
-__global__ void k_bfs_seed(int32_t* level, int32_t* frontier, int32_t* counts, int32_t node,
-                           int32_t lev) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    level[node] = lev;
-    frontier[0] = node;
-    counts[lev] = 1;
+// Breadth-first levels in one workgroup: all levels (and, in mode 1, all
+// remaining components) in one launch, frontier counters in LDS.
+//   mode 0: BFS from node 0 over its component; *out = lowest node on the
+//           last level (the pseudo-peripheral start).
+//   mode 1: level[] reset, BFS from *out, then from the lowest unvisited node
+//           of each further component (levels continue across components);
+//           *out = the last level used.
+// The level of a node is its breadth-first distance, which does not depend
+// on the order in which a level's frontier was built.
+constexpr int kBfsThreads = 1024;
+
+__device__ __forceinline__ int32_t bfs_from(const int64_t* __restrict__ rp,
+                                            const int32_t* __restrict__ col, int32_t* level,
+                                            int32_t* fa, int32_t* fb, int32_t start, int32_t lev0,
+                                            int32_t* s_cnt) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    level[start] = lev0;
+    fa[0] = start;
+    s_cnt[0] = 1;
   }
-}
-
-// One level: every node of frontier `fin` (counts[lev] of them) claims its
-// unvisited neighbours for level lev + 1 and appends them to `fout`.
-__global__ void k_bfs_level(const int64_t* rp, const int32_t* col, int32_t* level,
-                            const int32_t* fin, int32_t* fout, int32_t* counts, int32_t lev) {
-  const int32_t nin = counts[lev];
-  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nin; i += gridDim.x * blockDim.x) {
-    const int32_t u = fin[i];
-    for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
-      const int32_t v = col[t];
-      if (__atomic_load_n(&level[v], __ATOMIC_RELAXED) < 0 && atomicCAS(&level[v], -1, lev + 1) == -1)
-        fout[atomicAdd(&counts[lev + 1], 1)] = v;
+  __syncthreads();
+  int32_t lev = lev0;
+  int32_t* fin = fa;
+  int32_t* fout = fb;
+  for (;;) {
+    const int32_t nin = s_cnt[0];
+    if (tid == 0) s_cnt[1] = 0;
+    __syncthreads();
+    for (int32_t i = tid; i < nin; i += kBfsThreads) {
+      const int32_t u = fin[i];
+      for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
+        const int32_t v = col[t];
+        if (__atomic_load_n(&level[v], __ATOMIC_RELAXED) < 0 &&
+            atomicCAS(&level[v], -1, lev + 1) == -1)
+          fout[atomicAdd(&s_cnt[1], 1)] = v;
+      }
     }
+    __syncthreads();
+    const int32_t nout = s_cnt[1];
+    if (nout == 0) break;
+    if (tid == 0) s_cnt[0] = nout;
+    int32_t* t = fin;
+    fin = fout;
+    fout = t;
+    ++lev;
+    __syncthreads();
   }
+  return lev;
 }
 
-// lowest node id with level == lev (lev = -1: lowest unvisited node)
-__global__ void k_min_node_at(int64_t n, const int32_t* level, int32_t lev, int32_t* out) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n && level[i] == lev) atomicMin(out, (int32_t)i);
+__global__ void __launch_bounds__(kBfsThreads) k_bfs_block(int64_t n, const int64_t* rp,
+                                                           const int32_t* col, int32_t* level,
+                                                           int32_t* fa, int32_t* fb, int mode,
+                                                           int32_t* out) {
+  __shared__ int32_t s_cnt[2];
+  __shared__ int32_t s_min;
+  const int tid = threadIdx.x;
+  for (int64_t i = tid; i < n; i += kBfsThreads) level[i] = -1;
+  __syncthreads();
+  if (mode == 0) {
+    const int32_t last = bfs_from(rp, col, level, fa, fb, 0, 0, s_cnt);
+    if (tid == 0) s_min = INT32_MAX;
+    __syncthreads();
+    for (int64_t i = tid; i < n; i += kBfsThreads)
+      if (level[i] == last) atomicMin(&s_min, (int32_t)i);
+    __syncthreads();
+    if (tid == 0) *out = s_min;
+    return;
+  }
+  int32_t last = bfs_from(rp, col, level, fa, fb, *out, 0, s_cnt);
+  // further components: the lowest unvisited node only grows
+  int64_t ptr = 0;
+  for (;;) {
+    if (tid == 0) s_min = INT32_MAX;
+    __syncthreads();
+    for (; ptr < n; ptr += kBfsThreads) {
+      const int64_t i = ptr + tid;
+      if (i < n && level[i] < 0) atomicMin(&s_min, (int32_t)i);
+      __syncthreads();
+      if (s_min != INT32_MAX) break;
+      __syncthreads();
+    }
+    const int32_t nxt = s_min;
+    __syncthreads();
+    if (nxt == INT32_MAX) break;
+    last = bfs_from(rp, col, level, fa, fb, nxt, last + 1, s_cnt);
+  }
+  if (tid == 0) *out = last;
 }
+
 
 // --- stable LSD radix sort of (key, value) int32 pairs, 8-bit digits ------
 constexpr int kRsThreads = 256;
@@ -476,38 +534,6 @@ __global__ void k_invert_perm(int64_t n, const int32_t* perm, int32_t* iperm) {
   if (i < n) iperm[perm[i]] = (int32_t)i;
 }
 
-// BFS from `start` (levels from lev0) over the component; returns the last
-// non-empty level.
-static int bfs_component(const GraphOps* g, int32_t* level, int32_t* fa, int32_t* fb,
-                         int32_t* counts, int32_t start, int32_t lev0, int32_t* host_counts,
-                         hipStream_t s, int* last) {
-  constexpr int kChunk = 32;
-  k_bfs_seed<<<1, 1, 0, s>>>(level, fa, counts, start, lev0);
-  const int grid = 512;
-  for (int32_t l0 = lev0;; l0 += kChunk) {
-    for (int32_t l = l0; l < l0 + kChunk; ++l) {
-      if (l + 1 > g->n) break;
-      const bool even = ((l - lev0) & 1) == 0;
-      k_bfs_level<<<grid, 256, 0, s>>>(g->w_rp, g->w_col, level, even ? fa : fb, even ? fb : fa,
-                                       counts, l);
-    }
-    const int64_t hi = std::min<int64_t>(l0 + kChunk, g->n);
-    const int cnt = (int)(hi - l0 + 1);
-    ME_TRY(hipMemcpyAsync(host_counts, counts + l0, cnt * 4, hipMemcpyDeviceToHost, s));
-    ME_TRY(hipStreamSynchronize(s));
-    for (int j = 1; j < cnt; ++j) {
-      if (host_counts[j] == 0) {
-        *last = l0 + j - 1;
-        return ME_OK;
-      }
-    }
-    if (hi >= g->n) {
-      *last = (int)g->n - 1;
-      return ME_OK;
-    }
-  }
-}
-
 // perm (solver index -> user index), iperm (user -> solver).
 static int locality_order(GraphOps* g, int32_t* perm, int32_t* iperm, hipStream_t s) {
   const int64_t n = g->n;
@@ -517,7 +543,7 @@ static int locality_order(GraphOps* g, int32_t* perm, int32_t* iperm, hipStream_
     return ME_OK;
   }
   const int64_t nblk = ceil_div(n, kRsItems);
-  const size_t bytes = Arena::round((n + 2) * 4) * 7 + Arena::round(256 * nblk * 4) +
+  const size_t bytes = Arena::round((n + 2) * 4) * 6 + Arena::round(256 * nblk * 4) +
                        Arena::round(256 * nblk * 8 + 8) + Arena::round((256 * nblk / kScanTile + 2) * 8) +
                        Arena::round(64);
   void* mem = nullptr;
@@ -526,7 +552,6 @@ static int locality_order(GraphOps* g, int32_t* perm, int32_t* iperm, hipStream_
   int32_t* level = a.take<int32_t>(n + 2);
   int32_t* fa = a.take<int32_t>(n + 2);
   int32_t* fb = a.take<int32_t>(n + 2);
-  int32_t* counts = a.take<int32_t>(n + 2);
   int32_t* k2 = a.take<int32_t>(n + 2);
   int32_t* v1 = a.take<int32_t>(n + 2);
   int32_t* v2 = a.take<int32_t>(n + 2);
@@ -534,37 +559,14 @@ static int locality_order(GraphOps* g, int32_t* perm, int32_t* iperm, hipStream_
   int64_t* off = a.take<int64_t>(256 * nblk + 1);
   int64_t* tiles = a.take<int64_t>(256 * nblk / kScanTile + 2);
   int32_t* minv = a.take<int32_t>(16);
-  std::vector<int32_t> hc(40);
   int st = ME_OK;
-  auto reset = [&]() -> int {
-    k_fill_i32<<<ceil_div(n + 2, kBlock), kBlock, 0, s>>>(n + 2, level, -1);
-    k_fill_i32<<<ceil_div(n + 2, kBlock), kBlock, 0, s>>>(n + 2, counts, 0);
-    return ME_OK;
-  };
-  auto min_at = [&](int32_t lev, int32_t* out) -> int {
-    k_fill_i32<<<1, 1, 0, s>>>(1, minv, INT32_MAX);
-    k_min_node_at<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, level, lev, minv);
-    ME_TRY(hipMemcpyAsync(out, minv, 4, hipMemcpyDeviceToHost, s));
-    ME_TRY(hipStreamSynchronize(s));
-    return ME_OK;
-  };
-  // pseudo-peripheral start: search from node 0, restart from its last level
-  reset();
-  int last = 0;
-  st = bfs_component(g, level, fa, fb, counts, 0, 0, hc.data(), s, &last);
-  int32_t start = 0;
-  if (st >= 0) st = min_at(last, &start);
-  if (st >= 0) {
-    reset();
-    st = bfs_component(g, level, fa, fb, counts, start, 0, hc.data(), s, &last);
-  }
-  // remaining components, lowest unvisited node first
-  while (st >= 0) {
-    int32_t nxt = INT32_MAX;
-    st = min_at(-1, &nxt);
-    if (st < 0 || nxt == INT32_MAX) break;
-    st = bfs_component(g, level, fa, fb, counts, nxt, last + 1, hc.data(), s, &last);
-  }
+  // pseudo-peripheral start (search from node 0, lowest node on its last
+  // level), then the levels from there and from each further component
+  k_bfs_block<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb, 0, minv);
+  k_bfs_block<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb, 1, minv);
+  int32_t last = 0;
+  ME_TRY(hipMemcpyAsync(&last, minv, 4, hipMemcpyDeviceToHost, s));
+  ME_TRY(hipStreamSynchronize(s));
   if (st >= 0) {
     // stable sort of node ids by level
     k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, v1);

@@ -215,6 +215,10 @@ class Engine {
   Ctrl* h_ctrl_ = nullptr;  // pinned mirror
   std::vector<int> active_;
   std::vector<TileSet> sets_;  // work lists of active_, one per block width
+  // convergence history per slot (largest required rho at the last check)
+  std::vector<double> rho_prev_;
+  std::vector<int> it_prev_;
+  int round_length();
   bool sets_dirty_ = true;
   size_t bytes_in_use_ = 0;
   int phase_ = 0, tag_ = 0;

@@ -66,6 +66,8 @@ Engine::Engine(hipStream_t s, const me_opts& o, int capacity, bool timed)
 int Engine::init() {
   sh_.assign(cap_, SlotHost());
   res_.assign(cap_, SlotResult());
+  rho_prev_.assign(cap_, 0.0);
+  it_prev_.assign(cap_, -1);
   hdev_.assign(cap_, SlotDev());
   ME_TRY(hipMallocAsync((void**)&d_slots_, sizeof(SlotDev) * cap_, s_));
   ME_TRY(hipMallocAsync((void**)&d_ctrl_, sizeof(Ctrl) * cap_, s_));
@@ -127,6 +129,7 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
   h.sp = sp;
   bytes_in_use_ += need;
   res_[id] = SlotResult();
+  it_prev_[id] = -1;
 
   SlotDev d{};
   Arena a{(char*)ws, need, 0};
@@ -447,6 +450,27 @@ int Engine::certify(const std::vector<int>& ids, std::vector<int>* finished) {
   return ME_OK;
 }
 
+// Iterations to enqueue before the next check: check_every, shortened to
+// the fewest iterations any active slot still needs by the linear
+// convergence rate of its largest required rho over the last round (so that
+// few iterations are enqueued after the first slot has stopped).
+int Engine::round_length() {
+  const int ce = o_.check_every > 0 ? o_.check_every : 16;
+  double best = 1e300;
+  for (int id : active_) {
+    const Ctrl& c = h_ctrl_[id];
+    double rho = 0.0;
+    for (int j = 0; j < sh_[id].sp.need; ++j) rho = std::max(rho, c.rho[j]);
+    if (it_prev_[id] >= 0 && c.iter > it_prev_[id] && rho > 0.0 && rho < rho_prev_[id]) {
+      const double rate = std::log(rho_prev_[id] / rho) / (double)(c.iter - it_prev_[id]);
+      const double rem = rho > sh_[id].sp.tol ? std::log(rho / sh_[id].sp.tol) / rate : 0.0;
+      best = std::min(best, rem);
+    }
+  }
+  if (best >= 1e300) return ce;
+  return (int)std::max(1.0, std::min((double)ce, std::ceil(best) + 1.0));
+}
+
 int Engine::step(std::vector<int>* finished) {
   // start the slots added since the last round
   std::vector<int> fresh;
@@ -476,7 +500,14 @@ int Engine::step(std::vector<int>* finished) {
   for (size_t q = 0; q < active_.size(); ++q) iter0[q] = h_ctrl_[active_[q]].iter;
   if (timed_) phase_ = ktimer_new_phase();
   tag_ = 0;
-  const int ce = o_.check_every > 0 ? o_.check_every : 16;
+  const int ce = round_length();
+  for (size_t q = 0; q < active_.size(); ++q) {
+    const int id = active_[q];
+    double rho = 0.0;
+    for (int j = 0; j < sh_[id].sp.need; ++j) rho = std::max(rho, h_ctrl_[id].rho[j]);
+    rho_prev_[id] = rho;
+    it_prev_[id] = iter0[q] > 0 ? iter0[q] : -1;
+  }
   for (int q = 0; q < ce; ++q)
     for (auto& ts : sets_) iteration(ts);
   ME_TRY_STATUS(read_ctrl());
