@@ -201,6 +201,47 @@ int me_embed(const me_graph_ops* ops, int K, double tol, const me_opts* opts,
 int me_embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opts* opts,
                    double* const* Xs, double* const* lambdas, me_info* infos, void* stream);
 
+/* ---- Serving: continuous batching of independent requests ---------------
+ * A server owns one LOBPCG engine on `stream`.  Each request is a graph and
+ * K; requests wait in a FIFO queue until their estimated device footprint
+ * (operators plus solver state) fits `mem_budget` next to the admitted ones
+ * and fewer than `max_active` are admitted.  An admitted request is built on
+ * a second stream of the server (default priority) while the engine's
+ * current round runs, solves eps = lambda_2(Q) and then its embedding as
+ * engine slots beside all other admitted requests, and is retired when its
+ * embedding is certified; its memory then admits the next request.  A
+ * request's result does not depend on the other requests (its arithmetic is
+ * that of a batch of one).  One host thread drives a server. */
+typedef struct me_server me_server;
+typedef struct {
+  size_t mem_budget; /* device bytes for admitted requests; 0 = 60% of free memory at creation */
+  int max_active;    /* requests admitted at once, >= 1 (default 256)                  */
+  me_opts opts;      /* solver options of every request                               */
+} me_server_opts;
+
+void me_server_opts_default(me_server_opts* so);
+/* Creates a server; `so` host, may be NULL (defaults). */
+int me_server_create(const me_server_opts* so, void* stream, me_server** out);
+/* Queues a request (no GPU work).  W: host struct of device pointers that
+ * must stay valid until the request completes; X (n x K) and lambda (K):
+ * device outputs, written when the request completes; K 1..16, tol > 0.
+ * *ticket receives the request's id (0, 1, 2, ... in submission order). */
+int me_server_submit(me_server* s, const me_csr* W, int K, double tol, double* X,
+                     double* lambda, int64_t* ticket);
+/* One round: enqueues one batch of LOBPCG iterations for every active
+ * solve, admits and builds queued requests while those run, then certifies,
+ * retires and backfills.  *in_flight (may be NULL) = requests queued or
+ * running.  Returns an error only for a failure of the server itself; a
+ * request's own failure is reported by me_server_poll. */
+int me_server_step(me_server* s, int* in_flight);
+/* Completed requests since the last poll, oldest first: up to `max` tickets
+ * and me_info (status, iterations, eps, mu, max_residual, orth_error,
+ * ms_build = admission to operators ready, ms_solve = operators ready to
+ * completion; host arrays, may be NULL).  *count = entries written. */
+int me_server_poll(me_server* s, int64_t* tickets, me_info* infos, int max, int* count);
+/* Releases the server and every request it still holds. */
+void me_server_destroy(me_server* s);
+
 /* Kernel timing (diagnostic).  me_kernel_timing(kind) starts timing every
  * launch of one kernel kind with HIP events recorded on the launching stream
  * (kind 0 = off, 1 = SpMM of A on the embedding block, 2 = Rayleigh-Ritz

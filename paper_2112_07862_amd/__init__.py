@@ -5,5 +5,5 @@ in hand-written HIP kernels behind the C ABI of include/membed.h."""
 from ._lib import LIB_PATH, load  # noqa: F401
 from .api import (  # noqa: F401
     DeviceCSR, GraphOps, MembedError, build_graph_ops, embed, embed_batch, kernel_timing,
-    kernel_timing_read, make_opts, to_device,
+    kernel_timing_read, make_opts, Server, to_device,
 )

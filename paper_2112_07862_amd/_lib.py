@@ -46,6 +46,10 @@ class MeInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class MeServerOpts(ctypes.Structure):
+    _fields_ = [("mem_budget", c_size_t), ("max_active", c_int), ("opts", MeOpts)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "me_opts_default": (None, [ctypes.POINTER(MeOpts)]),
@@ -67,6 +71,15 @@ SIGNATURES = {
                                ctypes.POINTER(MeOpts), ctypes.POINTER(c_void_p),
                                ctypes.POINTER(c_void_p), ctypes.POINTER(MeInfo), c_void_p]),
     "me_graph_ops_destroy": (None, [c_void_p]),
+    "me_server_opts_default": (None, [ctypes.POINTER(MeServerOpts)]),
+    "me_server_create": (c_int, [ctypes.POINTER(MeServerOpts), c_void_p,
+                                 ctypes.POINTER(c_void_p)]),
+    "me_server_submit": (c_int, [c_void_p, ctypes.POINTER(MeCsr), c_int, c_double, c_void_p,
+                                 c_void_p, ctypes.POINTER(c_int64)]),
+    "me_server_step": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
+    "me_server_poll": (c_int, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(MeInfo), c_int,
+                               ctypes.POINTER(c_int)]),
+    "me_server_destroy": (None, [c_void_p]),
     "me_kernel_timing": (c_int, [c_int]),
     "me_kernel_timing_read": (c_int, [ctypes.POINTER(c_int64), ctypes.POINTER(c_double),
                                       ctypes.POINTER(c_double)]),

@@ -247,6 +247,69 @@ def embed_batch(graphs, Ks, tol: float = 1e-6, stream=None, **opts):
     return out
 
 
+class Server:
+    """Continuous-batching request loop (me_server_*): submit graphs at any
+    time, call step() to advance every admitted solve by one round (and admit,
+    retire and backfill), poll() for finished requests."""
+
+    def __init__(self, mem_budget: int = 0, max_active: int = 256, stream=None, **opts):
+        lib = L.load()
+        so = L.MeServerOpts()
+        lib.me_server_opts_default(ctypes.byref(so))
+        so.mem_budget = int(mem_budget)
+        so.max_active = int(max_active)
+        so.opts = make_opts(**opts)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(lib.me_server_create(ctypes.byref(so), _stream_ptr(stream), ctypes.byref(h)),
+               "server_create")
+        self._h = h
+        self._pending = {}  # ticket -> (csr, W struct, X, lam, K)
+
+    def submit(self, csr, K: int, tol: float = 1e-6) -> int:
+        d = to_device(csr)
+        X = torch.empty((d.n, int(K)), dtype=torch.float64, device=d.rowptr.device)
+        lam = torch.empty(int(K), dtype=torch.float64, device=d.rowptr.device)
+        W = d.as_struct()
+        t = ctypes.c_int64()
+        _check(L.load().me_server_submit(self._h, ctypes.byref(W), int(K), float(tol), _ptr(X),
+                                         _ptr(lam), ctypes.byref(t)), "server_submit")
+        self._pending[t.value] = (d, W, X, lam)
+        return t.value
+
+    def step(self) -> int:
+        n = ctypes.c_int()
+        _check(L.load().me_server_step(self._h, ctypes.byref(n)), "server_step")
+        return n.value
+
+    def poll(self, max_items: int = 1024):
+        """Finished requests: list of (ticket, X, lambda, info); X, lambda are
+        None for a failed request (info["status"] < 0)."""
+        t = (ctypes.c_int64 * max_items)()
+        inf = (L.MeInfo * max_items)()
+        c = ctypes.c_int()
+        _check(L.load().me_server_poll(self._h, t, inf, max_items, ctypes.byref(c)), "server_poll")
+        out = []
+        for q in range(c.value):
+            d = inf[q].as_dict()
+            d["status_name"] = L.STATUS_NAMES.get(d["status"], str(d["status"]))
+            _, _, X, lam = self._pending.pop(t[q])
+            out.append((t[q], X if d["status"] >= 0 else None, lam if d["status"] >= 0 else None, d))
+        return out
+
+    def close(self):
+        if self._h is not None:
+            L.load().me_server_destroy(self._h)
+            self._h = None
+            self._pending.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def kernel_timing(kind: int) -> None:
     """Start timing one kernel kind (0 off, 1 SpMM of A, 2 Rayleigh-Ritz Gram,
     3 block combine, 4 Chebyshev preconditioner step); clears the totals."""

@@ -172,6 +172,9 @@ class Engine {
   // ones, certification and output of those that stopped; appends the ids
   // that finished in this round.
   int step(std::vector<int>* finished);
+  // step() in two halves, so that host work can overlap the round on the GPU
+  int begin_round();
+  int end_round(std::vector<int>* finished);
   bool idle() const;
   int active() const;
   const SlotResult& result(int id) const { return res_[id]; }
@@ -218,6 +221,8 @@ class Engine {
   // convergence history per slot (largest required rho at the last check)
   std::vector<double> rho_prev_;
   std::vector<int> it_prev_;
+  std::vector<int> iter0_;
+  bool round_open_ = false;
   int round_length();
   bool sets_dirty_ = true;
   size_t bytes_in_use_ = 0;

@@ -320,9 +320,12 @@ void Engine::iteration(const TileSet& ts) {
     if (tm) {
       for (int id : ts.ids) {
         const GraphOps& g = *sh_[id].sp.g;
+        // algorithmic bytes of one step: column index of every entry, weight
+        // of every W entry, row bounds (8 B), 1/T_i and D^-1_i per row, and
+        // the block y_in (neighbour rows counted once), R, dd in, dd out, y_out
         const double sz = cheb32_ ? 4.0 : 8.0;
         cb += 4.0 * (double)(g.nnz_w + g.nnz_t) + sz * (double)g.nnz_w +
-              (double)g.n * (8.0 + sz) + 6.0 * (double)g.n * kb * sz;
+              (double)g.n * (8.0 + 2.0 * sz) + 5.0 * (double)g.n * kb * sz;
       }
     }
     const int w = cheb32_ ? BW32 : BW, y = cheb32_ ? BY32 : BY, dd = cheb32_ ? BDD32 : BDD;
@@ -358,6 +361,7 @@ void Engine::iteration(const TileSet& ts) {
   if (tm) {
     for (int id : ts.ids) {
       const GraphOps& g = *sh_[id].sp.g;
+      // column index of every entry, W weights, row bounds, 1/T_i, x in, y out
       sb += 4.0 * (double)(g.nnz_w + g.nnz_t) + 8.0 * (double)g.nnz_w + (double)g.n * 16.0 +
             2.0 * (double)g.n * kb * 8.0;
       blk += (double)g.n * kb * 8.0;
@@ -471,8 +475,10 @@ int Engine::round_length() {
   return (int)std::max(1.0, std::min((double)ce, std::ceil(best) + 1.0));
 }
 
-int Engine::step(std::vector<int>* finished) {
-  // start the slots added since the last round
+// Starts the slots added since the last round, then enqueues one round of
+// iterations of every active slot (returns without waiting for them).
+int Engine::begin_round() {
+  round_open_ = false;
   std::vector<int> fresh;
   for (int id = 0; id < cap_; ++id)
     if (sh_[id].used && !sh_[id].started) fresh.push_back(id);
@@ -496,8 +502,8 @@ int Engine::step(std::vector<int>* finished) {
     ME_TRY_STATUS(sets_for(active_, &sets_));
     sets_dirty_ = false;
   }
-  std::vector<int> iter0(active_.size());
-  for (size_t q = 0; q < active_.size(); ++q) iter0[q] = h_ctrl_[active_[q]].iter;
+  iter0_.resize(active_.size());
+  for (size_t q = 0; q < active_.size(); ++q) iter0_[q] = h_ctrl_[active_[q]].iter;
   if (timed_) phase_ = ktimer_new_phase();
   tag_ = 0;
   const int ce = round_length();
@@ -506,16 +512,25 @@ int Engine::step(std::vector<int>* finished) {
     double rho = 0.0;
     for (int j = 0; j < sh_[id].sp.need; ++j) rho = std::max(rho, h_ctrl_[id].rho[j]);
     rho_prev_[id] = rho;
-    it_prev_[id] = iter0[q] > 0 ? iter0[q] : -1;
+    it_prev_[id] = iter0_[q] > 0 ? iter0_[q] : -1;
   }
   for (int q = 0; q < ce; ++q)
     for (auto& ts : sets_) iteration(ts);
+  round_open_ = true;
+  return ME_OK;
+}
+
+// Waits for the round, then certifies the slots that stopped; appends the
+// ids that finished.
+int Engine::end_round(std::vector<int>* finished) {
+  if (!round_open_) return ME_OK;
+  round_open_ = false;
   ME_TRY_STATUS(read_ctrl());
   int adv = 0;
   std::vector<int> stopped;
   for (size_t q = 0; q < active_.size(); ++q) {
     const int id = active_[q];
-    adv = std::max(adv, h_ctrl_[id].iter - iter0[q]);
+    adv = std::max(adv, h_ctrl_[id].iter - iter0_[q]);
     if (h_ctrl_[id].done) stopped.push_back(id);
   }
   // launches of the round after every slot had stopped did no work
@@ -531,6 +546,11 @@ int Engine::step(std::vector<int>* finished) {
     }
   }
   return ME_OK;
+}
+
+int Engine::step(std::vector<int>* finished) {
+  ME_TRY_STATUS(begin_round());
+  return end_round(finished);
 }
 
 int Engine::run() {

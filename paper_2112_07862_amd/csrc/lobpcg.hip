@@ -14,7 +14,7 @@
 
 namespace me {
 
-static SlotSpec eps_spec(const GraphOps& g, const me_opts* o) {
+SlotSpec eps_slot_spec(const GraphOps& g, const me_opts* o) {
   SlotSpec sp;
   sp.g = &g;
   sp.op = OP_Q;
@@ -29,8 +29,8 @@ static SlotSpec eps_spec(const GraphOps& g, const me_opts* o) {
   return sp;
 }
 
-static SlotSpec embed_spec(const GraphOps& g, int K, double tol, const me_opts* o,
-                           const double* x0, double* X, double* lambda) {
+SlotSpec embed_slot_spec(const GraphOps& g, int K, double tol, const me_opts* o,
+                         const double* x0, double* X, double* lambda) {
   SlotSpec sp;
   sp.g = &g;
   sp.op = OP_A;
@@ -50,7 +50,7 @@ static SlotSpec embed_spec(const GraphOps& g, int K, double tol, const me_opts* 
   return sp;
 }
 
-static int dense_eps(const GraphOps& g, hipStream_t s, double* eps) {
+int dense_eps_solve(const GraphOps& g, hipStream_t s, double* eps) {
   const int64_t n = g.n;
   double* buf = nullptr;
   const size_t nn = (size_t)n * n;
@@ -67,11 +67,11 @@ static int dense_eps(const GraphOps& g, hipStream_t s, double* eps) {
 
 int solve_eps(GraphOps& g, const me_opts* o, hipStream_t s, double* eps, int* iters) {
   *iters = 0;
-  if (g.n <= kDenseMaxN) return dense_eps(g, s, eps);
+  if (g.n <= kDenseMaxN) return dense_eps_solve(g, s, eps);
   Engine e(s, *o, 1, false);
   ME_TRY_STATUS(e.init());
   int id = -1;
-  ME_TRY_STATUS(e.add(eps_spec(g, o), nullptr, 0, &id));
+  ME_TRY_STATUS(e.add(eps_slot_spec(g, o), nullptr, 0, &id));
   ME_TRY_STATUS(e.run());
   const SlotResult& r = e.result(id);
   *iters = r.iterations;
@@ -90,15 +90,15 @@ size_t embed_workspace_bytes(const GraphOps& g, int K, const me_opts* o) {
   return Engine::slot_bytes(g.n, block_width(K));
 }
 
-static int check_k(const GraphOps& g, int K) {
+int check_k_range(const GraphOps& g, int K) {
   if (K < 1 || K > kMaxBlockCols || K > g.n) return ME_ERR_K_RANGE;
   if (g.n > kDenseMaxN && 3 * block_width(K) > g.n) return ME_ERR_K_RANGE;
   return ME_OK;
 }
 
 // Dense solve of (A, B) for graphs with n <= kDenseMaxN (buf: 3 n^2 + n + 2048 doubles).
-static int dense_embed(const GraphOps& g, int K, double* buf, double* X, double* lambda,
-                       hipStream_t s) {
+int dense_embed_solve(const GraphOps& g, int K, double* buf, double* X, double* lambda,
+                      hipStream_t s) {
   const int64_t n = g.n;
   const size_t nn = (size_t)n * n;
   launch_dense_ops(g, 0, buf, buf + nn, s);
@@ -126,7 +126,7 @@ static void fill_info(me_info* info, const GraphOps& g, int st, int iters, int k
 int embed(const GraphOps& g, int K, double tol, const me_opts* o, const double* x0, void* ws,
           size_t ws_bytes, double* X, double* lambda, me_info* info, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
-  ME_TRY_STATUS(check_k(g, K));
+  ME_TRY_STATUS(check_k_range(g, K));
   if (!X || !lambda || !(tol > 0.0)) return ME_ERR_INVALID_ARG;
   const size_t need_bytes = embed_workspace_bytes(g, K, o);
   if (ws && ws_bytes < need_bytes) return ME_ERR_WORKSPACE;
@@ -138,7 +138,7 @@ int embed(const GraphOps& g, int K, double tol, const me_opts* o, const double* 
       ME_TRY(hipMallocAsync(&ws, need_bytes, s));
       own = true;
     }
-    dense_embed(g, K, (double*)ws, X, lambda, s);
+    dense_embed_solve(g, K, (double*)ws, X, lambda, s);
     if (own) ME_TRY(hipFreeAsync(ws, s));
     ME_TRY(hipStreamSynchronize(s));
     kb = (int)g.n;
@@ -147,7 +147,7 @@ int embed(const GraphOps& g, int K, double tol, const me_opts* o, const double* 
     Engine e(s, *o, 1, true);
     ME_TRY_STATUS(e.init());
     int id = -1;
-    ME_TRY_STATUS(e.add(embed_spec(g, K, tol, o, x0, X, lambda), ws, ws_bytes, &id));
+    ME_TRY_STATUS(e.add(embed_slot_spec(g, K, tol, o, x0, X, lambda), ws, ws_bytes, &id));
     ME_TRY_STATUS(e.run());
     const SlotResult& r = e.result(id);
     st = r.status;
@@ -185,7 +185,7 @@ int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opt
     else if (Ks[i] < 1 || Ks[i] > kMaxBlockCols) st[i] = ME_ERR_K_RANGE;
     if (st[i] < 0) continue;
     st[i] = build_pre(&Ws[i], o, s, &gs[i]);
-    if (st[i] >= 0) st[i] = check_k(gs[i], Ks[i]);
+    if (st[i] >= 0) st[i] = check_k_range(gs[i], Ks[i]);
   }
   // eps
   std::vector<double> eps(G, 0.0);
@@ -199,10 +199,10 @@ int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opt
     for (int i = 0; i < G; ++i) {
       if (st[i] < 0 || !gs[i].needs_eps) continue;
       if (gs[i].n <= kDenseMaxN) {
-        st[i] = dense_eps(gs[i], s, &eps[i]);
+        st[i] = dense_eps_solve(gs[i], s, &eps[i]);
         continue;
       }
-      const int a = e.add(eps_spec(gs[i], o), nullptr, 0, &id[i]);
+      const int a = e.add(eps_slot_spec(gs[i], o), nullptr, 0, &id[i]);
       if (a < 0) st[i] = a;
     }
     ME_TRY_STATUS(e.run());
@@ -234,12 +234,12 @@ int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opt
         double* buf = nullptr;
         const size_t bytes = embed_workspace_bytes(gs[i], Ks[i], o);
         ME_TRY(hipMallocAsync((void**)&buf, bytes, s));
-        dense_embed(gs[i], Ks[i], buf, Xs[i], lams[i], s);
+        dense_embed_solve(gs[i], Ks[i], buf, Xs[i], lams[i], s);
         ME_TRY(hipFreeAsync(buf, s));
         continue;
       }
       const int a =
-          e.add(embed_spec(gs[i], Ks[i], tol, o, nullptr, Xs[i], lams[i]), nullptr, 0, &id[i]);
+          e.add(embed_slot_spec(gs[i], Ks[i], tol, o, nullptr, Xs[i], lams[i]), nullptr, 0, &id[i]);
       if (a < 0) st[i] = a;
     }
     ME_TRY_STATUS(e.run());
