@@ -24,7 +24,8 @@ Readings of passages that are silent or ambiguous are listed at the top of
 from .graph_ops import (  # noqa: F401
     OracleInputError, validate, degrees, laplacian, two_hop, theta_sum_q,
     fiedler_value, mu_from_q, operator_a, gershgorin_radii, b_from_radii,
-    build_ops, two_hop_components,
+    build_ops, two_hop_components, two_hop_rows, q_diag_rows,
+    operator_a_rows,
 )
 from .solve import (  # noqa: F401
     generalized_eigs, dense_generalized_eigs, sparse_generalized_eigs,

@@ -109,6 +109,58 @@ def two_hop(W: sp.csr_matrix):
     return T.indptr.astype(np.int64), T.indices.astype(np.int32), counts
 
 
+def two_hop_rows(n, rowptr, col, rows):
+    """T_i for the listed rows only, straight from the definition (reading
+    R3): the neighbours of the neighbours of i, minus i and its own
+    neighbours.  For checking sampled rows of graphs too large for the
+    whole pattern.  Returns a list of sorted int arrays."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    col = np.asarray(col)
+    out = []
+    for i in rows:
+        nbr = set(col[rowptr[i]:rowptr[i + 1]].tolist())
+        two = set()
+        for k in nbr:
+            two.update(col[rowptr[k]:rowptr[k + 1]].tolist())
+        two.discard(int(i))
+        two.difference_update(nbr)
+        out.append(np.array(sorted(two), dtype=np.int64))
+    return out
+
+
+def q_diag_rows(n, rowptr, col, rows):
+    """Q_ii for the listed rows under reading R1: sum over j in T_i of
+    (1/T_i + 1/T_j) = 1 + sum_j 1/T_j (0 when T_i is empty)."""
+    out = []
+    for i, ti in zip(rows, two_hop_rows(n, rowptr, col, rows)):
+        if ti.size == 0:
+            out.append(0.0)
+            continue
+        tj = two_hop_rows(n, rowptr, col, ti.tolist())
+        out.append(sum(1.0 / ti.size + 1.0 / t.size for t in tj))
+    return np.array(out)
+
+
+def operator_a_rows(n, rowptr, col, val, rows, mu: float, eps: float, X):
+    """(A X)_i for the listed rows from the definitions, A = L - mu Q + eps I
+    (eq. (obj2), reading R1 for Q): d_i x_i - sum_j w_ij x_j
+    - mu (Q_ii x_i - sum_{j in T_i} (1/T_i + 1/T_j) x_j) + eps x_i."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    X = np.asarray(X, dtype=np.float64)
+    out = np.zeros((len(rows), X.shape[1]))
+    trows = two_hop_rows(n, rowptr, col, rows)
+    for q, (i, ti) in enumerate(zip(rows, trows)):
+        cols = np.asarray(col[rowptr[i]:rowptr[i + 1]], dtype=np.int64)
+        w = np.asarray(val[rowptr[i]:rowptr[i + 1]], dtype=np.float64)
+        y = w.sum() * X[i] - w @ X[cols]
+        if ti.size:
+            tj = np.array([t.size for t in two_hop_rows(n, rowptr, col, ti.tolist())], float)
+            qij = 1.0 / ti.size + 1.0 / tj
+            y -= mu * (qij.sum() * X[i] - qij @ X[ti])
+        out[q] = y + eps * X[i]
+    return out
+
+
 def theta_sum_q(n, t_rowptr, t_col, reading: str = "R1") -> sp.csr_matrix:
     """Q = sum_i Theta_i (eq. (Q)).  Each Theta_i is added entry by entry:
     for j in T_i, +1/T_i at (j, j), -1/T_i at (i, j) and (j, i); at (i, i)

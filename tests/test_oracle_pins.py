@@ -77,6 +77,35 @@ def test_two_hop_knn_graph_bruteforce():
     assert all(col[rp[i]:rp[i + 1]].tolist() == bf[i] for i in range(g.n))
 
 
+def test_two_hop_rows_match_golden_and_full_pattern():
+    """The per-row form (for sampled checks of large graphs) gives the hand-
+    derived tri-mesh sets and the same rows as the whole pattern."""
+    g = sg.tri_mesh(3)
+    rp, col, _ = oracle.two_hop(oracle.validate(g.n, g.rowptr, g.col, g.val))
+    rows = oracle.two_hop_rows(g.n, g.rowptr, g.col, range(g.n))
+    assert [r.tolist() for r in rows] == [col[rp[i]:rp[i + 1]].tolist() for i in range(g.n)]
+    g = sg.manifold_graph("torus", 400, 8, 9)
+    ops = oracle.build_ops(g.n, g.rowptr, g.col, g.val)
+    sample = [0, 17, 123, 399]
+    rows = oracle.two_hop_rows(g.n, g.rowptr, g.col, sample)
+    trp, tcol = ops["t_rowptr"], ops["t_col"]
+    assert all(r.tolist() == tcol[trp[i]:trp[i + 1]].tolist() for r, i in zip(rows, sample))
+    # Q_ii of the per-row form equals the diagonal of the assembled Q
+    np.testing.assert_allclose(oracle.q_diag_rows(g.n, g.rowptr, g.col, sample),
+                               ops["Q"].diagonal()[sample], rtol=1e-14)
+
+
+def test_operator_rows_match_assembled_a():
+    """Row-wise A X (sampled checks of large graphs) equals the assembled
+    sparse A times X on a graph small enough for both."""
+    g = sg.manifold_graph("swiss_roll", 500, 10, 4)
+    ops = oracle.build_ops(g.n, g.rowptr, g.col, g.val)
+    X = np.random.default_rng(0).standard_normal((g.n, 3))
+    rows = [0, 5, 250, 499]
+    got = oracle.operator_a_rows(g.n, g.rowptr, g.col, g.val, rows, ops["mu"], ops["eps"], X)
+    np.testing.assert_allclose(got, (ops["A"] @ X)[rows], rtol=1e-11, atol=1e-12)
+
+
 def test_two_hop_special_graphs():
     # line of 5 (Fig. 2a): ends and their neighbours have one, the middle two
     ops = ops_of(sg.line(5))
