@@ -641,8 +641,8 @@ __global__ void k_row_len_perm(int64_t n, const int32_t* perm, const int64_t* w_
 __global__ void k_pack_perm(int64_t n, const int32_t* perm, const int32_t* iperm,
                             const int64_t* off, const int64_t* w_rp, const int32_t* w_col,
                             const double* w_val, const int64_t* t_rp, const int32_t* t_col,
-                            int32_t* a_rp, int32_t* a_split, int32_t* a_col, double* a_w,
-                            float* a_w32) {
+                            const double* invt, int32_t* a_rp, int32_t* a_split,
+                            int32_t* a_col, double* a_w, float* a_w32) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i > n) return;
   const int64_t start = off[i];
@@ -657,8 +657,15 @@ __global__ void k_pack_perm(int64_t n, const int32_t* perm, const int32_t* iperm
     a_w[start + t] = v;
     a_w32[start + t] = (float)v;
   }
+  // T entries: weight 1/T_i + 1/T_j of the two-hop term (eq. (Q), reading R1)
   const int64_t tb = t_rp[o], te = t_rp[o + 1];
-  for (int64_t t = tb; t < te; ++t) a_col[start + nw + (t - tb)] = iperm[t_col[t]];
+  for (int64_t t = tb; t < te; ++t) {
+    const int64_t k = start + nw + (t - tb);
+    a_col[k] = iperm[t_col[t]];
+    const double q = invt[o] + invt[t_col[t]];
+    a_w[k] = q;
+    a_w32[k] = (float)q;
+  }
 }
 
 // dst[i'] = src[perm[i']] for a double array and its FP32 copy
@@ -778,11 +785,9 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   g->a_split = ar.take<int32_t>(n);
   g->perm = ar.take<int32_t>(n);
   g->iperm = ar.take<int32_t>(n);
-  g->invt_s = ar.take<double>(n);
   g->qinv_s = ar.take<double>(n);
   g->b_s = ar.take<double>(n);
   g->dinv_s = ar.take<double>(n);
-  g->invt32_s = ar.take<float>(n);
   g->qinv32_s = ar.take<float>(n);
   g->b32_s = ar.take<float>(n);
   g->dinv32_s = ar.take<float>(n);
@@ -878,10 +883,8 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   scan_counts(n, rowlen, aoff, tile_tmp, s);
   k_pack_perm<<<ceil_div(n + 1, kBlock), kBlock, 0, s>>>(n, g->perm, g->iperm, aoff, g->w_rp,
                                                          g->w_col, g->w_val, g->t_rp, g->t_col,
-                                                         g->a_rp, g->a_split, g->a_col, g->a_w,
-                                                         g->a_w32);
-  k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->invt, g->invt_s,
-                                                       g->invt32_s);
+                                                         g->invt, g->a_rp, g->a_split, g->a_col,
+                                                         g->a_w, g->a_w32);
   k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->qinv, g->qinv_s,
                                                        g->qinv32_s);
   int hroots = 0;

@@ -121,13 +121,13 @@ struct GraphOps {
   // Solver order (locality permutation): solver row i' is user row perm[i'].
   int32_t* perm = nullptr;     // solver index -> user index
   int32_t* iperm = nullptr;    // user index -> solver index
-  double *invt_s = nullptr, *qinv_s = nullptr, *b_s = nullptr, *dinv_s = nullptr;
-  float *invt32_s = nullptr, *qinv32_s = nullptr, *b32_s = nullptr, *dinv32_s = nullptr;
+  double *qinv_s = nullptr, *b_s = nullptr, *dinv_s = nullptr;
+  float *qinv32_s = nullptr, *b32_s = nullptr, *dinv32_s = nullptr;
   // merged difference-form operator in solver order: row i = [W cols | T cols]
   int32_t* a_rp = nullptr;     // int32[n+1]
   int32_t* a_split = nullptr;  // int32[n]: first T position of row i
   int32_t* a_col = nullptr;    // int32[nnz_w + nnz_t]
-  double* a_w = nullptr;       // W weights at the W positions (T positions unused)
+  double* a_w = nullptr;       // w_ij at the W positions, 1/T_i + 1/T_j at the T positions
   float* a_w32 = nullptr;
   double* scratch_d = nullptr;  // n doubles of build scratch
   int* dflags = nullptr;        // 64 ints of build flags and reductions

@@ -34,14 +34,12 @@ struct SlotDev {
   int kcopy;        // columns of x0 copied into the start block
   int k_out;        // columns written to out_x
   // operator Op in difference form: W entries w_ij, T entries
-  // c_t (1/T_i + 1/T_j), diagonal shift s_diag
+  // c_t (1/T_i + 1/T_j) (a_w holds both weights), diagonal shift s_diag
   const int32_t* a_rp;
   const int32_t* a_split;
   const int32_t* a_col;
   const double* a_w;
   const float* a_w32;
-  const double* invt;
-  const float* invt32;
   double c_t, s_diag;
   const double* bdiag;  // null: B = I
   const double* dinv;   // diag(Op)^-1

@@ -159,16 +159,12 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
   d.a_w = g.a_w;
   d.a_w32 = g.a_w32;
   if (sp.op == OP_A) {
-    d.invt = g.invt_s;
-    d.invt32 = g.invt32_s;
     d.c_t = -g.mu;
     d.s_diag = g.eps;
     d.bdiag = g.b_s;
     d.dinv = g.dinv_s;
     d.dinv32 = g.dinv32_s;
   } else {
-    d.invt = g.invt_s;
-    d.invt32 = g.invt32_s;
     d.c_t = 1.0;
     d.s_diag = 0.0;
     d.bdiag = nullptr;

@@ -19,13 +19,35 @@ struct Lay {
   using Vec = VecT<T, VEC>;
 };
 
-template <typename T, int V>
-__device__ inline VecT<T, V> ldv(const T* p) {
-  return *reinterpret_cast<const VecT<T, V>*>(p);
+// Every pointer these helpers take refers to global (device) memory.  The
+// engine's kernels fetch their pointers from the slot table, so the compiler
+// cannot infer the address space and would emit flat accesses; casting to
+// the global address space gives global loads and stores.
+#define ME_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const ME_GLOBAL T* glob(const T* p) {
+  return (const ME_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ ME_GLOBAL T* globw(T* p) {
+  return (ME_GLOBAL T*)p;
 }
 template <typename T, int V>
-__device__ inline void stv(T* p, const VecT<T, V>& v) {
-  *reinterpret_cast<VecT<T, V>*>(p) = v;
+__device__ __forceinline__ VecT<T, V> ldv(const T* p) {
+  typedef T vt __attribute__((ext_vector_type(V)));
+  const vt x = *(const ME_GLOBAL vt*)glob(p);
+  VecT<T, V> r;
+#pragma unroll
+  for (int q = 0; q < V; ++q) r.v[q] = x[q];
+  return r;
+}
+template <typename T, int V>
+__device__ __forceinline__ void stv(T* p, const VecT<T, V>& v) {
+  typedef T vt __attribute__((ext_vector_type(V)));
+  vt x;
+#pragma unroll
+  for (int q = 0; q < V; ++q) x[q] = v.v[q];
+  *(ME_GLOBAL vt*)globw(p) = x;
 }
 
 #define ME_DISPATCH_KB(kb, ...)                       \
@@ -36,86 +58,90 @@ __device__ inline void stv(T* p, const VecT<T, V>& v) {
     default: break;                                   \
   }
 
-// Row i of the product, without the diagonal term.  A group of G
-// consecutive lanes owns one row and splits the row's entries: lane q takes
-// entries q, q + G, q + 2G, ..., loads their columns and weights (coalesced
-// over the group), gathers the neighbour rows x_j whole (KB values, 16-byte
-// loads) UNR at a time, and accumulates the full row; a butterfly over the
-// group leaves the sum in every lane.  Entries before a_split are W entries
-// (weight w_ij), the rest T entries (weight c_t (1/T_i + 1/T_j)).  All
-// lanes of the wave must call it (shuffles).
+// Row i of the product, without the diagonal term.  A group of G = 8
+// consecutive lanes owns one row.  A row of KB values is NCH 16-byte chunks;
+// lane q takes chunk c = q % NCH of the entries e = q / NCH, e + EPL,
+// e + 2 EPL, ... (EPL = G / NCH entries per round), so the lanes of one
+// instruction that load the same neighbour row share its cache lines.
+// Entries before a_split are W entries (weight w_ij), the rest T entries
+// (stored weight 1/T_i + 1/T_j, scaled by c_t).  Each lane accumulates its
+// chunk; a butterfly over the lanes of equal chunk leaves the row's chunk c
+// in every lane.  All lanes of the wave must call it (shuffles).
 template <typename T, int KB>
 struct RowCfg {
-  static constexpr int G = 8;                                  // lanes per row
-  static constexpr int UNR = (KB * sizeof(T) >= 128) ? 2 : 4;  // entries in flight per lane
-  static constexpr int V16 = 16 / sizeof(T);                   // values per 16-byte load
-  static constexpr int NLD = KB * sizeof(T) / 16;              // 16-byte loads per row
+  static constexpr int G = 8;                         // lanes per row
+  static constexpr int V16 = 16 / (int)sizeof(T);     // values per 16-byte chunk
+  static constexpr int NCH = KB * (int)sizeof(T) / 16; // chunks per row
+  static constexpr int EPL = G / NCH;                 // entries per round
+  static constexpr int UNR = 4;                       // rounds in flight
 };
-
-template <typename T, int KB>
-__device__ __forceinline__ void load_row(const T* __restrict__ p, T (&v)[KB]) {
-  using C = RowCfg<T, KB>;
-#pragma unroll
-  for (int l = 0; l < C::NLD; ++l) {
-    const auto t = ldv<T, C::V16>(p + l * C::V16);
-#pragma unroll
-    for (int q = 0; q < C::V16; ++q) v[l * C::V16 + q] = t.v[q];
-  }
-}
 
 template <typename T, int KB>
 __device__ __forceinline__ void spmm_row(bool live, int64_t row, int q,
                                          const int32_t* __restrict__ a_rp,
                                          const int32_t* __restrict__ a_split,
                                          const int32_t* __restrict__ a_col,
-                                         const T* __restrict__ a_w, const T* __restrict__ invt,
-                                         T c_t, int skip_w, const T* __restrict__ x,
-                                         const T (&xi)[KB], T (&acc)[KB]) {
+                                         const T* __restrict__ a_w, T c_t, int skip_w,
+                                         const T* __restrict__ x,
+                                         const T (&xi)[RowCfg<T, KB>::V16],
+                                         T (&acc)[RowCfg<T, KB>::V16]) {
   using C = RowCfg<T, KB>;
-  constexpr int G = C::G, UNR = C::UNR;
+  constexpr int V = C::V16, EPL = C::EPL, UNR = C::UNR;
+  const int ch = q % C::NCH, e0 = q / C::NCH;
+  const ME_GLOBAL int32_t* rp = glob(a_rp);
+  const ME_GLOBAL int32_t* spl = glob(a_split);
+  const ME_GLOBAL int32_t* cl = glob(a_col);
+  const ME_GLOBAL T* wt = glob(a_w);
   int32_t s = 0, sp = 0, e = 0;
-  T ti = 0;
   if (live) {
-    s = skip_w ? a_split[row] : a_rp[row];
-    sp = a_split[row];
-    e = a_rp[row + 1];
-    ti = invt[row];
+    sp = spl[row];
+    s = skip_w ? sp : rp[row];
+    e = rp[row + 1];
   }
 #pragma unroll
-  for (int v = 0; v < KB; ++v) acc[v] = 0;
-  // steps of G entries; loop to the wave's longest row
-  int32_t steps = (e - s + G - 1) / G;
-  for (int o = kWave / 2; o > 0; o >>= 1) steps = max(steps, __shfl_xor(steps, o));
-  for (int32_t st = 0; st < steps; st += UNR) {
+  for (int v = 0; v < V; ++v) acc[v] = 0;
+  // rounds of EPL entries; loop to the wave's longest row
+  int32_t rounds = (e - s + EPL - 1) / EPL;
+  for (int o = kWave / 2; o > 0; o >>= 1) rounds = max(rounds, __shfl_xor(rounds, o));
+  for (int32_t r = 0; r < rounds; r += UNR) {
     int32_t c[UNR];
     T cf[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      const int32_t k = s + (st + u) * G + q;
+      const int32_t k = s + (r + u) * EPL + e0;
       const bool ok = k < e;
-      c[u] = ok ? a_col[k] : -1;
-      cf[u] = (ok && k < sp) ? a_w[k] : (T)0;
+      c[u] = ok ? cl[k] : -1;
+      const T w = ok ? wt[k] : (T)0;
+      cf[u] = k < sp ? w : c_t * w;
     }
-    T xj[UNR][KB];
+    T xj[UNR][V];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      const int32_t k = s + (st + u) * G + q;
       if (c[u] >= 0) {
-        load_row<T, KB>(x + (int64_t)c[u] * KB, xj[u]);
-        if (k >= sp) cf[u] = c_t * (ti + invt[c[u]]);
+        const auto t = ldv<T, V>(x + (int64_t)c[u] * KB + ch * V);
+#pragma unroll
+        for (int v = 0; v < V; ++v) xj[u][v] = t.v[v];
       } else {
 #pragma unroll
-        for (int v = 0; v < KB; ++v) xj[u][v] = xi[v];
+        for (int v = 0; v < V; ++v) xj[u][v] = xi[v];
       }
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u)
 #pragma unroll
-      for (int v = 0; v < KB; ++v) acc[v] += cf[u] * (xi[v] - xj[u][v]);
+      for (int v = 0; v < V; ++v) acc[v] += cf[u] * (xi[v] - xj[u][v]);
   }
 #pragma unroll
-  for (int v = 0; v < KB; ++v)
-    for (int o = G / 2; o > 0; o >>= 1) acc[v] += __shfl_xor(acc[v], o);
+  for (int v = 0; v < V; ++v)
+    for (int o = C::NCH; o < C::G; o <<= 1) acc[v] += __shfl_xor(acc[v], o);
+}
+
+// One 16-byte chunk of a row into registers.
+template <typename T, int V>
+__device__ __forceinline__ void load_chunk(const T* __restrict__ p, T (&v)[V]) {
+  const auto t = ldv<T, V>(p);
+#pragma unroll
+  for (int q = 0; q < V; ++q) v[q] = t.v[q];
 }
 
 typedef double dx4 __attribute__((ext_vector_type(4)));

@@ -8,7 +8,8 @@
 // (operator products) give each row 8 lanes that split the row's entries.
 //
 // Difference-form operator (eq. (obj2) with the Laplacian identity of
-// Section 3.1): with the merged row [W columns | T columns],
+// Section 3.1): with the merged row [W columns | T columns] (T entries carry
+// the weight 1/T_i + 1/T_j),
 //   (A x)_i = sum_{j in N(i)} w_ij (x_i - x_j)
 //             - mu sum_{j in T_i} (1/T_i + 1/T_j) (x_i - x_j) + eps x_i
 //   (Q x)_i = sum_{j in T_i} (1/T_i + 1/T_j) (x_i - x_j)
@@ -26,14 +27,12 @@ template <>
 struct SB<double> {
   static __device__ __forceinline__ double* blk(const SlotDev& d, int id) { return d.b64[id]; }
   static __device__ __forceinline__ const double* w(const SlotDev& d) { return d.a_w; }
-  static __device__ __forceinline__ const double* invt(const SlotDev& d) { return d.invt; }
   static __device__ __forceinline__ const double* dinv(const SlotDev& d) { return d.dinv; }
 };
 template <>
 struct SB<float> {
   static __device__ __forceinline__ float* blk(const SlotDev& d, int id) { return d.b32[id]; }
   static __device__ __forceinline__ const float* w(const SlotDev& d) { return d.a_w32; }
-  static __device__ __forceinline__ const float* invt(const SlotDev& d) { return d.invt32; }
   static __device__ __forceinline__ const float* dinv(const SlotDev& d) { return d.dinv32; }
 };
 
@@ -44,8 +43,9 @@ struct ElemCfg {
   static constexpr int VEC = L::VEC, LPR = L::LPR, RB = kBlock / LPR;
 };
 
+__device__ __forceinline__ bool slot_done(const SlotDev& d) { return *glob(&d.ctrl->done) != 0; }
 __device__ __forceinline__ bool skip_slot(const SlotDev& d, int cert) {
-  return !cert && d.ctrl->done;
+  return !cert && slot_done(d);
 }
 
 // ---------------------------------------------------------------------------
@@ -66,25 +66,19 @@ __global__ void __launch_bounds__(kBlock) k_sl_spmm(const SlotDev* __restrict__ 
   const int q = threadIdx.x % C::G;
   const bool live = row < d.n;
   const T* x = SB<T>::blk(d, in);
-  T xi[KB];
-#pragma unroll
-  for (int v = 0; v < KB; ++v) xi[v] = 0;
-  if (live) load_row<T, KB>(x + row * KB, xi);
-  T acc[KB];
-  spmm_row<T, KB>(live, row, q, d.a_rp, d.a_split, d.a_col, SB<T>::w(d), SB<T>::invt(d),
-                  (T)d.c_t, d.skip_w, x, xi, acc);
-  if (!live || q >= C::NLD) return;
-  T* y = SB<T>::blk(d, out);
+  const int ch = q % C::NCH;
+  T xi[C::V16], acc[C::V16];
+  // own row (row 0 stands in for rows past the end; their lanes add nothing)
+  load_chunk<T, C::V16>(x + (live ? row : 0) * KB + ch * C::V16, xi);
+  spmm_row<T, KB>(live, row, q, d.a_rp, d.a_split, d.a_col, SB<T>::w(d), (T)d.c_t, d.skip_w, x,
+                  xi, acc);
+  if (!live || q >= C::NCH) return;
+  // lane q < NCH holds chunk q of the row
   const T sd = (T)d.s_diag;
+  VecT<T, C::V16> o;
 #pragma unroll
-  for (int l = 0; l < C::NLD; ++l) {
-    if (q == l) {
-      VecT<T, C::V16> o;
-#pragma unroll
-      for (int v = 0; v < C::V16; ++v) o.v[v] = acc[l * C::V16 + v] + sd * xi[l * C::V16 + v];
-      stv<T, C::V16>(y + row * KB + l * C::V16, o);
-    }
-  }
+  for (int v = 0; v < C::V16; ++v) o.v[v] = acc[v] + sd * xi[v];
+  stv<T, C::V16>(SB<T>::blk(d, out) + row * KB + q * C::V16, o);
 }
 
 template <typename T>
@@ -111,7 +105,7 @@ __global__ void __launch_bounds__(kBlock) k_sl_cheb_first(const SlotDev* __restr
   using E = ElemCfg<T, KB>;
   const Tile t = tiles[blockIdx.x];
   const SlotDev& d = sl[t.slot];
-  if (d.ctrl->done) return;
+  if (slot_done(d)) return;
   const int64_t row = (int64_t)t.blk * E::RB + threadIdx.x / E::LPR;
   const int sub = threadIdx.x % E::LPR;
   if (row >= d.n) return;
@@ -134,43 +128,34 @@ __global__ void __launch_bounds__(kBlock) k_sl_cheb_step(const SlotDev* __restri
   if (b >= ntiles) return;
   const Tile t = tiles[b];
   const SlotDev& d = sl[t.slot];
-  if (d.ctrl->done) return;
+  if (slot_done(d)) return;
   const int64_t row = (int64_t)t.blk * kGatherRows + threadIdx.x / C::G;
   const int q = threadIdx.x % C::G;
   const bool live = row < d.n;
   const T* yi_p = SB<T>::blk(d, yin);
-  T yi[KB];
-#pragma unroll
-  for (int v = 0; v < KB; ++v) yi[v] = 0;
-  if (live) load_row<T, KB>(yi_p + row * KB, yi);
-  T acc[KB];
-  spmm_row<T, KB>(live, row, q, d.a_rp, d.a_split, d.a_col, SB<T>::w(d), SB<T>::invt(d),
-                  (T)d.c_t, d.skip_w, yi_p, yi, acc);
-  if (!live || q >= C::NLD) return;
+  const int ch = q % C::NCH;
+  T yi[C::V16], acc[C::V16];
+  load_chunk<T, C::V16>(yi_p + (live ? row : 0) * KB + ch * C::V16, yi);
+  spmm_row<T, KB>(live, row, q, d.a_rp, d.a_split, d.a_col, SB<T>::w(d), (T)d.c_t, d.skip_w,
+                  yi_p, yi, acc);
+  if (!live || q >= C::NCH) return;
+  // lane q < NCH updates chunk q of the row
   const T sd = (T)d.s_diag;
-  const T alpha = (T)d.cheb->alpha[k];
-  const T beta = (T)d.cheb->beta[k] * SB<T>::dinv(d)[row];
-  const T* rp = SB<T>::blk(d, r);
+  const T alpha = (T)*glob(&d.cheb->alpha[k]);
+  const T beta = (T)*glob(&d.cheb->beta[k]) * glob(SB<T>::dinv(d))[row];
+  const int64_t o = row * KB + q * C::V16;
+  const auto ri = ldv<T, C::V16>(SB<T>::blk(d, r) + o);
   T* dp = SB<T>::blk(d, ddb);
-  T* yo_p = SB<T>::blk(d, yout);
+  auto di = ldv<T, C::V16>(dp + o);
+  VecT<T, C::V16> yo;
 #pragma unroll
-  for (int l = 0; l < C::NLD; ++l) {
-    if (q == l) {
-      const int64_t o = row * KB + l * C::V16;
-      const auto ri = ldv<T, C::V16>(rp + o);
-      auto di = ldv<T, C::V16>(dp + o);
-      VecT<T, C::V16> yo;
-#pragma unroll
-      for (int v = 0; v < C::V16; ++v) {
-        const int c = l * C::V16 + v;
-        const T res = ri.v[v] - (acc[c] + sd * yi[c]);
-        di.v[v] = alpha * di.v[v] + beta * res;
-        yo.v[v] = yi[c] + di.v[v];
-      }
-      stv<T, C::V16>(dp + o, di);
-      stv<T, C::V16>(yo_p + o, yo);
-    }
+  for (int v = 0; v < C::V16; ++v) {
+    const T res = ri.v[v] - (acc[v] + sd * yi[v]);
+    di.v[v] = alpha * di.v[v] + beta * res;
+    yo.v[v] = yi[v] + di.v[v];
   }
+  stv<T, C::V16>(dp + o, di);
+  stv<T, C::V16>(SB<T>::blk(d, yout) + o, yo);
 }
 
 template <typename T>
@@ -680,7 +665,7 @@ __global__ void __launch_bounds__(kBlock) k_sl_convert(const SlotDev* __restrict
   constexpr int VEC = E::VEC, LPR = E::LPR;
   const Tile t = tiles[blockIdx.x];
   const SlotDev& d = sl[t.slot];
-  if (d.ctrl->done) return;
+  if (slot_done(d)) return;
   const int64_t row = (int64_t)t.blk * E::RB + threadIdx.x / LPR;
   const int sub = threadIdx.x % LPR;
   if (row >= d.n) return;

@@ -26,8 +26,7 @@ template <typename T, int KB>
 __global__ void __launch_bounds__(kBlock) k_spmm(int64_t n, const int32_t* __restrict__ a_rp,
                                                  const int32_t* __restrict__ a_split,
                                                  const int32_t* __restrict__ a_col,
-                                                 const T* __restrict__ a_w,
-                                                 const T* __restrict__ invt, T c_t, T s_diag,
+                                                 const T* __restrict__ a_w, T c_t, T s_diag,
                                                  int skip_w, const T* __restrict__ x,
                                                  T* __restrict__ y, const int* done) {
   using C = RowCfg<T, KB>;
@@ -38,22 +37,15 @@ __global__ void __launch_bounds__(kBlock) k_spmm(int64_t n, const int32_t* __res
   const int64_t row = gt / C::G;
   const int q = (int)(gt % C::G);
   const bool live = row < n;
-  T xi[KB];
+  const int ch = q % C::NCH;
+  T xi[C::V16], acc[C::V16];
+  load_chunk<T, C::V16>(x + (live ? row : 0) * KB + ch * C::V16, xi);
+  spmm_row<T, KB>(live, row, q, a_rp, a_split, a_col, a_w, c_t, skip_w, x, xi, acc);
+  if (!live || q >= C::NCH) return;
+  VecT<T, C::V16> o;
 #pragma unroll
-  for (int v = 0; v < KB; ++v) xi[v] = 0;
-  if (live) load_row<T, KB>(x + row * KB, xi);
-  T acc[KB];
-  spmm_row<T, KB>(live, row, q, a_rp, a_split, a_col, a_w, invt, c_t, skip_w, x, xi, acc);
-  if (!live) return;
-#pragma unroll
-  for (int l = 0; l < C::NLD; ++l) {
-    if (q == l) {
-      VecT<T, C::V16> out;
-#pragma unroll
-      for (int v = 0; v < C::V16; ++v) out.v[v] = acc[l * C::V16 + v] + s_diag * xi[l * C::V16 + v];
-      stv<T, C::V16>(y + row * KB + l * C::V16, out);
-    }
-  }
+  for (int v = 0; v < C::V16; ++v) o.v[v] = acc[v] + s_diag * xi[v];
+  stv<T, C::V16>(y + row * KB + q * C::V16, o);
 }
 
 template <typename T>
@@ -61,12 +53,10 @@ struct OpArrays;
 template <>
 struct OpArrays<double> {
   static const double* w(const GraphOps& g) { return g.a_w; }
-  static const double* invt(const GraphOps& g) { return g.invt_s; }
 };
 template <>
 struct OpArrays<float> {
   static const float* w(const GraphOps& g) { return g.a_w32; }
-  static const float* invt(const GraphOps& g) { return g.invt32_s; }
 };
 
 template <typename T>
@@ -78,7 +68,7 @@ void launch_spmm(const GraphOps& g, int kb, OpKind op, const T* x, T* y, const i
   ME_DISPATCH_KB(kb, {
     const int64_t grid = xcd_grid(ceil_div(g.n * RowCfg<T, KB>::G, kBlock));
     k_spmm<T, KB><<<grid, kBlock, 0, s>>>(g.n, g.a_rp, g.a_split, g.a_col, OpArrays<T>::w(g),
-                                          OpArrays<T>::invt(g), c_t, s_diag, skip_w, x, y, done);
+                                          c_t, s_diag, skip_w, x, y, done);
   });
 }
 template void launch_spmm<double>(const GraphOps&, int, OpKind, const double*, double*,
