@@ -140,10 +140,13 @@ int me_graph_ops_export(const me_graph_ops* ops, int64_t* T_rowptr, int32_t* T_c
 
 /* The node order the solver works in (a locality order; outputs are always
  * in the caller's order): perm[i] = caller's node id of solver row i
- * (device int32[n]).  Breadth-first levels from a pseudo-peripheral node
- * (the lowest-numbered node on the last level of a search from node 0),
- * ties by node id, further components after the first, each started at
- * its lowest-numbered node.  A test and diagnostic hook.  Synchronises. */
+ * (device int32[n]).  Cuthill-McKee order: start at the lowest-numbered node
+ * on the last breadth-first level of a search from node 0 (a
+ * pseudo-peripheral node); level l+1 holds the unvisited neighbours of level
+ * l, ordered by the position of their first neighbour in level l, then by
+ * node id; further components follow, each started at its lowest-numbered
+ * unvisited node.  Graphs of at most 48 nodes keep the identity.  A test and
+ * diagnostic hook.  Synchronises. */
 int me_graph_ops_order(const me_graph_ops* ops, int32_t* perm, void* stream);
 
 /* Applies the operators to a dense block (device, row-major n x k, 1 <= k <= 16):

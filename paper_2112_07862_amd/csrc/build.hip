@@ -371,29 +371,42 @@ __global__ void k_uf_count_roots(int64_t n, int32_t* parent, int* roots) {
 // ---------------------------------------------------------------------------
 
 
-// Breadth-first levels in one workgroup: all levels (and, in mode 1, all
-// remaining components) in one launch, frontier counters in LDS.
-//   mode 0: BFS from node 0 over its component; *out = lowest node on the
-//           last level (the pseudo-peripheral start).
-//   mode 1: level[] reset, BFS from *out, then from the lowest unvisited node
-//           of each further component (levels continue across components);
-//           *out = the last level used.
-// The level of a node is its breadth-first distance, which does not depend
-// on the order in which a level's frontier was built.
+// Breadth-first levels in one workgroup, with frontier counters in LDS.
+//
+// bfs_levels: plain levels from one node (used to find the pseudo-peripheral
+// start: the lowest-numbered node on the last level of a search from 0).
+//
+// cm_order: the Cuthill-McKee order, written straight into perm.  Level 0 is
+// the start; level l+1 holds the unvisited neighbours of level l, ordered by
+// the position of their first (lowest-positioned) neighbour in level l and
+// then by node id -- exactly the order of a sequential search that scans
+// level l in order and each row's neighbours in increasing id.  In parallel:
+// every level-l node claims its unvisited neighbours and lowers their key to
+// its own position (atomic min); each node then counts the neighbours whose
+// key is its position, a block-wide scan turns the counts into offsets, and
+// each node writes its children in row (id) order.  Further components
+// follow, each started at its lowest unvisited node.
+// level[] and key[] change through device-scope atomics, which are performed
+// in L2; every read of them is an agent-scope atomic load so that no stale
+// L1 copy is used.
+__device__ __forceinline__ int32_t ld_coherent(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr int kBfsThreads = 1024;
 
-__device__ __forceinline__ int32_t bfs_from(const int64_t* __restrict__ rp,
-                                            const int32_t* __restrict__ col, int32_t* level,
-                                            int32_t* fa, int32_t* fb, int32_t start, int32_t lev0,
-                                            int32_t* s_cnt) {
+__device__ __forceinline__ int32_t bfs_levels(const int64_t* __restrict__ rp,
+                                              const int32_t* __restrict__ col, int32_t* level,
+                                              int32_t* fa, int32_t* fb, int32_t start,
+                                              int32_t* s_cnt) {
   const int tid = threadIdx.x;
   if (tid == 0) {
-    level[start] = lev0;
+    level[start] = 0;
     fa[0] = start;
     s_cnt[0] = 1;
   }
   __syncthreads();
-  int32_t lev = lev0;
+  int32_t lev = 0;
   int32_t* fin = fa;
   int32_t* fout = fb;
   for (;;) {
@@ -404,7 +417,7 @@ __device__ __forceinline__ int32_t bfs_from(const int64_t* __restrict__ rp,
       const int32_t u = fin[i];
       for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
         const int32_t v = col[t];
-        if (__atomic_load_n(&level[v], __ATOMIC_RELAXED) < 0 &&
+        if (ld_coherent(&level[v]) < 0 &&
             atomicCAS(&level[v], -1, lev + 1) == -1)
           fout[atomicAdd(&s_cnt[1], 1)] = v;
       }
@@ -422,26 +435,134 @@ __device__ __forceinline__ int32_t bfs_from(const int64_t* __restrict__ rp,
   return lev;
 }
 
-__global__ void __launch_bounds__(kBfsThreads) k_bfs_block(int64_t n, const int64_t* rp,
-                                                           const int32_t* col, int32_t* level,
-                                                           int32_t* fa, int32_t* fb, int mode,
-                                                           int32_t* out) {
+// Exclusive scan of a[0..n) in place by one workgroup; returns the total.
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t* a, int32_t n, int32_t* s_wave) {
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  constexpr int NW = kBfsThreads / kWave;
+  int32_t carry = 0;
+  for (int32_t base = 0; base < n; base += kBfsThreads) {
+    const int32_t i = base + tid;
+    const int32_t v = i < n ? a[i] : 0;
+    int32_t x = v;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) s_wave[wave] = x;
+    __syncthreads();
+    if (wave == 0) {
+      int32_t w = lane < NW ? s_wave[lane] : 0;
+      for (int o = 1; o < NW; o <<= 1) {
+        const int32_t y = __shfl_up(w, o);
+        if (lane >= o) w += y;
+      }
+      if (lane < NW) s_wave[lane] = w;
+    }
+    __syncthreads();
+    const int32_t before = wave > 0 ? s_wave[wave - 1] : 0;
+    if (i < n) a[i] = carry + before + x - v;
+    const int32_t chunk = s_wave[NW - 1];
+    __syncthreads();
+    carry += chunk;
+  }
+  return carry;
+}
+
+// One component of the Cuthill-McKee order: perm[off] = start, levels from
+// lev0; key and cnt are n-int scratch (key = INT32_MAX for unvisited nodes).
+// Returns the number of nodes placed; *last_lev receives the last level.
+__device__ __forceinline__ int64_t cm_component(const int64_t* __restrict__ rp,
+                                                const int32_t* __restrict__ col, int32_t* level,
+                                                int32_t* key, int32_t* cnt, int32_t* perm,
+                                                int64_t off, int32_t start, int32_t lev0,
+                                                int32_t* s_wave, int32_t* last_lev) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    level[start] = lev0;
+    perm[off] = start;
+  }
+  __syncthreads();
+  int64_t placed = 1;
+  int32_t nin = 1, lev = lev0;
+  for (;;) {
+    const int32_t* fin = perm + off + placed - nin;
+    int32_t* fout = perm + off + placed;
+    // claim unvisited neighbours; key = lowest claiming position
+    for (int32_t i = tid; i < nin; i += kBfsThreads) {
+      const int32_t u = fin[i];
+      for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
+        const int32_t v = col[t];
+        int32_t lv = ld_coherent(&level[v]);
+        if (lv < 0) {
+          const int32_t old = atomicCAS(&level[v], -1, lev + 1);
+          lv = old < 0 ? lev + 1 : old;
+        }
+        if (lv == lev + 1) atomicMin(&key[v], i);
+      }
+    }
+    __syncthreads();
+    // own children per frontier node
+    for (int32_t i = tid; i < nin; i += kBfsThreads) {
+      const int32_t u = fin[i];
+      int32_t c = 0;
+      for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
+        const int32_t v = col[t];
+        c += (ld_coherent(&level[v]) == lev + 1 && ld_coherent(&key[v]) == i) ? 1 : 0;
+      }
+      cnt[i] = c;
+    }
+    __syncthreads();
+    const int32_t nout = block_exclusive_scan(cnt, nin, s_wave);
+    for (int32_t i = tid; i < nin; i += kBfsThreads) {
+      const int32_t u = fin[i];
+      int32_t j = cnt[i];
+      for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
+        const int32_t v = col[t];
+        if (ld_coherent(&level[v]) == lev + 1 && ld_coherent(&key[v]) == i) fout[j++] = v;
+      }
+    }
+    __syncthreads();
+    if (nout == 0) break;
+    placed += nout;
+    nin = nout;
+    ++lev;
+  }
+  *last_lev = lev;
+  return placed;
+}
+
+__global__ void __launch_bounds__(kBfsThreads) k_pseudo_peripheral(int64_t n, const int64_t* rp,
+                                                                   const int32_t* col,
+                                                                   int32_t* level, int32_t* fa,
+                                                                   int32_t* fb, int32_t* out) {
   __shared__ int32_t s_cnt[2];
   __shared__ int32_t s_min;
   const int tid = threadIdx.x;
   for (int64_t i = tid; i < n; i += kBfsThreads) level[i] = -1;
   __syncthreads();
-  if (mode == 0) {
-    const int32_t last = bfs_from(rp, col, level, fa, fb, 0, 0, s_cnt);
-    if (tid == 0) s_min = INT32_MAX;
-    __syncthreads();
-    for (int64_t i = tid; i < n; i += kBfsThreads)
-      if (level[i] == last) atomicMin(&s_min, (int32_t)i);
-    __syncthreads();
-    if (tid == 0) *out = s_min;
-    return;
+  const int32_t last = bfs_levels(rp, col, level, fa, fb, 0, s_cnt);
+  if (tid == 0) s_min = INT32_MAX;
+  __syncthreads();
+  for (int64_t i = tid; i < n; i += kBfsThreads)
+    if (ld_coherent(&level[i]) == last) atomicMin(&s_min, (int32_t)i);
+  __syncthreads();
+  if (tid == 0) *out = s_min;
+}
+
+__global__ void __launch_bounds__(kBfsThreads) k_cm_order(int64_t n, const int64_t* rp,
+                                                          const int32_t* col, int32_t* level,
+                                                          int32_t* key, int32_t* cnt,
+                                                          const int32_t* start, int32_t* perm) {
+  __shared__ int32_t s_wave[kBfsThreads / kWave];
+  __shared__ int32_t s_min;
+  const int tid = threadIdx.x;
+  for (int64_t i = tid; i < n; i += kBfsThreads) {
+    level[i] = -1;
+    key[i] = INT32_MAX;
   }
-  int32_t last = bfs_from(rp, col, level, fa, fb, *out, 0, s_cnt);
+  __syncthreads();
+  int32_t last = 0;
+  int64_t off = cm_component(rp, col, level, key, cnt, perm, 0, *start, 0, s_wave, &last);
   // further components: the lowest unvisited node only grows
   int64_t ptr = 0;
   for (;;) {
@@ -449,7 +570,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_block(int64_t n, const int6
     __syncthreads();
     for (; ptr < n; ptr += kBfsThreads) {
       const int64_t i = ptr + tid;
-      if (i < n && level[i] < 0) atomicMin(&s_min, (int32_t)i);
+      if (i < n && ld_coherent(&level[i]) < 0) atomicMin(&s_min, (int32_t)i);
       __syncthreads();
       if (s_min != INT32_MAX) break;
       __syncthreads();
@@ -457,70 +578,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_bfs_block(int64_t n, const int6
     const int32_t nxt = s_min;
     __syncthreads();
     if (nxt == INT32_MAX) break;
-    last = bfs_from(rp, col, level, fa, fb, nxt, last + 1, s_cnt);
-  }
-  if (tid == 0) *out = last;
-}
-
-
-// --- stable LSD radix sort of (key, value) int32 pairs, 8-bit digits ------
-constexpr int kRsThreads = 256;
-constexpr int kRsItems = 4 * kRsThreads;  // per block
-
-__global__ void __launch_bounds__(kRsThreads) k_rs_count(int64_t n, const int32_t* key, int shift,
-                                                         int nblk, int32_t* cnt) {
-  __shared__ int32_t h[256];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kRsItems;
-  for (int r = 0; r < 4; ++r) {
-    const int64_t i = base + r * kRsThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(key[i] >> shift) & 255], 1);
-  }
-  __syncthreads();
-  cnt[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];  // digit-major
-}
-
-// Items of a block are placed in index order within each digit: per round
-// of 256 items, the rank among equal digits is the count in earlier rounds,
-// earlier waves of this round and earlier lanes of this wave.
-__global__ void __launch_bounds__(kRsThreads) k_rs_scatter(int64_t n, const int32_t* key,
-                                                           const int32_t* val, int shift, int nblk,
-                                                           const int64_t* off, int32_t* key_out,
-                                                           int32_t* val_out) {
-  __shared__ int32_t running[256];
-  __shared__ int32_t wcnt[kRsThreads / kWave][256];
-  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-  running[tid] = 0;
-  const int64_t base = (int64_t)blockIdx.x * kRsItems;
-  const unsigned long long lt = (1ull << lane) - 1ull;
-  for (int r = 0; r < 4; ++r) {
-    for (int q = 0; q < kRsThreads / kWave; ++q) wcnt[q][tid] = 0;
-    const int64_t i = base + r * kRsThreads + tid;
-    const bool valid = i < n;
-    const int32_t k = valid ? key[i] : 0;
-    const int d = (k >> shift) & 255;
-    unsigned long long mask = __ballot(valid);
-    for (int bit = 0; bit < 8; ++bit) {
-      const bool b = (d >> bit) & 1;
-      const unsigned long long bs = __ballot(valid && b);
-      mask &= b ? bs : ~bs;
-    }
-    const int rank = __popcll(mask & lt);
-    __syncthreads();
-    if (valid && rank == 0) wcnt[wave][d] = __popcll(mask);
-    __syncthreads();
-    if (valid) {
-      int64_t pos = off[(int64_t)d * nblk + blockIdx.x] + running[d] + rank;
-      for (int q = 0; q < wave; ++q) pos += wcnt[q][d];
-      key_out[pos] = k;
-      val_out[pos] = val[i];
-    }
-    __syncthreads();
-    int add = 0;
-    for (int q = 0; q < kRsThreads / kWave; ++q) add += wcnt[q][tid];
-    running[tid] += add;
-    __syncthreads();
+    off += cm_component(rp, col, level, key, cnt, perm, off, nxt, last + 1, s_wave, &last);
   }
 }
 
@@ -542,47 +600,22 @@ static int locality_order(GraphOps* g, int32_t* perm, int32_t* iperm, hipStream_
     k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, iperm);
     return ME_OK;
   }
-  const int64_t nblk = ceil_div(n, kRsItems);
-  const size_t bytes = Arena::round((n + 2) * 4) * 6 + Arena::round(256 * nblk * 4) +
-                       Arena::round(256 * nblk * 8 + 8) + Arena::round((256 * nblk / kScanTile + 2) * 8) +
-                       Arena::round(64);
+  const size_t bytes = Arena::round((n + 2) * 4) * 3 + Arena::round(64);
   void* mem = nullptr;
   ME_TRY(hipMallocAsync(&mem, bytes, s));
   Arena a{(char*)mem, bytes, 0};
   int32_t* level = a.take<int32_t>(n + 2);
   int32_t* fa = a.take<int32_t>(n + 2);
   int32_t* fb = a.take<int32_t>(n + 2);
-  int32_t* k2 = a.take<int32_t>(n + 2);
-  int32_t* v1 = a.take<int32_t>(n + 2);
-  int32_t* v2 = a.take<int32_t>(n + 2);
-  int32_t* cnt = a.take<int32_t>(256 * nblk);
-  int64_t* off = a.take<int64_t>(256 * nblk + 1);
-  int64_t* tiles = a.take<int64_t>(256 * nblk / kScanTile + 2);
-  int32_t* minv = a.take<int32_t>(16);
-  int st = ME_OK;
-  // pseudo-peripheral start (search from node 0, lowest node on its last
-  // level), then the levels from there and from each further component
-  k_bfs_block<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb, 0, minv);
-  k_bfs_block<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb, 1, minv);
-  int32_t last = 0;
-  ME_TRY(hipMemcpyAsync(&last, minv, 4, hipMemcpyDeviceToHost, s));
-  ME_TRY(hipStreamSynchronize(s));
-  if (st >= 0) {
-    // stable sort of node ids by level
-    k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, v1);
-    int32_t *kin = level, *kout = k2, *vin = v1, *vout = v2;
-    for (int shift = 0; shift < 32 && (last >> shift) > 0; shift += 8) {
-      k_rs_count<<<nblk, kRsThreads, 0, s>>>(n, kin, shift, (int)nblk, cnt);
-      scan_counts(256 * nblk, cnt, off, tiles, s);
-      k_rs_scatter<<<nblk, kRsThreads, 0, s>>>(n, kin, vin, shift, (int)nblk, off, kout, vout);
-      std::swap(kin, kout);
-      std::swap(vin, vout);
-    }
-    ME_TRY(hipMemcpyAsync(perm, vin, n * 4, hipMemcpyDeviceToDevice, s));
-    k_invert_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, perm, iperm);
-  }
-  (void)hipFreeAsync(mem, s);
-  return st;
+  int32_t* start = a.take<int32_t>(16);
+  // pseudo-peripheral start, then the Cuthill-McKee order from it (fa, fb
+  // serve as the frontiers of the first search and as key / count scratch
+  // of the second)
+  k_pseudo_peripheral<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb, start);
+  k_cm_order<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb, start, perm);
+  k_invert_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, perm, iperm);
+  ME_TRY(hipFreeAsync(mem, s));
+  return ME_OK;
 }
 
 // ---------------------------------------------------------------------------

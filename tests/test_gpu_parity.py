@@ -245,37 +245,49 @@ def test_embed_mixed_precision_matches_oracle(me, name, K):
     assert np.all(oracle.relative_residuals(ops["A"], ops["b"], X, lam) <= tol * 1.01 + 1e-12)
 
 
-def bfs_order_reference(g):
-    """Breadth-first levels from a pseudo-peripheral node, ties by node id,
-    components in order of their lowest unvisited node (pure Python)."""
+def cm_order_reference(g):
+    """Cuthill-McKee order (pure Python, sequential): start at the lowest
+    node on the last breadth-first level of a search from node 0; scan each
+    level in order and each node's neighbours in increasing id, appending
+    unvisited ones; further components from their lowest unvisited node."""
     n = g.n
-    nbr = [g.col[g.rowptr[i]:g.rowptr[i + 1]] for i in range(n)]
+    if n <= 48:
+        return np.arange(n)
+    nbr = [g.col[g.rowptr[i]:g.rowptr[i + 1]].tolist() for i in range(n)]
+    level = [-1] * n
+    level[0], front = 0, [0]
+    while front:
+        nxt = []
+        for u in front:
+            for v in nbr[u]:
+                if level[v] < 0:
+                    level[v] = level[u] + 1
+                    nxt.append(v)
+        front = nxt
+    last = max(level)
+    start = min(i for i in range(n) if level[i] == last)
+    seen = [False] * n
+    order = []
 
-    def bfs(start, lev0, level):
-        level[start] = lev0
-        front, lev = [start], lev0
+    def component(s):
+        seen[s] = True
+        order.append(s)
+        front = [s]
         while front:
             nxt = []
             for u in front:
                 for v in nbr[u]:
-                    if level[v] < 0:
-                        level[v] = lev + 1
+                    if not seen[v]:
+                        seen[v] = True
                         nxt.append(v)
-            if nxt:
-                lev += 1
+            order.extend(nxt)
             front = nxt
-        return lev
 
-    if n <= 48:
-        return np.arange(n)
-    level = -np.ones(n, dtype=np.int64)
-    last = bfs(0, 0, level)
-    start = int(np.min(np.nonzero(level == last)[0]))
-    level[:] = -1
-    last = bfs(start, 0, level)
-    while np.any(level < 0):
-        last = bfs(int(np.min(np.nonzero(level < 0)[0])), last + 1, level)
-    return np.argsort(level, kind="stable")
+    component(start)
+    for i in range(n):
+        if not seen[i]:
+            component(i)
+    return np.array(order)
 
 
 @pytest.mark.parametrize("name", ["square_2k", "sphere_3k", "two_squares", "grid_bipartite",
@@ -285,5 +297,5 @@ def test_solver_order_bit_exact(me, name):
     h = me.build_graph_ops(g)
     perm = _np(h.order())
     assert np.array_equal(np.sort(perm), np.arange(g.n))
-    assert np.array_equal(perm, bfs_order_reference(g))
+    assert np.array_equal(perm, cm_order_reference(g))
     h.close()
