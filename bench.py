@@ -123,6 +123,8 @@ def bench_batch(args) -> int:
     torch.cuda.synchronize()
     total_n = sum(g.n for g in graphs)
     opts = dict(precision=args.precision, seed=0, cheb_degree=args.cheb_degree)
+    if args.eps_tol is not None:
+        opts["eps_tol"] = args.eps_tol
     tol = 1e-6
     for w in range(args.warmup):
         t = time.perf_counter()
@@ -255,6 +257,7 @@ def main() -> int:
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--time-kernel", default="cheb", choices=list(KERNELS))
     ap.add_argument("--cheb-degree", type=int, default=128)
+    ap.add_argument("--eps-tol", type=float, default=None)
     ap.add_argument("--cpu-sample-n", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512)

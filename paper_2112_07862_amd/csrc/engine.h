@@ -69,7 +69,7 @@ struct Tile {
   int32_t blk;
 };
 
-constexpr int kGatherRows = kBlock / 8;  // rows per block of the gathering kernels
+constexpr int kGatherRows = 32;  // rows per workgroup of the gathering kernels
 
 // Work lists of one set of slots with a common block width kb (device).
 struct TileSet {

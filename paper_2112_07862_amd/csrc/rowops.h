@@ -58,7 +58,7 @@ __device__ __forceinline__ void stv(T* p, const VecT<T, V>& v) {
     default: break;                                   \
   }
 
-// Row i of the product, without the diagonal term.  A group of G = 8
+// Row i of the product, without the diagonal term.  A group of G
 // consecutive lanes owns one row.  A row of KB values is NCH 16-byte chunks;
 // lane q takes chunk c = q % NCH of the entries e = q / NCH, e + EPL,
 // e + 2 EPL, ... (EPL = G / NCH entries per round), so the lanes of one
@@ -69,11 +69,14 @@ __device__ __forceinline__ void stv(T* p, const VecT<T, V>& v) {
 // in every lane.  All lanes of the wave must call it (shuffles).
 template <typename T, int KB>
 struct RowCfg {
-  static constexpr int G = 8;                         // lanes per row
-  static constexpr int V16 = 16 / (int)sizeof(T);     // values per 16-byte chunk
+  static constexpr int V16 = 16 / (int)sizeof(T);      // values per 16-byte chunk
   static constexpr int NCH = KB * (int)sizeof(T) / 16; // chunks per row
-  static constexpr int EPL = G / NCH;                 // entries per round
-  static constexpr int UNR = 4;                       // rounds in flight
+  // lanes per row: 8, or 4 per chunk for rows of more than two chunks
+  static constexpr int G = (4 * NCH > 8) ? (4 * NCH > 32 ? 32 : 4 * NCH) : 8;
+  static constexpr int EPL = G / NCH;                  // entries per round
+  static constexpr int UNR = 4;                        // rounds in flight
+  static constexpr int ROWS = 32;                      // rows per workgroup
+  static constexpr int THREADS = ROWS * G;
 };
 
 template <typename T, int KB>

@@ -5,7 +5,8 @@
 //
 // Blocks are row-major n x KB.  Elementwise kernels give each row
 // LPR = KB / VEC lanes with one 16-byte vector each; the gathering kernels
-// (operator products) give each row 8 lanes that split the row's entries.
+// (operator products) give each row G lanes (8 to 32 by row size) that
+// split the row's entries, 32 rows per workgroup.
 //
 // Difference-form operator (eq. (obj2) with the Laplacian identity of
 // Section 3.1): with the merged row [W columns | T columns] (T entries carry
@@ -53,7 +54,7 @@ __device__ __forceinline__ bool skip_slot(const SlotDev& d, int cert) {
 // ---------------------------------------------------------------------------
 
 template <typename T, int KB>
-__global__ void __launch_bounds__(kBlock) k_sl_spmm(const SlotDev* __restrict__ sl,
+__global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_spmm(const SlotDev* __restrict__ sl,
                                                     const Tile* __restrict__ tiles,
                                                     int64_t ntiles, int in, int out, int cert) {
   using C = RowCfg<T, KB>;
@@ -85,8 +86,9 @@ template <typename T>
 void sl_spmm(const SlotDev* sl, const TileSet& ts, int in, int out, int cert, hipStream_t s) {
   if (ts.n_gather == 0) return;
   ME_DISPATCH_KB(ts.kb, {
-    k_sl_spmm<T, KB><<<xcd_grid(ts.n_gather), kBlock, 0, s>>>(sl, ts.gather, ts.n_gather, in,
-                                                               out, cert);
+    static_assert(RowCfg<T, KB>::ROWS == kGatherRows, "gather tile rows");
+    k_sl_spmm<T, KB><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
+        sl, ts.gather, ts.n_gather, in, out, cert);
   });
 }
 template void sl_spmm<double>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
@@ -119,7 +121,7 @@ __global__ void __launch_bounds__(kBlock) k_sl_cheb_first(const SlotDev* __restr
 }
 
 template <typename T, int KB>
-__global__ void __launch_bounds__(kBlock) k_sl_cheb_step(const SlotDev* __restrict__ sl,
+__global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const SlotDev* __restrict__ sl,
                                                          const Tile* __restrict__ tiles,
                                                          int64_t ntiles, int k, int r, int yin,
                                                          int yout, int ddb) {
@@ -170,8 +172,9 @@ void sl_cheb_step(const SlotDev* sl, const TileSet& ts, int k, int r, int yin, i
                   hipStream_t s) {
   if (ts.n_gather == 0) return;
   ME_DISPATCH_KB(ts.kb, {
-    k_sl_cheb_step<T, KB><<<xcd_grid(ts.n_gather), kBlock, 0, s>>>(sl, ts.gather, ts.n_gather, k,
-                                                                    r, yin, yout, dd);
+    static_assert(RowCfg<T, KB>::ROWS == kGatherRows, "gather tile rows");
+    k_sl_cheb_step<T, KB><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
+        sl, ts.gather, ts.n_gather, k, r, yin, yout, dd);
   });
 }
 template void sl_cheb_first<double>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);

@@ -23,7 +23,7 @@ namespace me {
 // Y = Op X: G lanes per row; lane q < KB / V16 writes the q-th 16-byte
 // slice of the row.
 template <typename T, int KB>
-__global__ void __launch_bounds__(kBlock) k_spmm(int64_t n, const int32_t* __restrict__ a_rp,
+__global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_spmm(int64_t n, const int32_t* __restrict__ a_rp,
                                                  const int32_t* __restrict__ a_split,
                                                  const int32_t* __restrict__ a_col,
                                                  const T* __restrict__ a_w, T c_t, T s_diag,
@@ -31,9 +31,9 @@ __global__ void __launch_bounds__(kBlock) k_spmm(int64_t n, const int32_t* __res
                                                  T* __restrict__ y, const int* done) {
   using C = RowCfg<T, KB>;
   if (done && *done) return;
-  const int64_t blk = xcd_block(ceil_div(n * C::G, kBlock));
-  if (blk * kBlock >= n * C::G) return;
-  const int64_t gt = blk * kBlock + threadIdx.x;
+  const int64_t blk = xcd_block(ceil_div(n, C::ROWS));
+  if (blk * C::ROWS >= n) return;
+  const int64_t gt = blk * C::THREADS + threadIdx.x;
   const int64_t row = gt / C::G;
   const int q = (int)(gt % C::G);
   const bool live = row < n;
@@ -66,8 +66,8 @@ void launch_spmm(const GraphOps& g, int kb, OpKind op, const T* x, T* y, const i
   const T s_diag = op == OP_A ? (T)g.eps : (T)0;
   const int skip_w = op == OP_Q;
   ME_DISPATCH_KB(kb, {
-    const int64_t grid = xcd_grid(ceil_div(g.n * RowCfg<T, KB>::G, kBlock));
-    k_spmm<T, KB><<<grid, kBlock, 0, s>>>(g.n, g.a_rp, g.a_split, g.a_col, OpArrays<T>::w(g),
+    const int64_t grid = xcd_grid(ceil_div(g.n, RowCfg<T, KB>::ROWS));
+    k_spmm<T, KB><<<grid, RowCfg<T, KB>::THREADS, 0, s>>>(g.n, g.a_rp, g.a_split, g.a_col, OpArrays<T>::w(g),
                                           c_t, s_diag, skip_w, x, y, done);
   });
 }
