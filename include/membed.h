@@ -59,6 +59,12 @@ enum { ME_FP64 = 0, ME_MIXED = 1 };
  * diag(A)^-1 A that approximates A^-1 on [a, b] (b: Gershgorin bound,
  * a: half the diag(A)-Rayleigh quotient of the leading Ritz vector). */
 enum { ME_PRECOND_NONE = 0, ME_PRECOND_JACOBI = 1, ME_PRECOND_CHEBYSHEV = 2 };
+/* The Chebyshev preconditioner of the embedding solve approximates the
+ * inverse of L + eps I (one-hop entries only; spectrally within about mu |Q|
+ * of A, and a third of the entries) or of A itself.  Any symmetric positive
+ * definite preconditioner leaves the converged pairs unchanged; it only
+ * changes the iteration count.  The eps solve always uses Q. */
+enum { ME_CHEB_LAPLACIAN = 0, ME_CHEB_FULL = 1 };
 
 /* Input graph W (Section 3.1), CSR, device memory, owned by the caller and
  * only read during the call.  rowptr int64[n+1] (rowptr[0] = 0), col int32[nnz]
@@ -82,6 +88,8 @@ typedef struct {
   int check_every;    /* iterations enqueued between host convergence reads (default 16) */
   uint64_t seed;      /* seed of the library's starting blocks (default 0)          */
   int cheb_degree;    /* Chebyshev preconditioner degree, 2..256 (default 64)       */
+  int cheb_op;        /* operator the Chebyshev preconditioner inverts in the
+                         embedding solve: ME_CHEB_LAPLACIAN (default) or ME_CHEB_FULL */
 } me_opts;
 
 /* Per-solve report.  Times are host wall-clock milliseconds of the phases. */

@@ -38,8 +38,12 @@ _PRECOND = {"none": L.ME_PRECOND_NONE, "jacobi": L.ME_PRECOND_JACOBI,
             "chebyshev": L.ME_PRECOND_CHEBYSHEV}
 
 
+_CHEB_OP = {"laplacian": L.ME_CHEB_LAPLACIAN, "full": L.ME_CHEB_FULL}
+
+
 def make_opts(precision="fp64", precond="chebyshev", max_iter=None, eps_max_iter=None,
-              eps_tol=None, check_every=None, seed=None, cheb_degree=None) -> L.MeOpts:
+              eps_tol=None, check_every=None, seed=None, cheb_degree=None,
+              cheb_op=None) -> L.MeOpts:
     o = L.MeOpts()
     L.load().me_opts_default(ctypes.byref(o))
     o.precision = _PRECISION[precision]
@@ -56,6 +60,8 @@ def make_opts(precision="fp64", precond="chebyshev", max_iter=None, eps_max_iter
         o.seed = int(seed)
     if cheb_degree is not None:
         o.cheb_degree = int(cheb_degree)
+    if cheb_op is not None:
+        o.cheb_op = _CHEB_OP[cheb_op]
     return o
 
 

@@ -30,6 +30,7 @@ void me_opts_default(me_opts* o) {
   o->check_every = 16;
   o->seed = 0;
   o->cheb_degree = 64;
+  o->cheb_op = ME_CHEB_LAPLACIAN;
 }
 
 const char* me_status_string(int st) {
@@ -55,7 +56,7 @@ const char* me_status_string(int st) {
 static bool opts_valid(const me_opts& o) {
   return o.max_iter >= 1 && o.eps_max_iter >= 1 && o.check_every >= 1 && o.precond >= 0 &&
          o.precond <= 2 && (o.precision == ME_FP64 || o.precision == ME_MIXED) &&
-         o.eps_tol > 0 &&
+         o.eps_tol > 0 && (o.cheb_op == ME_CHEB_LAPLACIAN || o.cheb_op == ME_CHEB_FULL) &&
          (o.precond != ME_PRECOND_CHEBYSHEV ||
           (o.cheb_degree >= 2 && o.cheb_degree <= kMaxChebDegree));
 }

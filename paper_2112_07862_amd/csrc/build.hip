@@ -734,13 +734,14 @@ __global__ void __launch_bounds__(kBlock) k_radius(int64_t n, const double* d, c
 // b_i = r_i / (prod r)^(1/N) through logs; Jacobi 1 / A_ii, A_ii = d_i - mu Q_ii + eps.
 __global__ void k_bvec(int64_t n, const double* r, const double* d, const double* qdiag,
                        const double* partial, int nparts, double mu, double eps, double* b,
-                       float* b32, double* dinv, float* dinv32, unsigned long long* maxdiag_bits,
-                       unsigned long long* maxratio_bits) {
+                       float* b32, double* dinv, float* dinv32, double* pdinv, float* pdinv32,
+                       unsigned long long* maxdiag_bits, unsigned long long* maxratio_bits,
+                       unsigned long long* maxpratio_bits) {
   double sum = 0.0;
   for (int q = 0; q < nparts; ++q) sum += partial[q];
   const double mean = sum / (double)n;
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  double diag = 0.0, ratio = 0.0;
+  double diag = 0.0, ratio = 0.0, pratio = 0.0;
   if (i < n) {
     double bi = exp(log(r[i]) - mean);
     b[i] = bi;
@@ -749,14 +750,20 @@ __global__ void k_bvec(int64_t n, const double* r, const double* d, const double
     dinv[i] = 1.0 / diag;
     dinv32[i] = (float)(1.0 / diag);
     ratio = (diag + r[i]) / diag;  // Gershgorin right end of row i of diag(A)^-1 A
+    const double pd = d[i] + eps;  // L + eps I: diagonal d_i + eps, radius d_i
+    pdinv[i] = 1.0 / pd;
+    pdinv32[i] = (float)(1.0 / pd);
+    pratio = (pd + d[i]) / pd;
   }
   for (int o = 32; o > 0; o >>= 1) {
     diag = fmax(diag, __shfl_xor(diag, o));
     ratio = fmax(ratio, __shfl_xor(ratio, o));
+    pratio = fmax(pratio, __shfl_xor(pratio, o));
   }
   if ((threadIdx.x & (kWave - 1)) == 0) {
     atomic_max_pos_double(maxdiag_bits, diag);
     atomic_max_pos_double(maxratio_bits, ratio);
+    atomic_max_pos_double(maxpratio_bits, pratio);
   }
 }
 
@@ -787,7 +794,7 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   size_t b1 = 0;
   b1 += Arena::round((n + 1) * 8) + Arena::round(nnz * 4) + Arena::round(nnz * 8);  // W
   b1 += Arena::round((n + 1) * 8) + Arena::round(n * 4);                            // t_rp, t_cnt
-  b1 += 8 * Arena::round(n * 8) + 4 * Arena::round(n * 4);                          // per node
+  b1 += 9 * Arena::round(n * 8) + 5 * Arena::round(n * 4);                          // per node
   b1 += Arena::round((n + 1) * 4) + Arena::round(n * 4);                            // a_rp, a_split
   b1 += 2 * Arena::round(n * 4) + 4 * Arena::round(n * 8) + 4 * Arena::round(n * 4);  // solver order
   b1 += Arena::round((n + 1) * 8);                                                  // offsets
@@ -809,6 +816,8 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   g->dinv = ar.take<double>(n);
   g->invt = ar.take<double>(n);
   g->qinv = ar.take<double>(n);
+  g->pdinv = ar.take<double>(n);
+  g->pdinv32 = ar.take<float>(n);
   double* scratch_d = ar.take<double>(n);  // tile sums / partials / parents
   g->b32 = ar.take<float>(n);
   g->dinv32 = ar.take<float>(n);
@@ -821,9 +830,11 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   g->qinv_s = ar.take<double>(n);
   g->b_s = ar.take<double>(n);
   g->dinv_s = ar.take<double>(n);
+  g->pdinv_s = ar.take<double>(n);
   g->qinv32_s = ar.take<float>(n);
   g->b32_s = ar.take<float>(n);
   g->dinv32_s = ar.take<float>(n);
+  g->pdinv32_s = ar.take<float>(n);
   int64_t* aoff = ar.take<int64_t>(n + 1);
   int* dflags = ar.take<int>(64);
   if (!dflags) return ME_ERR_HIP;
@@ -952,14 +963,21 @@ int build_post(GraphOps* g, double eps, int eps_iters, hipStream_t s) {
   const int nparts = (int)std::min<int64_t>(ceil_div(n, kBlock), kPartialBlocks);
   double* partial = reinterpret_cast<double*>(scratch_d);
   k_radius<<<nparts, kBlock, 0, s>>>(n, g->d, g->qdiag, g->mu, g->r, partial);
+  unsigned long long* maxpratio_bits = reinterpret_cast<unsigned long long*>(dflags + 10);
   k_bvec<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->r, g->d, g->qdiag, partial, nparts, g->mu,
                                                 g->eps, g->b, g->b32, g->dinv, g->dinv32,
-                                                maxdiag_bits, maxratio_bits);
-  unsigned long long hmaxdiag = 0, hmaxratio = 0;
-  ME_TRY_STATUS(read_scalar(maxdiag_bits, &hmaxdiag, s));
-  ME_TRY_STATUS(read_scalar(maxratio_bits, &hmaxratio, s));
-  std::memcpy(&g->max_diag_a, &hmaxdiag, 8);
-  std::memcpy(&g->cheb_b_a, &hmaxratio, 8);
+                                                g->pdinv, g->pdinv32, maxdiag_bits, maxratio_bits,
+                                                maxpratio_bits);
+  unsigned long long hmax[3] = {0, 0, 0};
+  ME_TRY(hipMemcpyAsync(hmax, maxdiag_bits, 8, hipMemcpyDeviceToHost, s));
+  ME_TRY(hipMemcpyAsync(hmax + 1, maxratio_bits, 8, hipMemcpyDeviceToHost, s));
+  ME_TRY(hipMemcpyAsync(hmax + 2, maxpratio_bits, 8, hipMemcpyDeviceToHost, s));
+  ME_TRY(hipStreamSynchronize(s));
+  std::memcpy(&g->max_diag_a, &hmax[0], 8);
+  std::memcpy(&g->cheb_b_a, &hmax[1], 8);
+  std::memcpy(&g->cheb_b_p, &hmax[2], 8);
+  k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->pdinv, g->pdinv_s,
+                                                       g->pdinv32_s);
   k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->b, g->b_s, g->b32_s);
   k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->dinv, g->dinv_s,
                                                        g->dinv32_s);

@@ -115,14 +115,17 @@ struct GraphOps {
   float* qinv32 = nullptr;
   double cheb_b_a = 2.0;    // Gershgorin bound of the spectrum of diag(A)^-1 A
   double cheb_b_q = 2.0;    // and of diag(Q)^-1 Q
+  double cheb_b_p = 2.0;    // and of diag(L + eps I)^-1 (L + eps I)
+  double* pdinv = nullptr;  // 1 / (d_i + eps): Jacobi scaling of L + eps I
+  float* pdinv32 = nullptr;
   float* b32 = nullptr;
   float* dinv32 = nullptr;
   float* invt32 = nullptr;
   // Solver order (locality permutation): solver row i' is user row perm[i'].
   int32_t* perm = nullptr;     // solver index -> user index
   int32_t* iperm = nullptr;    // user index -> solver index
-  double *qinv_s = nullptr, *b_s = nullptr, *dinv_s = nullptr;
-  float *qinv32_s = nullptr, *b32_s = nullptr, *dinv32_s = nullptr;
+  double *qinv_s = nullptr, *b_s = nullptr, *dinv_s = nullptr, *pdinv_s = nullptr;
+  float *qinv32_s = nullptr, *b32_s = nullptr, *dinv32_s = nullptr, *pdinv32_s = nullptr;
   // merged difference-form operator in solver order: row i = [W cols | T cols]
   int32_t* a_rp = nullptr;     // int32[n+1]
   int32_t* a_split = nullptr;  // int32[n]: first T position of row i

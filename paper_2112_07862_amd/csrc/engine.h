@@ -42,8 +42,15 @@ struct SlotDev {
   const float* a_w32;
   double c_t, s_diag;
   const double* bdiag;  // null: B = I
-  const double* dinv;   // diag(Op)^-1
+  const double* dinv;   // diag(Op)^-1 (Jacobi preconditioner)
   const float* dinv32;
+  // operator the Chebyshev preconditioner inverts: the same rows, restricted
+  // to the W entries when cheb_w_only (L + eps I), with its own diagonal
+  // shift and Jacobi scaling
+  int cheb_w_only;
+  double cheb_s_diag;
+  const double* cheb_dinv;
+  const float* cheb_dinv32;
   const int32_t* perm;   // solver row -> user row (null: identity)
   const int32_t* iperm;  // user row -> solver row
   const double* x0;      // user-order n x kcopy start columns (may be null)

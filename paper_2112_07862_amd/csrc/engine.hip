@@ -164,12 +164,21 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
     d.bdiag = g.b_s;
     d.dinv = g.dinv_s;
     d.dinv32 = g.dinv32_s;
+    const bool lap = o_.cheb_op == ME_CHEB_LAPLACIAN;
+    d.cheb_w_only = lap;
+    d.cheb_s_diag = g.eps;
+    d.cheb_dinv = lap ? g.pdinv_s : g.dinv_s;
+    d.cheb_dinv32 = lap ? g.pdinv32_s : g.dinv32_s;
   } else {
     d.c_t = 1.0;
     d.s_diag = 0.0;
     d.bdiag = nullptr;
     d.dinv = g.qinv_s;
     d.dinv32 = g.qinv32_s;
+    d.cheb_w_only = 0;
+    d.cheb_s_diag = 0.0;
+    d.cheb_dinv = g.qinv_s;
+    d.cheb_dinv32 = g.qinv32_s;
   }
   d.perm = g.perm;
   d.iperm = g.iperm;
@@ -316,12 +325,16 @@ void Engine::iteration(const TileSet& ts) {
     if (tm) {
       for (int id : ts.ids) {
         const GraphOps& g = *sh_[id].sp.g;
-        // algorithmic bytes of one step: column index of every entry, weight
-        // of every W entry, row bounds (8 B), 1/T_i and D^-1_i per row, and
-        // the block y_in (neighbour rows counted once), R, dd in, dd out, y_out
+        // algorithmic bytes of one step: column index and weight of every
+        // entry of the preconditioner's operator, row bounds (8 B), D^-1_i,
+        // and the block y_in (neighbour rows counted once), R, dd in, dd out,
+        // y_out
         const double sz = cheb32_ ? 4.0 : 8.0;
-        cb += 4.0 * (double)(g.nnz_w + g.nnz_t) + sz * (double)g.nnz_w +
-              (double)g.n * (8.0 + 2.0 * sz) + 5.0 * (double)g.n * kb * sz;
+        const bool w_only = sh_[id].sp.op == OP_A && o_.cheb_op == ME_CHEB_LAPLACIAN;
+        const double nnz = sh_[id].sp.op == OP_Q ? (double)g.nnz_t
+                                                 : (w_only ? (double)g.nnz_w
+                                                           : (double)(g.nnz_w + g.nnz_t));
+        cb += (4.0 + sz) * nnz + (double)g.n * (8.0 + sz) + 5.0 * (double)g.n * kb * sz;
       }
     }
     const int w = cheb32_ ? BW32 : BW, y = cheb32_ ? BY32 : BY, dd = cheb32_ ? BDD32 : BDD;

@@ -39,7 +39,7 @@ SlotSpec embed_slot_spec(const GraphOps& g, int K, double tol, const me_opts* o,
   sp.tol = tol;
   sp.max_iter = o->max_iter;
   sp.deflate = false;
-  sp.cheb_b = g.cheb_b_a * 1.01;
+  sp.cheb_b = (o->cheb_op == ME_CHEB_LAPLACIAN ? g.cheb_b_p : g.cheb_b_a) * 1.01;
   sp.lam_scale = g.max_diag_a > 0 ? g.max_diag_a : 1.0;
   sp.seed = o->seed;
   sp.x0 = x0;

@@ -29,12 +29,14 @@ struct SB<double> {
   static __device__ __forceinline__ double* blk(const SlotDev& d, int id) { return d.b64[id]; }
   static __device__ __forceinline__ const double* w(const SlotDev& d) { return d.a_w; }
   static __device__ __forceinline__ const double* dinv(const SlotDev& d) { return d.dinv; }
+  static __device__ __forceinline__ const double* cdinv(const SlotDev& d) { return d.cheb_dinv; }
 };
 template <>
 struct SB<float> {
   static __device__ __forceinline__ float* blk(const SlotDev& d, int id) { return d.b32[id]; }
   static __device__ __forceinline__ const float* w(const SlotDev& d) { return d.a_w32; }
   static __device__ __forceinline__ const float* dinv(const SlotDev& d) { return d.dinv32; }
+  static __device__ __forceinline__ const float* cdinv(const SlotDev& d) { return d.cheb_dinv32; }
 };
 
 // rows per tile of the elementwise kernels
@@ -71,8 +73,8 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_spmm(const Slot
   T xi[C::V16], acc[C::V16];
   // own row (row 0 stands in for rows past the end; their lanes add nothing)
   load_chunk<T, C::V16>(x + (live ? row : 0) * KB + ch * C::V16, xi);
-  spmm_row<T, KB>(live, row, q, d.a_rp, d.a_split, d.a_col, SB<T>::w(d), (T)d.c_t, d.skip_w, x,
-                  xi, acc);
+  spmm_row<T, KB>(live, row, q, d.a_rp, d.a_split, d.a_col, SB<T>::w(d), (T)d.c_t, d.skip_w, 0,
+                  x, xi, acc);
   if (!live || q >= C::NCH) return;
   // lane q < NCH holds chunk q of the row
   const T sd = (T)d.s_diag;
@@ -111,7 +113,7 @@ __global__ void __launch_bounds__(kBlock) k_sl_cheb_first(const SlotDev* __restr
   const int64_t row = (int64_t)t.blk * E::RB + threadIdx.x / E::LPR;
   const int sub = threadIdx.x % E::LPR;
   if (row >= d.n) return;
-  const T sc = (T)(1.0 / d.cheb->theta) * SB<T>::dinv(d)[row];
+  const T sc = (T)(1.0 / *glob(&d.cheb->theta)) * glob(SB<T>::cdinv(d))[row];
   const int64_t o = row * KB + sub * E::VEC;
   auto v = ldv<T, E::VEC>(SB<T>::blk(d, r) + o);
 #pragma unroll
@@ -139,12 +141,12 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const
   T yi[C::V16], acc[C::V16];
   load_chunk<T, C::V16>(yi_p + (live ? row : 0) * KB + ch * C::V16, yi);
   spmm_row<T, KB>(live, row, q, d.a_rp, d.a_split, d.a_col, SB<T>::w(d), (T)d.c_t, d.skip_w,
-                  yi_p, yi, acc);
+                  d.cheb_w_only, yi_p, yi, acc);
   if (!live || q >= C::NCH) return;
   // lane q < NCH updates chunk q of the row
-  const T sd = (T)d.s_diag;
+  const T sd = (T)d.cheb_s_diag;
   const T alpha = (T)*glob(&d.cheb->alpha[k]);
-  const T beta = (T)*glob(&d.cheb->beta[k]) * glob(SB<T>::dinv(d))[row];
+  const T beta = (T)*glob(&d.cheb->beta[k]) * glob(SB<T>::cdinv(d))[row];
   const int64_t o = row * KB + q * C::V16;
   const auto ri = ldv<T, C::V16>(SB<T>::blk(d, r) + o);
   T* dp = SB<T>::blk(d, ddb);
@@ -186,7 +188,8 @@ template void sl_cheb_step<float>(const SlotDev*, const TileSet&, int, int, int,
 
 // ---------------------------------------------------------------------------
 // Residual R = AX - B X Lambda; W = R or D^-1 R (Jacobi); per tile: column
-// sums of |r|^2, |B x|^2 and x^T D x (3 KB partials).
+// sums of |r|^2, |B x|^2 and x^T D x with D the diagonal of the operator the
+// Chebyshev preconditioner inverts (3 KB partials).
 // ---------------------------------------------------------------------------
 
 template <int KB>
@@ -216,9 +219,8 @@ __global__ void __launch_bounds__(kBlock) k_sl_resid(const SlotDev* __restrict__
     const auto xi = ldv<double, VEC>(x + o);
     const auto ai = ldv<double, VEC>(ax + o);
     const double bi = d.bdiag ? d.bdiag[row] : 1.0;
-    const double dv = d.dinv[row];
-    const double di = jacobi ? dv : 1.0;
-    const double rdv = 1.0 / dv;
+    const double di = jacobi ? d.dinv[row] : 1.0;
+    const double rdv = 1.0 / d.cheb_dinv[row];
     VecT<double, VEC> wv;
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {

@@ -213,16 +213,18 @@ def test_k_range_errors(me):
 
 
 @pytest.mark.parametrize("name,K", [("square_2k", 4), ("sphere_3k", 16), ("torus_2500", 8)])
-@pytest.mark.parametrize("precond,deg", [("none", None), ("jacobi", None), ("chebyshev", 8),
-                                         ("chebyshev", 48), ("chebyshev", 256)])
-def test_embed_preconditioners(me, name, K, precond, deg):
-    """Every preconditioner reaches the same pairs (the converged result
-    does not depend on the preconditioner)."""
+@pytest.mark.parametrize("precond,deg,cop", [("none", None, None), ("jacobi", None, None),
+                                             ("chebyshev", 8, None), ("chebyshev", 48, None),
+                                             ("chebyshev", 256, None), ("chebyshev", 48, "full"),
+                                             ("chebyshev", 128, "full")])
+def test_embed_preconditioners(me, name, K, precond, deg, cop):
+    """Every preconditioner (Jacobi, Chebyshev on L + eps I or on A) reaches
+    the same pairs: the converged result does not depend on it."""
     g, ops = oracle_ops(name)
     lam_o, V_o = oracle.generalized_eigs(ops["A"], ops["b"], K)
     relgap = (lam_o[K] - lam_o[K - 1]) / lam_o[K - 1]
     tol = min(1e-6, 1e-5 * relgap / 4)
-    X, lam, info = me.embed(g, K, tol=tol, seed=3, precond=precond, cheb_degree=deg)
+    X, lam, info = me.embed(g, K, tol=tol, seed=3, precond=precond, cheb_degree=deg, cheb_op=cop)
     assert info["status"] == 0, info
     lam = _np(lam)
     np.testing.assert_array_less(np.abs(lam - lam_o[:K]) / np.abs(lam_o[:K]), 1e-6)
