@@ -123,8 +123,6 @@ def bench_batch(args) -> int:
     torch.cuda.synchronize()
     total_n = sum(g.n for g in graphs)
     opts = dict(precision=args.precision, seed=0, cheb_degree=args.cheb_degree)
-    if args.eps_tol is not None:
-        opts["eps_tol"] = args.eps_tol
     tol = 1e-6
     for w in range(args.warmup):
         t = time.perf_counter()
@@ -301,6 +299,8 @@ def main() -> int:
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     opts = dict(precision=args.precision, seed=0, cheb_degree=args.cheb_degree)
+    if args.eps_tol is not None:
+        opts["eps_tol"] = args.eps_tol
 
     def step():
         X, lam, info = me.embed(dcsr, K, tol=tol, **opts)

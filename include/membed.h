@@ -63,7 +63,8 @@ enum { ME_PRECOND_NONE = 0, ME_PRECOND_JACOBI = 1, ME_PRECOND_CHEBYSHEV = 2 };
  * inverse of L + eps I (one-hop entries only; spectrally within about mu |Q|
  * of A, and a third of the entries) or of A itself.  Any symmetric positive
  * definite preconditioner leaves the converged pairs unchanged; it only
- * changes the iteration count.  The eps solve always uses Q. */
+ * changes the iteration count.  The eps solve's preconditioner always
+ * inverts Q. */
 enum { ME_CHEB_LAPLACIAN = 0, ME_CHEB_FULL = 1 };
 
 /* Input graph W (Section 3.1), CSR, device memory, owned by the caller and
@@ -87,7 +88,7 @@ typedef struct {
   double eps_tol;     /* relative residual target of the eps solve (default 1e-8)   */
   int check_every;    /* iterations enqueued between host convergence reads (default 16) */
   uint64_t seed;      /* seed of the library's starting blocks (default 0)          */
-  int cheb_degree;    /* Chebyshev preconditioner degree, 2..256 (default 64)       */
+  int cheb_degree;    /* Chebyshev preconditioner degree, 2..256 (default 128)      */
   int cheb_op;        /* operator the Chebyshev preconditioner inverts in the
                          embedding solve: ME_CHEB_LAPLACIAN (default) or ME_CHEB_FULL */
 } me_opts;

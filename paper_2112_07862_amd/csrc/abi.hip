@@ -29,7 +29,7 @@ void me_opts_default(me_opts* o) {
   o->eps_tol = 1e-8;
   o->check_every = 16;
   o->seed = 0;
-  o->cheb_degree = 64;
+  o->cheb_degree = 128;
   o->cheb_op = ME_CHEB_LAPLACIAN;
 }
 

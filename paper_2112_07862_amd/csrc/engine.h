@@ -30,7 +30,7 @@ struct SlotDev {
   int nparts;       // reduction tiles
   int need;         // leading columns that must converge
   int deflate;      // keep the iterates orthogonal to the constant vector
-  int skip_w;       // operator uses only the T entries (Q)
+  int range;        // entries of the operator: all (A) or T only (Q)
   int kcopy;        // columns of x0 copied into the start block
   int k_out;        // columns written to out_x
   // operator Op in difference form: W entries w_ij, T entries
@@ -44,10 +44,10 @@ struct SlotDev {
   const double* bdiag;  // null: B = I
   const double* dinv;   // diag(Op)^-1 (Jacobi preconditioner)
   const float* dinv32;
-  // operator the Chebyshev preconditioner inverts: the same rows, restricted
-  // to the W entries when cheb_w_only (L + eps I), with its own diagonal
-  // shift and Jacobi scaling
-  int cheb_w_only;
+  // operator the Chebyshev preconditioner inverts: the same rows restricted
+  // to an entry range (all, W only or T only; T entries scaled by c_t), with
+  // its own diagonal shift and Jacobi scaling
+  int cheb_range;
   double cheb_s_diag;
   const double* cheb_dinv;
   const float* cheb_dinv32;

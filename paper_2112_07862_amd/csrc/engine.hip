@@ -23,6 +23,7 @@
 #include <cstring>
 
 #include "engine.h"
+#include "rowops.h"
 
 namespace me {
 
@@ -150,7 +151,7 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
   d.per = ((ceil_div(n, np) + 15) / 16) * 16;
   d.need = sp.need;
   d.deflate = sp.deflate;
-  d.skip_w = sp.op == OP_Q;
+  d.range = sp.op == OP_Q ? kRangeT : kRangeAll;
   d.kcopy = sp.x0 ? sp.kcopy : 0;
   d.k_out = sp.k_out;
   d.a_rp = g.a_rp;
@@ -165,7 +166,7 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
     d.dinv = g.dinv_s;
     d.dinv32 = g.dinv32_s;
     const bool lap = o_.cheb_op == ME_CHEB_LAPLACIAN;
-    d.cheb_w_only = lap;
+    d.cheb_range = lap ? kRangeW : kRangeAll;
     d.cheb_s_diag = g.eps;
     d.cheb_dinv = lap ? g.pdinv_s : g.dinv_s;
     d.cheb_dinv32 = lap ? g.pdinv32_s : g.dinv32_s;
@@ -175,7 +176,9 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
     d.bdiag = nullptr;
     d.dinv = g.qinv_s;
     d.dinv32 = g.qinv32_s;
-    d.cheb_w_only = 0;
+    // eps solve: the preconditioner inverts Q itself (the one-hop
+    // Laplacian is a poor stand-in: ten times the iterations)
+    d.cheb_range = kRangeT;
     d.cheb_s_diag = 0.0;
     d.cheb_dinv = g.qinv_s;
     d.cheb_dinv32 = g.qinv32_s;
@@ -330,10 +333,10 @@ void Engine::iteration(const TileSet& ts) {
         // and the block y_in (neighbour rows counted once), R, dd in, dd out,
         // y_out
         const double sz = cheb32_ ? 4.0 : 8.0;
-        const bool w_only = sh_[id].sp.op == OP_A && o_.cheb_op == ME_CHEB_LAPLACIAN;
-        const double nnz = sh_[id].sp.op == OP_Q ? (double)g.nnz_t
-                                                 : (w_only ? (double)g.nnz_w
-                                                           : (double)(g.nnz_w + g.nnz_t));
+        const int rg = hdev_[id].cheb_range;
+        const double nnz = rg == kRangeW ? (double)g.nnz_w
+                                         : (rg == kRangeT ? (double)g.nnz_t
+                                                          : (double)(g.nnz_w + g.nnz_t));
         cb += (4.0 + sz) * nnz + (double)g.n * (8.0 + sz) + 5.0 * (double)g.n * kb * sz;
       }
     }

@@ -64,10 +64,13 @@ __device__ __forceinline__ void stv(T* p, const VecT<T, V>& v) {
 // e + 2 EPL, ... (EPL = G / NCH entries per round), so the lanes of one
 // instruction that load the same neighbour row share its cache lines.
 // Entries before a_split are W entries (weight w_ij), the rest T entries
-// (stored weight 1/T_i + 1/T_j, scaled by c_t); skip_w keeps only the T
-// entries, w_only only the W entries.  Each lane accumulates its
+// (stored weight 1/T_i + 1/T_j, scaled by c_t); `range` selects all
+// entries, the W entries only or the T entries only.  Each lane accumulates its
 // chunk; a butterfly over the lanes of equal chunk leaves the row's chunk c
 // in every lane.  All lanes of the wave must call it (shuffles).
+// entry ranges of a row of the merged operator
+enum { kRangeAll = 0, kRangeW = 1, kRangeT = 2 };
+
 template <typename T, int KB>
 struct RowCfg {
   static constexpr int V16 = 16 / (int)sizeof(T);      // values per 16-byte chunk
@@ -85,8 +88,8 @@ __device__ __forceinline__ void spmm_row(bool live, int64_t row, int q,
                                          const int32_t* __restrict__ a_rp,
                                          const int32_t* __restrict__ a_split,
                                          const int32_t* __restrict__ a_col,
-                                         const T* __restrict__ a_w, T c_t, int skip_w,
-                                         int w_only, const T* __restrict__ x,
+                                         const T* __restrict__ a_w, T c_t, int range,
+                                         const T* __restrict__ x,
                                          const T (&xi)[RowCfg<T, KB>::V16],
                                          T (&acc)[RowCfg<T, KB>::V16]) {
   using C = RowCfg<T, KB>;
@@ -99,8 +102,8 @@ __device__ __forceinline__ void spmm_row(bool live, int64_t row, int q,
   int32_t s = 0, sp = 0, e = 0;
   if (live) {
     sp = spl[row];
-    s = skip_w ? sp : rp[row];
-    e = w_only ? sp : rp[row + 1];
+    s = range == kRangeT ? sp : rp[row];
+    e = range == kRangeW ? sp : rp[row + 1];
   }
 #pragma unroll
   for (int v = 0; v < V; ++v) acc[v] = 0;

@@ -40,7 +40,8 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_spmm(int64_t n, co
   const int ch = q % C::NCH;
   T xi[C::V16], acc[C::V16];
   load_chunk<T, C::V16>(x + (live ? row : 0) * KB + ch * C::V16, xi);
-  spmm_row<T, KB>(live, row, q, a_rp, a_split, a_col, a_w, c_t, skip_w, 0, x, xi, acc);
+  spmm_row<T, KB>(live, row, q, a_rp, a_split, a_col, a_w, c_t, skip_w ? kRangeT : kRangeAll, x,
+                  xi, acc);
   if (!live || q >= C::NCH) return;
   VecT<T, C::V16> o;
 #pragma unroll
