@@ -380,12 +380,8 @@ __global__ void k_uf_count_roots(int64_t n, int32_t* parent, int* roots) {
 // the start; level l+1 holds the unvisited neighbours of level l, ordered by
 // the position of their first (lowest-positioned) neighbour in level l and
 // then by node id -- exactly the order of a sequential search that scans
-// level l in order and each row's neighbours in increasing id.  In parallel:
-// every level-l node claims its unvisited neighbours and lowers their key to
-// its own position (atomic min); each node then counts the neighbours whose
-// key is its position, a block-wide scan turns the counts into offsets, and
-// each node writes its children in row (id) order.  Further components
-// follow, each started at its lowest unvisited node.
+// level l in order and each row's neighbours in increasing id.  Further
+// components follow, each started at its lowest unvisited node.
 // level[] and key[] change through device-scope atomics, which are performed
 // in L2; every read of them is an agent-scope atomic load so that no stale
 // L1 copy is used.
@@ -468,12 +464,31 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t* a, int32_t n, i
   return carry;
 }
 
+// Largest i < n with off[i] <= e (off strictly increasing, off[0] = 0).
+__device__ __forceinline__ int32_t find_owner(const int32_t* off, int32_t n, int32_t e) {
+  int32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // One component of the Cuthill-McKee order: perm[off] = start, levels from
-// lev0; key and cnt are n-int scratch (key = INT32_MAX for unvisited nodes).
+// lev0.  Scratch: key (n ints, INT32_MAX for unvisited nodes), eoff (n ints)
+// and ev, ei, ef (one int per edge).  Every level-l node claims its
+// unvisited neighbours and lowers their key to its own position (atomic
+// min); a child belongs to the node whose position is its key.  A narrow
+// level works on its frontier's edges in (frontier position, neighbour id)
+// order, one thread per edge, and an exclusive scan of the "my child" flags
+// over the edges places every child; a wide level (one thread per frontier
+// node) scans per-node child counts and each node writes its children in
+// row order.  Both give the sequential Cuthill-McKee order.
 // Returns the number of nodes placed; *last_lev receives the last level.
 __device__ __forceinline__ int64_t cm_component(const int64_t* __restrict__ rp,
                                                 const int32_t* __restrict__ col, int32_t* level,
-                                                int32_t* key, int32_t* cnt, int32_t* perm,
+                                                int32_t* key, int32_t* eoff, int32_t* ev,
+                                                int32_t* ei, int32_t* ef, int32_t* perm,
                                                 int64_t off, int32_t start, int32_t lev0,
                                                 int32_t* s_wave, int32_t* last_lev) {
   const int tid = threadIdx.x;
@@ -487,11 +502,55 @@ __device__ __forceinline__ int64_t cm_component(const int64_t* __restrict__ rp,
   for (;;) {
     const int32_t* fin = perm + off + placed - nin;
     int32_t* fout = perm + off + placed;
-    // claim unvisited neighbours; key = lowest claiming position
-    for (int32_t i = tid; i < nin; i += kBfsThreads) {
-      const int32_t u = fin[i];
-      for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
-        const int32_t v = col[t];
+    int32_t nout = 0;
+    if (nin >= kBfsThreads) {
+      // wide level: one thread per frontier node
+      for (int32_t i = tid; i < nin; i += kBfsThreads) {
+        const int32_t u = fin[i];
+        for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
+          const int32_t v = col[t];
+          int32_t lv = ld_coherent(&level[v]);
+          if (lv < 0) {
+            const int32_t old = atomicCAS(&level[v], -1, lev + 1);
+            lv = old < 0 ? lev + 1 : old;
+          }
+          if (lv == lev + 1) atomicMin(&key[v], i);
+        }
+      }
+      __syncthreads();
+      for (int32_t i = tid; i < nin; i += kBfsThreads) {
+        const int32_t u = fin[i];
+        int32_t c = 0;
+        for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
+          const int32_t v = col[t];
+          c += (ld_coherent(&level[v]) == lev + 1 && ld_coherent(&key[v]) == i) ? 1 : 0;
+        }
+        eoff[i] = c;
+      }
+      __syncthreads();
+      nout = block_exclusive_scan(eoff, nin, s_wave);
+      for (int32_t i = tid; i < nin; i += kBfsThreads) {
+        const int32_t u = fin[i];
+        int32_t j = eoff[i];
+        for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
+          const int32_t v = col[t];
+          if (ld_coherent(&level[v]) == lev + 1 && ld_coherent(&key[v]) == i) fout[j++] = v;
+        }
+      }
+    } else {
+      // narrow level: one thread per frontier edge
+      for (int32_t i = tid; i < nin; i += kBfsThreads) {
+        const int32_t u = fin[i];
+        eoff[i] = (int32_t)(rp[u + 1] - rp[u]);
+      }
+      __syncthreads();
+      const int32_t m = block_exclusive_scan(eoff, nin, s_wave);
+      for (int32_t e = tid; e < m; e += kBfsThreads) {
+        const int32_t i = find_owner(eoff, nin, e);
+        const int32_t u = fin[i];
+        const int32_t v = col[rp[u] + (e - eoff[i])];
+        ev[e] = v;
+        ei[e] = i;
         int32_t lv = ld_coherent(&level[v]);
         if (lv < 0) {
           const int32_t old = atomicCAS(&level[v], -1, lev + 1);
@@ -499,26 +558,17 @@ __device__ __forceinline__ int64_t cm_component(const int64_t* __restrict__ rp,
         }
         if (lv == lev + 1) atomicMin(&key[v], i);
       }
-    }
-    __syncthreads();
-    // own children per frontier node
-    for (int32_t i = tid; i < nin; i += kBfsThreads) {
-      const int32_t u = fin[i];
-      int32_t c = 0;
-      for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
-        const int32_t v = col[t];
-        c += (ld_coherent(&level[v]) == lev + 1 && ld_coherent(&key[v]) == i) ? 1 : 0;
+      __syncthreads();
+      for (int32_t e = tid; e < m; e += kBfsThreads) {
+        const int32_t v = ev[e];
+        ef[e] = (ld_coherent(&level[v]) == lev + 1 && ld_coherent(&key[v]) == ei[e]) ? 1 : 0;
       }
-      cnt[i] = c;
-    }
-    __syncthreads();
-    const int32_t nout = block_exclusive_scan(cnt, nin, s_wave);
-    for (int32_t i = tid; i < nin; i += kBfsThreads) {
-      const int32_t u = fin[i];
-      int32_t j = cnt[i];
-      for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
-        const int32_t v = col[t];
-        if (ld_coherent(&level[v]) == lev + 1 && ld_coherent(&key[v]) == i) fout[j++] = v;
+      __syncthreads();
+      // after the scan, edge e was flagged iff the next prefix differs
+      nout = block_exclusive_scan(ef, m, s_wave);
+      for (int32_t e = tid; e < m; e += kBfsThreads) {
+        const int32_t nxt = e + 1 < m ? ef[e + 1] : nout;
+        if (nxt != ef[e]) fout[ef[e]] = ev[e];
       }
     }
     __syncthreads();
@@ -551,7 +601,8 @@ __global__ void __launch_bounds__(kBfsThreads) k_pseudo_peripheral(int64_t n, co
 
 __global__ void __launch_bounds__(kBfsThreads) k_cm_order(int64_t n, const int64_t* rp,
                                                           const int32_t* col, int32_t* level,
-                                                          int32_t* key, int32_t* cnt,
+                                                          int32_t* key, int32_t* eoff,
+                                                          int32_t* ev, int32_t* ei, int32_t* ef,
                                                           const int32_t* start, int32_t* perm) {
   __shared__ int32_t s_wave[kBfsThreads / kWave];
   __shared__ int32_t s_min;
@@ -562,7 +613,8 @@ __global__ void __launch_bounds__(kBfsThreads) k_cm_order(int64_t n, const int64
   }
   __syncthreads();
   int32_t last = 0;
-  int64_t off = cm_component(rp, col, level, key, cnt, perm, 0, *start, 0, s_wave, &last);
+  int64_t off =
+      cm_component(rp, col, level, key, eoff, ev, ei, ef, perm, 0, *start, 0, s_wave, &last);
   // further components: the lowest unvisited node only grows
   int64_t ptr = 0;
   for (;;) {
@@ -578,7 +630,8 @@ __global__ void __launch_bounds__(kBfsThreads) k_cm_order(int64_t n, const int64
     const int32_t nxt = s_min;
     __syncthreads();
     if (nxt == INT32_MAX) break;
-    off += cm_component(rp, col, level, key, cnt, perm, off, nxt, last + 1, s_wave, &last);
+    off += cm_component(rp, col, level, key, eoff, ev, ei, ef, perm, off, nxt, last + 1, s_wave,
+                        &last);
   }
 }
 
@@ -600,19 +653,25 @@ static int locality_order(GraphOps* g, int32_t* perm, int32_t* iperm, hipStream_
     k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, iperm);
     return ME_OK;
   }
-  const size_t bytes = Arena::round((n + 2) * 4) * 3 + Arena::round(64);
+  const int64_t nnz = g->nnz_w;
+  const size_t bytes =
+      Arena::round((n + 2) * 4) * 3 + Arena::round((nnz + 2) * 4) * 3 + Arena::round(64);
   void* mem = nullptr;
   ME_TRY(hipMallocAsync(&mem, bytes, s));
   Arena a{(char*)mem, bytes, 0};
   int32_t* level = a.take<int32_t>(n + 2);
   int32_t* fa = a.take<int32_t>(n + 2);
   int32_t* fb = a.take<int32_t>(n + 2);
+  int32_t* ev = a.take<int32_t>(nnz + 2);
+  int32_t* ei = a.take<int32_t>(nnz + 2);
+  int32_t* ef = a.take<int32_t>(nnz + 2);
   int32_t* start = a.take<int32_t>(16);
   // pseudo-peripheral start, then the Cuthill-McKee order from it (fa, fb
-  // serve as the frontiers of the first search and as key / count scratch
-  // of the second)
+  // serve as the frontiers of the first search and as the key and frontier
+  // edge offsets of the second)
   k_pseudo_peripheral<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb, start);
-  k_cm_order<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb, start, perm);
+  k_cm_order<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb, ev, ei, ef, start,
+                                       perm);
   k_invert_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, perm, iperm);
   ME_TRY(hipFreeAsync(mem, s));
   return ME_OK;
