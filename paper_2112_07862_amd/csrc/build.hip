@@ -603,7 +603,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_cm_order(int64_t n, const int64
                                                           const int32_t* col, int32_t* level,
                                                           int32_t* key, int32_t* eoff,
                                                           int32_t* ev, int32_t* ei, int32_t* ef,
-                                                          const int32_t* start, int32_t* perm) {
+                                                          int32_t* start, int32_t* perm) {
   __shared__ int32_t s_wave[kBfsThreads / kWave];
   __shared__ int32_t s_min;
   const int tid = threadIdx.x;
@@ -633,6 +633,14 @@ __global__ void __launch_bounds__(kBfsThreads) k_cm_order(int64_t n, const int64
     off += cm_component(rp, col, level, key, eoff, ev, ei, ef, perm, off, nxt, last + 1, s_wave,
                         &last);
   }
+  if (tid == 0) start[1] = last;
+}
+
+// lev_s[i'] = breadth-first level of solver row i'
+__global__ void k_gather_level(int64_t n, const int32_t* perm, const int32_t* level,
+                               int32_t* lev_s) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) lev_s[i] = level[perm[i]];
 }
 
 __global__ void k_iota(int64_t n, int32_t* a) {
@@ -651,6 +659,7 @@ static int locality_order(GraphOps* g, int32_t* perm, int32_t* iperm, hipStream_
   if (n <= kDenseMaxN) {
     k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, perm);
     k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, iperm);
+    g->max_level = 0;
     return ME_OK;
   }
   const int64_t nnz = g->nnz_w;
@@ -673,6 +682,11 @@ static int locality_order(GraphOps* g, int32_t* perm, int32_t* iperm, hipStream_
   k_cm_order<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb, ev, ei, ef, start,
                                        perm);
   k_invert_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, perm, iperm);
+  k_gather_level<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, perm, level, g->lev_s);
+  int32_t hl[2] = {0, 0};
+  ME_TRY(hipMemcpyAsync(hl, start, 8, hipMemcpyDeviceToHost, s));
+  ME_TRY(hipStreamSynchronize(s));
+  g->max_level = hl[1];
   ME_TRY(hipFreeAsync(mem, s));
   return ME_OK;
 }
@@ -855,7 +869,7 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   b1 += Arena::round((n + 1) * 8) + Arena::round(n * 4);                            // t_rp, t_cnt
   b1 += 9 * Arena::round(n * 8) + 5 * Arena::round(n * 4);                          // per node
   b1 += Arena::round((n + 1) * 4) + Arena::round(n * 4);                            // a_rp, a_split
-  b1 += 2 * Arena::round(n * 4) + 4 * Arena::round(n * 8) + 4 * Arena::round(n * 4);  // solver order
+  b1 += 3 * Arena::round(n * 4) + 4 * Arena::round(n * 8) + 4 * Arena::round(n * 4);  // solver order
   b1 += Arena::round((n + 1) * 8);                                                  // offsets
   b1 += Arena::round(sizeof(int) * 64);
   void* mem1 = nullptr;
@@ -885,6 +899,7 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   g->a_rp = ar.take<int32_t>(n + 1);
   g->a_split = ar.take<int32_t>(n);
   g->perm = ar.take<int32_t>(n);
+  g->lev_s = ar.take<int32_t>(n);
   g->iperm = ar.take<int32_t>(n);
   g->qinv_s = ar.take<double>(n);
   g->b_s = ar.take<double>(n);

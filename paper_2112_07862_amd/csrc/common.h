@@ -123,6 +123,8 @@ struct GraphOps {
   float* invt32 = nullptr;
   // Solver order (locality permutation): solver row i' is user row perm[i'].
   int32_t* perm = nullptr;     // solver index -> user index
+  int32_t* lev_s = nullptr;    // breadth-first level of each solver row
+  int32_t max_level = 0;       // deepest level
   int32_t* iperm = nullptr;    // user index -> solver index
   double *qinv_s = nullptr, *b_s = nullptr, *dinv_s = nullptr, *pdinv_s = nullptr;
   float *qinv32_s = nullptr, *b32_s = nullptr, *dinv32_s = nullptr, *pdinv32_s = nullptr;

@@ -55,6 +55,13 @@ struct SlotDev {
   const int32_t* iperm;  // user row -> solver row
   const double* x0;      // user-order n x kcopy start columns (may be null)
   uint64_t seed;
+  // smooth start: column j < nsmooth is cos(pi (j + jfreq) (level + 1/2) /
+  // (max_level + 1)) plus a tenth of the seeded random column (null lev:
+  // random start)
+  const int32_t* lev;
+  int32_t max_lev;
+  int32_t jfreq;
+  int32_t nsmooth;
   double* out_x;         // user-order n x k_out output (may be null)
   double* out_lam;       // k_out
   double* b64[kNumBlk64];
@@ -146,6 +153,8 @@ struct SlotSpec {
   double lam_scale = 1.0;  // operator scale (replaces |lambda| near zero)
   uint64_t seed = 0;
   const double* x0 = nullptr;  // user-order n x kcopy (device)
+  int nsmooth = 0;             // leading columns of the start from the breadth-first levels
+  int jfreq = 0;               // frequency of column 0 of the smooth start
   int kcopy = 0;
   double* out_x = nullptr;  // user-order n x k_out (device)
   double* out_lam = nullptr;

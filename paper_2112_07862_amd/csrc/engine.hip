@@ -187,6 +187,10 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
   d.iperm = g.iperm;
   d.x0 = sp.x0;
   d.seed = sp.seed;
+  d.lev = (sp.nsmooth > 0 && g.max_level > 0) ? g.lev_s : nullptr;
+  d.max_lev = g.max_level;
+  d.jfreq = sp.jfreq;
+  d.nsmooth = sp.nsmooth;
   d.out_x = sp.out_x;
   d.out_lam = sp.out_lam;
   d.ctrl = d_ctrl_ + id;

@@ -26,6 +26,10 @@ SlotSpec eps_slot_spec(const GraphOps& g, const me_opts* o) {
   sp.cheb_b = g.cheb_b_q * 1.01;
   sp.lam_scale = g.maxden > 0 ? g.maxden : 1.0;
   sp.seed = o->seed ^ 0x51ED2701D5ull;
+  // smooth start: lambda_2(Q)'s vector varies along the manifold, like the
+  // level cosines of frequencies 1..4 (the constant is deflated)
+  sp.nsmooth = 4;
+  sp.jfreq = 1;
   return sp;
 }
 
@@ -44,6 +48,11 @@ SlotSpec embed_slot_spec(const GraphOps& g, int K, double tol, const me_opts* o,
   sp.seed = o->seed;
   sp.x0 = x0;
   sp.kcopy = x0 ? K : 0;
+  // a random start: level cosines fit only the modes along the search
+  // direction, and a partly smooth block converged more slowly than a
+  // random one on the manifold graphs measured
+  sp.nsmooth = 0;
+  sp.jfreq = 0;
   sp.out_x = X;
   sp.out_lam = lambda;
   sp.k_out = K;

@@ -714,8 +714,11 @@ void sl_to64(const SlotDev* sl, const TileSet& ts, int from32, int to64, hipStre
 // ---------------------------------------------------------------------------
 // Starting block: copies x0 (user order, n x kcopy) and fills the remaining
 // columns with a counter-based generator (SplitMix64 of seed and element
-// index, Steele, Lea & Flood 2014), uniform in [-1, 1).  Values depend only
-// on (seed, user row, column), not on the solver's node order.
+// index, Steele, Lea & Flood 2014), uniform in [-1, 1), or -- smooth start
+// -- with cos(pi f t) of the row's breadth-first depth t in (0, 1) plus a
+// tenth of that random value: on a manifold graph the depth from a
+// peripheral node is a coordinate along the manifold, and these cosines
+// approximate its lowest eigenvectors along that direction.
 // ---------------------------------------------------------------------------
 
 __device__ inline uint64_t splitmix64(uint64_t z) {
@@ -744,7 +747,13 @@ __global__ void __launch_bounds__(kBlock) k_sl_fill_start(const SlotDev* __restr
       v.v[q] = d.x0[u * d.kcopy + j];
     } else {
       const uint64_t h = splitmix64(d.seed * 0x2545F4914F6CDD1Dull + (uint64_t)(u * KB + j));
-      v.v[q] = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+      const double rnd = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+      if (d.lev && j < d.nsmooth) {
+        const double t = ((double)d.lev[row] + 0.5) / ((double)d.max_lev + 1.0);
+        v.v[q] = cos(3.141592653589793 * (double)(j + d.jfreq) * t) + 0.1 * rnd;
+      } else {
+        v.v[q] = rnd;
+      }
     }
   }
   stv<double, VEC>(d.b64[BX] + row * KB + sub * VEC, v);
