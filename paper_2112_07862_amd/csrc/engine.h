@@ -20,8 +20,8 @@ struct ChebCoef {
 };
 
 // Dense blocks of a slot (row-major n x kb).
-enum Blk64 { BX = 0, BAX, BW, BAW, BP, BAP, BR, BY, BDD, kNumBlk64 };
-enum Blk32 { BR32 = 0, BW32, BY32, BDD32, kNumBlk32 };
+enum Blk64 { BX = 0, BAX, BW, BAW, BP, BAP, BR, BY, kNumBlk64 };
+enum Blk32 { BR32 = 0, BW32, BY32, kNumBlk32 };
 
 // Device view of one slot.
 struct SlotDev {
@@ -105,10 +105,11 @@ struct TileSet {
 // certificate passes); otherwise such slots are skipped.
 template <typename T>
 void sl_spmm(const SlotDev* sl, const TileSet& ts, int in, int out, int cert, hipStream_t s);
+// y <- D^-1 R / theta, yprev <- 0; then y_{k+1} into yout (which holds y_{k-1})
 template <typename T>
-void sl_cheb_first(const SlotDev* sl, const TileSet& ts, int r, int y, int dd, hipStream_t s);
+void sl_cheb_first(const SlotDev* sl, const TileSet& ts, int r, int y, int yprev, hipStream_t s);
 template <typename T>
-void sl_cheb_step(const SlotDev* sl, const TileSet& ts, int k, int r, int yin, int yout, int dd,
+void sl_cheb_step(const SlotDev* sl, const TileSet& ts, int k, int r, int yin, int yout,
                   hipStream_t s);
 // R = AX - B X Lambda (-> block w unless w < 0; Jacobi-scaled if jacobi),
 // per-tile sums of |r|^2, |Bx|^2, x^T D x.

@@ -334,31 +334,31 @@ void Engine::iteration(const TileSet& ts) {
         const GraphOps& g = *sh_[id].sp.g;
         // algorithmic bytes of one step: column index and weight of every
         // entry of the preconditioner's operator, row bounds (8 B), D^-1_i,
-        // and the block y_in (neighbour rows counted once), R, dd in, dd out,
-        // y_out
+        // and the blocks y_k (neighbour rows counted once), y_{k-1}, R read
+        // and y_{k+1} written
         const double sz = cheb32_ ? 4.0 : 8.0;
         const int rg = hdev_[id].cheb_range;
         const double nnz = rg == kRangeW ? (double)g.nnz_w
                                          : (rg == kRangeT ? (double)g.nnz_t
                                                           : (double)(g.nnz_w + g.nnz_t));
-        cb += (4.0 + sz) * nnz + (double)g.n * (8.0 + sz) + 5.0 * (double)g.n * kb * sz;
+        cb += (4.0 + sz) * nnz + (double)g.n * (8.0 + sz) + 4.0 * (double)g.n * kb * sz;
       }
     }
-    const int w = cheb32_ ? BW32 : BW, y = cheb32_ ? BY32 : BY, dd = cheb32_ ? BDD32 : BDD;
+    const int w = cheb32_ ? BW32 : BW, y = cheb32_ ? BY32 : BY;
     const int r = cheb32_ ? BR32 : BR;
     int cur = ((deg - 1) % 2 == 0) ? w : y;
     int nxt = cur == w ? y : w;
     if (cheb32_) {
       sl_to32(d_slots_, ts, BR, BR32, s_);
-      sl_cheb_first<float>(d_slots_, ts, r, cur, dd, s_);
+      sl_cheb_first<float>(d_slots_, ts, r, cur, nxt, s_);
     } else {
-      sl_cheb_first<double>(d_slots_, ts, r, cur, dd, s_);
+      sl_cheb_first<double>(d_slots_, ts, r, cur, nxt, s_);
     }
     {
       KScope ks(tm ? KT_CHEB : -1, s_, (deg - 1) * cb, tag_, deg - 1);
       for (int k = 1; k < deg; ++k) {
-        if (cheb32_) sl_cheb_step<float>(d_slots_, ts, k, r, cur, nxt, dd, s_);
-        else sl_cheb_step<double>(d_slots_, ts, k, r, cur, nxt, dd, s_);
+        if (cheb32_) sl_cheb_step<float>(d_slots_, ts, k, r, cur, nxt, s_);
+        else sl_cheb_step<double>(d_slots_, ts, k, r, cur, nxt, s_);
         std::swap(cur, nxt);
       }
     }

@@ -97,15 +97,18 @@ template void sl_spmm<double>(const SlotDev*, const TileSet&, int, int, int, hip
 
 // ---------------------------------------------------------------------------
 // Chebyshev preconditioner: approximate solve of Op y = R with Jacobi
-// scaling D, spectrum of D^-1 Op taken as [a, b], theta = (a + b) / 2:
-//   y_1 = dd_1 = D^-1 R / theta,
-//   dd_{k+1} = alpha_k dd_k + beta_k D^-1 (R - Op y_k),  y_{k+1} = y_k + dd_{k+1}.
+// scaling D, spectrum of D^-1 Op taken as [a, b], theta = (a + b) / 2, in
+// three-term form (y_0 = 0):
+//   y_1 = D^-1 R / theta,
+//   y_{k+1} = y_k + alpha_k (y_k - y_{k-1}) + beta_k D^-1 (R - Op y_k).
+// Step k gathers y_k and overwrites y_{k-1} with y_{k+1} (each row reads its
+// own y_{k-1} before writing it; neighbours only read y_k).
 // ---------------------------------------------------------------------------
 
 template <typename T, int KB>
 __global__ void __launch_bounds__(kBlock) k_sl_cheb_first(const SlotDev* __restrict__ sl,
                                                           const Tile* __restrict__ tiles, int r,
-                                                          int y, int dd) {
+                                                          int y, int yprev) {
   using E = ElemCfg<T, KB>;
   const Tile t = tiles[blockIdx.x];
   const SlotDev& d = sl[t.slot];
@@ -119,14 +122,16 @@ __global__ void __launch_bounds__(kBlock) k_sl_cheb_first(const SlotDev* __restr
 #pragma unroll
   for (int q = 0; q < E::VEC; ++q) v.v[q] *= sc;
   stv<T, E::VEC>(SB<T>::blk(d, y) + o, v);
-  stv<T, E::VEC>(SB<T>::blk(d, dd) + o, v);
+#pragma unroll
+  for (int q = 0; q < E::VEC; ++q) v.v[q] = 0;
+  stv<T, E::VEC>(SB<T>::blk(d, yprev) + o, v);
 }
 
 template <typename T, int KB>
 __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const SlotDev* __restrict__ sl,
                                                          const Tile* __restrict__ tiles,
                                                          int64_t ntiles, int k, int r, int yin,
-                                                         int yout, int ddb) {
+                                                         int yout) {
   using C = RowCfg<T, KB>;
   const int64_t b = xcd_block(ntiles);
   if (b >= ntiles) return;
@@ -149,41 +154,38 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const
   const T beta = (T)*glob(&d.cheb->beta[k]) * glob(SB<T>::cdinv(d))[row];
   const int64_t o = row * KB + q * C::V16;
   const auto ri = ldv<T, C::V16>(SB<T>::blk(d, r) + o);
-  T* dp = SB<T>::blk(d, ddb);
-  auto di = ldv<T, C::V16>(dp + o);
-  VecT<T, C::V16> yo;
+  T* yo_p = SB<T>::blk(d, yout);
+  auto yo = ldv<T, C::V16>(yo_p + o);  // y_{k-1} of this row
 #pragma unroll
   for (int v = 0; v < C::V16; ++v) {
     const T res = ri.v[v] - (acc[v] + sd * yi[v]);
-    di.v[v] = alpha * di.v[v] + beta * res;
-    yo.v[v] = yi[v] + di.v[v];
+    yo.v[v] = yi[v] + (alpha * (yi[v] - yo.v[v]) + beta * res);
   }
-  stv<T, C::V16>(dp + o, di);
-  stv<T, C::V16>(SB<T>::blk(d, yout) + o, yo);
+  stv<T, C::V16>(yo_p + o, yo);
 }
 
 template <typename T>
-void sl_cheb_first(const SlotDev* sl, const TileSet& ts, int r, int y, int dd, hipStream_t s) {
+void sl_cheb_first(const SlotDev* sl, const TileSet& ts, int r, int y, int yprev, hipStream_t s) {
   const Tile* tl = sizeof(T) == 8 ? ts.elem64 : ts.elem32;
   const int64_t nt = sizeof(T) == 8 ? ts.n_elem64 : ts.n_elem32;
   if (nt == 0) return;
-  ME_DISPATCH_KB(ts.kb, { k_sl_cheb_first<T, KB><<<nt, kBlock, 0, s>>>(sl, tl, r, y, dd); });
+  ME_DISPATCH_KB(ts.kb, { k_sl_cheb_first<T, KB><<<nt, kBlock, 0, s>>>(sl, tl, r, y, yprev); });
 }
 template <typename T>
-void sl_cheb_step(const SlotDev* sl, const TileSet& ts, int k, int r, int yin, int yout, int dd,
+void sl_cheb_step(const SlotDev* sl, const TileSet& ts, int k, int r, int yin, int yout,
                   hipStream_t s) {
   if (ts.n_gather == 0) return;
   ME_DISPATCH_KB(ts.kb, {
     static_assert(RowCfg<T, KB>::ROWS == kGatherRows, "gather tile rows");
     k_sl_cheb_step<T, KB><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
-        sl, ts.gather, ts.n_gather, k, r, yin, yout, dd);
+        sl, ts.gather, ts.n_gather, k, r, yin, yout);
   });
 }
 template void sl_cheb_first<double>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
 template void sl_cheb_first<float>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
-template void sl_cheb_step<double>(const SlotDev*, const TileSet&, int, int, int, int, int,
+template void sl_cheb_step<double>(const SlotDev*, const TileSet&, int, int, int, int,
                                    hipStream_t);
-template void sl_cheb_step<float>(const SlotDev*, const TileSet&, int, int, int, int, int,
+template void sl_cheb_step<float>(const SlotDev*, const TileSet&, int, int, int, int,
                                   hipStream_t);
 
 // ---------------------------------------------------------------------------
