@@ -736,37 +736,43 @@ __global__ void k_qdiag(int64_t n, const int64_t* t_rp, const int32_t* t_col, co
 // Merged difference-form operator rows in the solver order: solver row i'
 // is user row o = perm[i'], entries [W columns | T columns] in the user
 // row's order, columns renumbered by iperm.
+// W and T row lengths of the rows in solver order
 __global__ void k_row_len_perm(int64_t n, const int32_t* perm, const int64_t* w_rp,
-                               const int64_t* t_rp, int32_t* len) {
+                               const int64_t* t_rp, int32_t* wlen, int32_t* tlen) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int32_t o = perm[i];
-  len[i] = (int32_t)((w_rp[o + 1] - w_rp[o]) + (t_rp[o + 1] - t_rp[o]));
+  wlen[i] = (int32_t)(w_rp[o + 1] - w_rp[o]);
+  tlen[i] = (int32_t)(t_rp[o + 1] - t_rp[o]);
 }
 
-__global__ void k_pack_perm(int64_t n, const int32_t* perm, const int32_t* iperm,
-                            const int64_t* off, const int64_t* w_rp, const int32_t* w_col,
-                            const double* w_val, const int64_t* t_rp, const int32_t* t_col,
-                            const double* invt, int32_t* a_rp, int32_t* a_split,
-                            int32_t* a_col, double* a_w, float* a_w32) {
+// The operator in solver order as two CSR blocks in one array: the W entries
+// of all rows ([a_rp[i], a_rp[i+1]), weight w_ij), then the T entries of all
+// rows ([a_tp[i], a_tp[i+1]), stored weight 1/T_i + 1/T_j).  A solve that
+// reads one kind of entry reads whole cache lines of it.
+__global__ void k_pack_perm(int64_t n, int64_t nnz_w, const int32_t* perm, const int32_t* iperm,
+                            const int64_t* woff, const int64_t* toff, const int64_t* w_rp,
+                            const int32_t* w_col, const double* w_val, const int64_t* t_rp,
+                            const int32_t* t_col, const double* invt, int32_t* a_rp,
+                            int32_t* a_tp, int32_t* a_col, double* a_w, float* a_w32) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i > n) return;
-  const int64_t start = off[i];
-  a_rp[i] = (int32_t)start;
+  const int64_t ws = woff[i], ts = nnz_w + toff[i];
+  a_rp[i] = (int32_t)ws;
+  a_tp[i] = (int32_t)ts;
   if (i == n) return;
   const int32_t o = perm[i];
   const int64_t nw = w_rp[o + 1] - w_rp[o];
-  a_split[i] = (int32_t)(start + nw);
   for (int64_t t = 0; t < nw; ++t) {
-    a_col[start + t] = iperm[w_col[w_rp[o] + t]];
+    a_col[ws + t] = iperm[w_col[w_rp[o] + t]];
     const double v = w_val[w_rp[o] + t];
-    a_w[start + t] = v;
-    a_w32[start + t] = (float)v;
+    a_w[ws + t] = v;
+    a_w32[ws + t] = (float)v;
   }
   // T entries: weight 1/T_i + 1/T_j of the two-hop term (eq. (Q), reading R1)
   const int64_t tb = t_rp[o], te = t_rp[o + 1];
   for (int64_t t = tb; t < te; ++t) {
-    const int64_t k = start + nw + (t - tb);
+    const int64_t k = ts + (t - tb);
     a_col[k] = iperm[t_col[t]];
     const double q = invt[o] + invt[t_col[t]];
     a_w[k] = q;
@@ -868,9 +874,9 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   b1 += Arena::round((n + 1) * 8) + Arena::round(nnz * 4) + Arena::round(nnz * 8);  // W
   b1 += Arena::round((n + 1) * 8) + Arena::round(n * 4);                            // t_rp, t_cnt
   b1 += 9 * Arena::round(n * 8) + 5 * Arena::round(n * 4);                          // per node
-  b1 += Arena::round((n + 1) * 4) + Arena::round(n * 4);                            // a_rp, a_split
+  b1 += 2 * Arena::round((n + 1) * 4);                                              // a_rp, a_tp
   b1 += 3 * Arena::round(n * 4) + 4 * Arena::round(n * 8) + 4 * Arena::round(n * 4);  // solver order
-  b1 += Arena::round((n + 1) * 8);                                                  // offsets
+  b1 += 2 * Arena::round((n + 1) * 8);                                              // offsets
   b1 += Arena::round(sizeof(int) * 64);
   void* mem1 = nullptr;
   ME_TRY(hipMallocAsync(&mem1, b1, s));
@@ -897,7 +903,7 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   g->invt32 = ar.take<float>(n);
   g->qinv32 = ar.take<float>(n);
   g->a_rp = ar.take<int32_t>(n + 1);
-  g->a_split = ar.take<int32_t>(n);
+  g->a_tp = ar.take<int32_t>(n + 1);
   g->perm = ar.take<int32_t>(n);
   g->lev_s = ar.take<int32_t>(n);
   g->iperm = ar.take<int32_t>(n);
@@ -909,7 +915,8 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   g->b32_s = ar.take<float>(n);
   g->dinv32_s = ar.take<float>(n);
   g->pdinv32_s = ar.take<float>(n);
-  int64_t* aoff = ar.take<int64_t>(n + 1);
+  int64_t* woff = ar.take<int64_t>(n + 1);
+  int64_t* toff = ar.take<int64_t>(n + 1);
   int* dflags = ar.take<int>(64);
   if (!dflags) return ME_ERR_HIP;
   g->scratch_d = scratch_d;
@@ -996,13 +1003,14 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
                                                  g->qinv, g->qinv32, maxden_bits);
   // locality order of the solver and the packed operator in that order
   ME_TRY_STATUS(locality_order(g, g->perm, g->iperm, s));
-  int32_t* rowlen = reinterpret_cast<int32_t*>(g->r);  // n int32 fit in n doubles
-  k_row_len_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->w_rp, g->t_rp, rowlen);
-  scan_counts(n, rowlen, aoff, tile_tmp, s);
-  k_pack_perm<<<ceil_div(n + 1, kBlock), kBlock, 0, s>>>(n, g->perm, g->iperm, aoff, g->w_rp,
-                                                         g->w_col, g->w_val, g->t_rp, g->t_col,
-                                                         g->invt, g->a_rp, g->a_split, g->a_col,
-                                                         g->a_w, g->a_w32);
+  int32_t* wlen = reinterpret_cast<int32_t*>(g->r);  // 2n int32 fit in n doubles
+  int32_t* tlen = wlen + n;
+  k_row_len_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->w_rp, g->t_rp, wlen, tlen);
+  scan_counts(n, wlen, woff, tile_tmp, s);
+  scan_counts(n, tlen, toff, tile_tmp, s);
+  k_pack_perm<<<ceil_div(n + 1, kBlock), kBlock, 0, s>>>(
+      n, nnz, g->perm, g->iperm, woff, toff, g->w_rp, g->w_col, g->w_val, g->t_rp, g->t_col,
+      g->invt, g->a_rp, g->a_tp, g->a_col, g->a_w, g->a_w32);
   k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->qinv, g->qinv_s,
                                                        g->qinv32_s);
   int hroots = 0;

@@ -36,7 +36,7 @@ struct SlotDev {
   // operator Op in difference form: W entries w_ij, T entries
   // c_t (1/T_i + 1/T_j) (a_w holds both weights), diagonal shift s_diag
   const int32_t* a_rp;
-  const int32_t* a_split;
+  const int32_t* a_tp;
   const int32_t* a_col;
   const double* a_w;
   const float* a_w32;

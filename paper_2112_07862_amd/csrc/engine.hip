@@ -155,7 +155,7 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
   d.kcopy = sp.x0 ? sp.kcopy : 0;
   d.k_out = sp.k_out;
   d.a_rp = g.a_rp;
-  d.a_split = g.a_split;
+  d.a_tp = g.a_tp;
   d.a_col = g.a_col;
   d.a_w = g.a_w;
   d.a_w32 = g.a_w32;

@@ -63,9 +63,10 @@ __device__ __forceinline__ void stv(T* p, const VecT<T, V>& v) {
 // lane q takes chunk c = q % NCH of the entries e = q / NCH, e + EPL,
 // e + 2 EPL, ... (EPL = G / NCH entries per round), so the lanes of one
 // instruction that load the same neighbour row share its cache lines.
-// Entries before a_split are W entries (weight w_ij), the rest T entries
-// (stored weight 1/T_i + 1/T_j, scaled by c_t); `range` selects all
-// entries, the W entries only or the T entries only.  Each lane accumulates its
+// Row i has W entries [a_rp[i], a_rp[i+1]) (weight w_ij) and T entries
+// [a_tp[i], a_tp[i+1]) (stored weight 1/T_i + 1/T_j, scaled by c_t) in
+// separate blocks of a_col / a_w; `range` selects both (the W entries come
+// first in the row's sequence), the W entries only or the T entries only.  Each lane accumulates its
 // chunk; a butterfly over the lanes of equal chunk leaves the row's chunk c
 // in every lane.  All lanes of the wave must call it (shuffles).
 // entry ranges of a row of the merged operator
@@ -86,7 +87,7 @@ struct RowCfg {
 template <typename T, int KB>
 __device__ __forceinline__ void spmm_row(bool live, int64_t row, int q,
                                          const int32_t* __restrict__ a_rp,
-                                         const int32_t* __restrict__ a_split,
+                                         const int32_t* __restrict__ a_tp,
                                          const int32_t* __restrict__ a_col,
                                          const T* __restrict__ a_w, T c_t, int range,
                                          const T* __restrict__ x,
@@ -96,30 +97,39 @@ __device__ __forceinline__ void spmm_row(bool live, int64_t row, int q,
   constexpr int V = C::V16, EPL = C::EPL, UNR = C::UNR;
   const int ch = q % C::NCH, e0 = q / C::NCH;
   const ME_GLOBAL int32_t* rp = glob(a_rp);
-  const ME_GLOBAL int32_t* spl = glob(a_split);
+  const ME_GLOBAL int32_t* tp = glob(a_tp);
   const ME_GLOBAL int32_t* cl = glob(a_col);
   const ME_GLOBAL T* wt = glob(a_w);
-  int32_t s = 0, sp = 0, e = 0;
+  // the row's entries as one sequence: positions [0, nw) are W entries at
+  // ws + k, positions [nw, len) T entries at ts + (k - nw)
+  int32_t ws = 0, nw = 0, ts = 0, len = 0;
   if (live) {
-    sp = spl[row];
-    s = range == kRangeT ? sp : rp[row];
-    e = range == kRangeW ? sp : rp[row + 1];
+    if (range != kRangeT) {
+      ws = rp[row];
+      nw = rp[row + 1] - ws;
+    }
+    len = nw;
+    if (range != kRangeW) {
+      ts = tp[row] - nw;
+      len += tp[row + 1] - tp[row];
+    }
   }
 #pragma unroll
   for (int v = 0; v < V; ++v) acc[v] = 0;
   // rounds of EPL entries; loop to the wave's longest row
-  int32_t rounds = (e - s + EPL - 1) / EPL;
+  int32_t rounds = (len + EPL - 1) / EPL;
   for (int o = kWave / 2; o > 0; o >>= 1) rounds = max(rounds, __shfl_xor(rounds, o));
   for (int32_t r = 0; r < rounds; r += UNR) {
     int32_t c[UNR];
     T cf[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      const int32_t k = s + (r + u) * EPL + e0;
-      const bool ok = k < e;
-      c[u] = ok ? cl[k] : -1;
-      const T w = ok ? wt[k] : (T)0;
-      cf[u] = k < sp ? w : c_t * w;
+      const int32_t k = (r + u) * EPL + e0;
+      const bool ok = k < len, isw = k < nw;
+      const int32_t at = (isw ? ws : ts) + k;
+      c[u] = ok ? cl[at] : -1;
+      const T w = ok ? wt[at] : (T)0;
+      cf[u] = isw ? w : c_t * w;
     }
     T xj[UNR][V];
 #pragma unroll

@@ -73,7 +73,7 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_spmm(const Slot
   T xi[C::V16], acc[C::V16];
   // own row (row 0 stands in for rows past the end; their lanes add nothing)
   load_chunk<T, C::V16>(x + (live ? row : 0) * KB + ch * C::V16, xi);
-  spmm_row<T, KB>(live, row, q, d.a_rp, d.a_split, d.a_col, SB<T>::w(d), (T)d.c_t, d.range, x,
+  spmm_row<T, KB>(live, row, q, d.a_rp, d.a_tp, d.a_col, SB<T>::w(d), (T)d.c_t, d.range, x,
                   xi, acc);
   if (!live || q >= C::NCH) return;
   // lane q < NCH holds chunk q of the row
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const
   const int ch = q % C::NCH;
   T yi[C::V16], acc[C::V16];
   load_chunk<T, C::V16>(yi_p + (live ? row : 0) * KB + ch * C::V16, yi);
-  spmm_row<T, KB>(live, row, q, d.a_rp, d.a_split, d.a_col, SB<T>::w(d), (T)d.c_t,
+  spmm_row<T, KB>(live, row, q, d.a_rp, d.a_tp, d.a_col, SB<T>::w(d), (T)d.c_t,
                   d.cheb_range, yi_p, yi, acc);
   if (!live || q >= C::NCH) return;
   // lane q < NCH updates chunk q of the row

@@ -24,7 +24,7 @@ namespace me {
 // slice of the row.
 template <typename T, int KB>
 __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_spmm(int64_t n, const int32_t* __restrict__ a_rp,
-                                                 const int32_t* __restrict__ a_split,
+                                                 const int32_t* __restrict__ a_tp,
                                                  const int32_t* __restrict__ a_col,
                                                  const T* __restrict__ a_w, T c_t, T s_diag,
                                                  int skip_w, const T* __restrict__ x,
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_spmm(int64_t n, co
   const int ch = q % C::NCH;
   T xi[C::V16], acc[C::V16];
   load_chunk<T, C::V16>(x + (live ? row : 0) * KB + ch * C::V16, xi);
-  spmm_row<T, KB>(live, row, q, a_rp, a_split, a_col, a_w, c_t, skip_w ? kRangeT : kRangeAll, x,
+  spmm_row<T, KB>(live, row, q, a_rp, a_tp, a_col, a_w, c_t, skip_w ? kRangeT : kRangeAll, x,
                   xi, acc);
   if (!live || q >= C::NCH) return;
   VecT<T, C::V16> o;
@@ -68,7 +68,7 @@ void launch_spmm(const GraphOps& g, int kb, OpKind op, const T* x, T* y, const i
   const int skip_w = op == OP_Q;
   ME_DISPATCH_KB(kb, {
     const int64_t grid = xcd_grid(ceil_div(g.n, RowCfg<T, KB>::ROWS));
-    k_spmm<T, KB><<<grid, RowCfg<T, KB>::THREADS, 0, s>>>(g.n, g.a_rp, g.a_split, g.a_col, OpArrays<T>::w(g),
+    k_spmm<T, KB><<<grid, RowCfg<T, KB>::THREADS, 0, s>>>(g.n, g.a_rp, g.a_tp, g.a_col, OpArrays<T>::w(g),
                                           c_t, s_diag, skip_w, x, y, done);
   });
 }
