@@ -66,6 +66,12 @@ enum { ME_PRECOND_NONE = 0, ME_PRECOND_JACOBI = 1, ME_PRECOND_CHEBYSHEV = 2 };
  * changes the iteration count.  The eps solve's preconditioner always
  * inverts Q. */
 enum { ME_CHEB_LAPLACIAN = 0, ME_CHEB_FULL = 1 };
+/* Addressing of the operator-product kernels.  ME_ADDR_AUTO (default) uses
+ * 32-bit buffer offsets whenever every array of a solve is below 2 GiB and
+ * 64-bit global addresses otherwise; ME_ADDR_GLOBAL always uses the 64-bit
+ * form.  Both visit the entries in the same order, so the results are the
+ * same; the option exists to exercise the large-graph form on small graphs. */
+enum { ME_ADDR_AUTO = 0, ME_ADDR_GLOBAL = 1 };
 
 /* Input graph W (Section 3.1), CSR, device memory, owned by the caller and
  * only read during the call.  rowptr int64[n+1] (rowptr[0] = 0), col int32[nnz]
@@ -91,6 +97,7 @@ typedef struct {
   int cheb_degree;    /* Chebyshev preconditioner degree, 2..256 (default 128)      */
   int cheb_op;        /* operator the Chebyshev preconditioner inverts in the
                          embedding solve: ME_CHEB_LAPLACIAN (default) or ME_CHEB_FULL */
+  int addressing;     /* ME_ADDR_AUTO (default) or ME_ADDR_GLOBAL                     */
 } me_opts;
 
 /* Per-solve report.  Times are host wall-clock milliseconds of the phases. */

@@ -17,6 +17,14 @@ void free_graph_ops(GraphOps& g) {
 
 static void free_ops(GraphOps& g) { free_graph_ops(g); }
 
+bool me::opts_valid(const me_opts& o) {
+  return o.max_iter >= 1 && o.eps_max_iter >= 1 && o.check_every >= 1 && o.precond >= 0 &&
+         o.precond <= 2 && (o.precision == ME_FP64 || o.precision == ME_MIXED) &&
+         o.eps_tol > 0 && (o.cheb_op == ME_CHEB_LAPLACIAN || o.cheb_op == ME_CHEB_FULL) &&
+         (o.addressing == ME_ADDR_AUTO || o.addressing == ME_ADDR_GLOBAL) &&
+         (o.precond != ME_PRECOND_CHEBYSHEV ||
+          (o.cheb_degree >= 2 && o.cheb_degree <= kMaxChebDegree));
+}
 
 extern "C" {
 
@@ -31,6 +39,7 @@ void me_opts_default(me_opts* o) {
   o->seed = 0;
   o->cheb_degree = 128;
   o->cheb_op = ME_CHEB_LAPLACIAN;
+  o->addressing = ME_ADDR_AUTO;
 }
 
 const char* me_status_string(int st) {
@@ -52,14 +61,6 @@ const char* me_status_string(int st) {
   }
 }
 
-
-static bool opts_valid(const me_opts& o) {
-  return o.max_iter >= 1 && o.eps_max_iter >= 1 && o.check_every >= 1 && o.precond >= 0 &&
-         o.precond <= 2 && (o.precision == ME_FP64 || o.precision == ME_MIXED) &&
-         o.eps_tol > 0 && (o.cheb_op == ME_CHEB_LAPLACIAN || o.cheb_op == ME_CHEB_FULL) &&
-         (o.precond != ME_PRECOND_CHEBYSHEV ||
-          (o.cheb_degree >= 2 && o.cheb_degree <= kMaxChebDegree));
-}
 
 int me_build_graph_ops(const me_csr* W, const me_opts* opts, void* stream, me_graph_ops** out,
                        me_info* info) {

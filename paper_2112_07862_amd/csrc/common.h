@@ -31,6 +31,8 @@ constexpr int kDenseMaxN = 48;       // graphs up to this size are solved densel
 constexpr int kPartialBlocks = 256;  // grid of the reducing streaming kernels
 constexpr int kMaxChebDegree = 256;  // largest Chebyshev preconditioner degree
 constexpr int kXcd = 8;              // accelerator complex dies (one L2 each)
+// largest array (bytes) the buffer-resource kernels address with 32-bit offsets
+constexpr int64_t kBufMaxBytes = (int64_t)1 << 31;
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -147,6 +149,8 @@ struct GraphOps {
 
 // ---- launchers: build.hip -------------------------------------------------
 int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g, me_info* info);
+// option ranges of me_opts (shared by every entry point that takes them)
+bool opts_valid(const me_opts& o);
 int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g);
 int build_post(GraphOps* g, double eps, int eps_iters, hipStream_t s);
 

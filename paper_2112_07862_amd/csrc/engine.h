@@ -40,6 +40,7 @@ struct SlotDev {
   const int32_t* a_col;
   const double* a_w;
   const float* a_w32;
+  int64_t nnz_ops;  // entries of a_col / a_w (W and T)
   double c_t, s_diag;
   const double* bdiag;  // null: B = I
   const double* dinv;   // diag(Op)^-1 (Jacobi preconditioner)
@@ -95,6 +96,7 @@ struct TileSet {
   const Tile* elem32 = nullptr;    // kBlock / LPR(float, kb) rows per tile
   const Tile* red = nullptr;       // reduction tiles (slot.per rows)
   int64_t n_gather = 0, n_elem64 = 0, n_elem32 = 0, n_red = 0;
+  bool buf = false;                // every array below kBufMaxBytes (buffer loads)
   void* mem = nullptr;             // device allocation behind the lists
   std::vector<char> host;          // staging copy (kept until the next sync)
   std::vector<int> ids;            // slot ids (host)

@@ -50,6 +50,46 @@ __device__ __forceinline__ void stv(T* p, const VecT<T, V>& v) {
   *(ME_GLOBAL vt*)globw(p) = x;
 }
 
+// Raw buffer access: a 128-bit resource (base, byte size) in scalar
+// registers and a 32-bit byte offset per lane.  Loads past the size return
+// zero, which the row product uses for its padding entries.  Used where
+// every array of a launch is below kBufMaxBytes.
+typedef int32_t BufRsrc __attribute__((ext_vector_type(4)));
+typedef int32_t BufI4 __attribute__((ext_vector_type(4)));
+typedef int32_t BufI2 __attribute__((ext_vector_type(2)));
+__device__ int32_t me_buf_load_i32(BufRsrc r, uint32_t voff, int32_t soff, int32_t aux)
+    __asm("llvm.amdgcn.raw.buffer.load.i32");
+__device__ BufI2 me_buf_load_v2i32(BufRsrc r, uint32_t voff, int32_t soff, int32_t aux)
+    __asm("llvm.amdgcn.raw.buffer.load.v2i32");
+__device__ BufI4 me_buf_load_v4i32(BufRsrc r, uint32_t voff, int32_t soff, int32_t aux)
+    __asm("llvm.amdgcn.raw.buffer.load.v4i32");
+constexpr uint32_t kBufOut = 0x80000000u;  // an offset past every buffer
+__device__ __forceinline__ BufRsrc buf_rsrc(const void* p, int64_t bytes) {
+  const uint64_t a = (uint64_t)p;
+  BufRsrc r;
+  r.x = (int32_t)(uint32_t)a;
+  r.y = (int32_t)(uint32_t)(a >> 32);  // stride 0
+  r.z = (int32_t)(uint32_t)bytes;
+  r.w = 0x00020000;  // 32-bit data format (gfx9 family)
+  return r;
+}
+__device__ __forceinline__ int32_t buf_i32(BufRsrc r, uint32_t off) {
+  return me_buf_load_i32(r, off, 0, 0);
+}
+template <typename T>
+__device__ __forceinline__ T buf_scalar(BufRsrc r, uint32_t off) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, me_buf_load_i32(r, off, 0, 0));
+  } else {
+    return __builtin_bit_cast(T, me_buf_load_v2i32(r, off, 0, 0));
+  }
+}
+template <typename T, int V>
+__device__ __forceinline__ VecT<T, V> buf_vec16(BufRsrc r, uint32_t off) {
+  static_assert(sizeof(T) * V == 16, "16-byte chunk");
+  return __builtin_bit_cast(VecT<T, V>, me_buf_load_v4i32(r, off, 0, 0));
+}
+
 #define ME_DISPATCH_KB(kb, ...)                       \
   switch (kb) {                                       \
     case 4: { constexpr int KB = 4; __VA_ARGS__; } break;   \
@@ -76,13 +116,76 @@ template <typename T, int KB>
 struct RowCfg {
   static constexpr int V16 = 16 / (int)sizeof(T);      // values per 16-byte chunk
   static constexpr int NCH = KB * (int)sizeof(T) / 16; // chunks per row
-  // lanes per row: 8, or 4 per chunk for rows of more than two chunks
-  static constexpr int G = (4 * NCH > 8) ? (4 * NCH > 32 ? 32 : 4 * NCH) : 8;
+  // lanes per row: two entries per round (four for one-chunk rows), eight
+  // rounds in flight; fewer lanes per row and more loads in flight per lane
+  // measured faster than wider lane groups on the gather-bound products
+  static constexpr int G = NCH == 1 ? 4 : 2 * NCH;
   static constexpr int EPL = G / NCH;                  // entries per round
-  static constexpr int UNR = 4;                        // rounds in flight
+  static constexpr int UNR = 8;                        // rounds in flight
   static constexpr int ROWS = 32;                      // rows per workgroup
   static constexpr int THREADS = ROWS * G;
 };
+
+// Entry span of a row: W entries [ws, ws + nw), then T entries at ts + k for
+// positions k in [nw, len) (the range selects which kinds are present).
+struct RowSpan {
+  int32_t ws, nw, ts, len;
+};
+__device__ __forceinline__ RowSpan row_span(bool live, int64_t row,
+                                            const int32_t* __restrict__ a_rp,
+                                            const int32_t* __restrict__ a_tp, int range) {
+  const ME_GLOBAL int32_t* rp = glob(a_rp);
+  const ME_GLOBAL int32_t* tp = glob(a_tp);
+  const int64_t r = live ? row : 0;
+  const int32_t w0 = rp[r], w1 = rp[r + 1], t0 = tp[r], t1 = tp[r + 1];
+  RowSpan s;
+  s.ws = w0;
+  s.nw = (live && range != kRangeT) ? w1 - w0 : 0;
+  s.ts = t0 - s.nw;
+  s.len = s.nw + ((live && range != kRangeW) ? t1 - t0 : 0);
+  return s;
+}
+
+// The row product over buffer resources: rc / rw hold the column indices and
+// weights, rx the block.  Lane q takes the entries e0, e0 + EPL, ... of the
+// span; an entry past the span loads column 0 and weight 0 (out-of-range
+// loads) and adds 0 * (x_i - x_0).  Loop counts are per lane.
+template <typename T, int KB>
+__device__ __forceinline__ void spmm_span_buf(int32_t ws, int32_t nw, int32_t ts, int32_t len,
+                                              int q, BufRsrc rc, BufRsrc rw, BufRsrc rx,
+                                              T c_t, const T (&xi)[RowCfg<T, KB>::V16],
+                                              T (&acc)[RowCfg<T, KB>::V16]) {
+  using C = RowCfg<T, KB>;
+  constexpr int V = C::V16, EPL = C::EPL, UNR = C::UNR;
+  const int ch = q % C::NCH, e0 = q / C::NCH;
+#pragma unroll
+  for (int v = 0; v < V; ++v) acc[v] = 0;
+  const int32_t mine = len > e0 ? (len - e0 + EPL - 1) / EPL : 0;  // this lane's entries
+  for (int32_t r = 0; r < mine; r += UNR) {
+    int32_t c[UNR];
+    T cf[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int32_t k = (r + u) * EPL + e0;
+      const bool isw = k < nw;
+      const uint32_t at = (uint32_t)((isw ? ws : ts) + k);
+      const bool ok = r + u < mine;
+      c[u] = buf_i32(rc, ok ? at * 4u : kBufOut);
+      const T w = buf_scalar<T>(rw, ok ? at * (uint32_t)sizeof(T) : kBufOut);
+      cf[u] = isw ? w : c_t * w;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const auto xj = buf_vec16<T, V>(rx, (uint32_t)c[u] * (uint32_t)(KB * sizeof(T)) +
+                                              (uint32_t)(ch * 16));
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v] += cf[u] * (xi[v] - xj.v[v]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+    for (int o = C::NCH; o < C::G; o <<= 1) acc[v] += __shfl_xor(acc[v], o);
+}
 
 template <typename T, int KB>
 __device__ __forceinline__ void spmm_row(bool live, int64_t row, int q,

@@ -330,13 +330,7 @@ int me_server_create(const me_server_opts* so, void* stream, me_server** out) {
   *out = nullptr;
   me_server_opts o;
   if (so) o = *so; else me_server_opts_default(&o);
-  if (o.max_active < 1 || o.opts.max_iter < 1 || o.opts.check_every < 1 ||
-      (o.opts.cheb_op != ME_CHEB_LAPLACIAN && o.opts.cheb_op != ME_CHEB_FULL) ||
-      o.opts.eps_max_iter < 1 || !(o.opts.eps_tol > 0) || o.opts.precond < 0 ||
-      o.opts.precond > 2 || (o.opts.precision != ME_FP64 && o.opts.precision != ME_MIXED) ||
-      (o.opts.precond == ME_PRECOND_CHEBYSHEV &&
-       (o.opts.cheb_degree < 2 || o.opts.cheb_degree > me::kMaxChebDegree)))
-    return ME_ERR_INVALID_ARG;
+  if (o.max_active < 1 || !me::opts_valid(o.opts)) return ME_ERR_INVALID_ARG;
   auto* h = new (std::nothrow) me_server();
   if (!h) return ME_ERR_HIP;
   h->s = new (std::nothrow) me::Server(o, (hipStream_t)stream);

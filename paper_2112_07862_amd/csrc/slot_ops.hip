@@ -55,7 +55,7 @@ __device__ __forceinline__ bool skip_slot(const SlotDev& d, int cert) {
 // Operator product Y = Op X (gathering; XCD-aware tile order)
 // ---------------------------------------------------------------------------
 
-template <typename T, int KB>
+template <typename T, int KB, bool BUF>
 __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_spmm(const SlotDev* __restrict__ sl,
                                                     const Tile* __restrict__ tiles,
                                                     int64_t ntiles, int in, int out, int cert) {
@@ -72,9 +72,21 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_spmm(const Slot
   const int ch = q % C::NCH;
   T xi[C::V16], acc[C::V16];
   // own row (row 0 stands in for rows past the end; their lanes add nothing)
-  load_chunk<T, C::V16>(x + (live ? row : 0) * KB + ch * C::V16, xi);
-  spmm_row<T, KB>(live, row, q, d.a_rp, d.a_tp, d.a_col, SB<T>::w(d), (T)d.c_t, d.range, x,
-                  xi, acc);
+  if constexpr (BUF) {
+    const BufRsrc rx = buf_rsrc(x, d.n * KB * (int64_t)sizeof(T));
+    const auto own = buf_vec16<T, C::V16>(
+        rx, (uint32_t)(live ? row : 0) * (uint32_t)(KB * sizeof(T)) + (uint32_t)(ch * 16));
+#pragma unroll
+    for (int v = 0; v < C::V16; ++v) xi[v] = own.v[v];
+    const RowSpan sp = row_span(live, row, d.a_rp, d.a_tp, d.range);
+    spmm_span_buf<T, KB>(sp.ws, sp.nw, sp.ts, sp.len, q, buf_rsrc(d.a_col, d.nnz_ops * 4),
+                         buf_rsrc(SB<T>::w(d), d.nnz_ops * (int64_t)sizeof(T)), rx, (T)d.c_t,
+                         xi, acc);
+  } else {
+    load_chunk<T, C::V16>(x + (live ? row : 0) * KB + ch * C::V16, xi);
+    spmm_row<T, KB>(live, row, q, d.a_rp, d.a_tp, d.a_col, SB<T>::w(d), (T)d.c_t, d.range, x,
+                    xi, acc);
+  }
   if (!live || q >= C::NCH) return;
   // lane q < NCH holds chunk q of the row
   const T sd = (T)d.s_diag;
@@ -89,8 +101,12 @@ void sl_spmm(const SlotDev* sl, const TileSet& ts, int in, int out, int cert, hi
   if (ts.n_gather == 0) return;
   ME_DISPATCH_KB(ts.kb, {
     static_assert(RowCfg<T, KB>::ROWS == kGatherRows, "gather tile rows");
-    k_sl_spmm<T, KB><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
-        sl, ts.gather, ts.n_gather, in, out, cert);
+    if (ts.buf)
+      k_sl_spmm<T, KB, true><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
+          sl, ts.gather, ts.n_gather, in, out, cert);
+    else
+      k_sl_spmm<T, KB, false><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
+          sl, ts.gather, ts.n_gather, in, out, cert);
   });
 }
 template void sl_spmm<double>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
@@ -127,7 +143,7 @@ __global__ void __launch_bounds__(kBlock) k_sl_cheb_first(const SlotDev* __restr
   stv<T, E::VEC>(SB<T>::blk(d, yprev) + o, v);
 }
 
-template <typename T, int KB>
+template <typename T, int KB, bool BUF>
 __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const SlotDev* __restrict__ sl,
                                                          const Tile* __restrict__ tiles,
                                                          int64_t ntiles, int k, int r, int yin,
@@ -144,9 +160,21 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const
   const T* yi_p = SB<T>::blk(d, yin);
   const int ch = q % C::NCH;
   T yi[C::V16], acc[C::V16];
-  load_chunk<T, C::V16>(yi_p + (live ? row : 0) * KB + ch * C::V16, yi);
-  spmm_row<T, KB>(live, row, q, d.a_rp, d.a_tp, d.a_col, SB<T>::w(d), (T)d.c_t,
-                  d.cheb_range, yi_p, yi, acc);
+  if constexpr (BUF) {
+    const BufRsrc rx = buf_rsrc(yi_p, d.n * KB * (int64_t)sizeof(T));
+    const auto own = buf_vec16<T, C::V16>(
+        rx, (uint32_t)(live ? row : 0) * (uint32_t)(KB * sizeof(T)) + (uint32_t)(ch * 16));
+#pragma unroll
+    for (int v = 0; v < C::V16; ++v) yi[v] = own.v[v];
+    const RowSpan sp = row_span(live, row, d.a_rp, d.a_tp, d.cheb_range);
+    spmm_span_buf<T, KB>(sp.ws, sp.nw, sp.ts, sp.len, q, buf_rsrc(d.a_col, d.nnz_ops * 4),
+                         buf_rsrc(SB<T>::w(d), d.nnz_ops * (int64_t)sizeof(T)), rx, (T)d.c_t,
+                         yi, acc);
+  } else {
+    load_chunk<T, C::V16>(yi_p + (live ? row : 0) * KB + ch * C::V16, yi);
+    spmm_row<T, KB>(live, row, q, d.a_rp, d.a_tp, d.a_col, SB<T>::w(d), (T)d.c_t,
+                    d.cheb_range, yi_p, yi, acc);
+  }
   if (!live || q >= C::NCH) return;
   // lane q < NCH updates chunk q of the row
   const T sd = (T)d.cheb_s_diag;
@@ -177,8 +205,12 @@ void sl_cheb_step(const SlotDev* sl, const TileSet& ts, int k, int r, int yin, i
   if (ts.n_gather == 0) return;
   ME_DISPATCH_KB(ts.kb, {
     static_assert(RowCfg<T, KB>::ROWS == kGatherRows, "gather tile rows");
-    k_sl_cheb_step<T, KB><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
-        sl, ts.gather, ts.n_gather, k, r, yin, yout);
+    if (ts.buf)
+      k_sl_cheb_step<T, KB, true><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
+          sl, ts.gather, ts.n_gather, k, r, yin, yout);
+    else
+      k_sl_cheb_step<T, KB, false><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
+          sl, ts.gather, ts.n_gather, k, r, yin, yout);
   });
 }
 template void sl_cheb_first<double>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);

@@ -301,3 +301,22 @@ def test_solver_order_bit_exact(me, name):
     assert np.array_equal(np.sort(perm), np.arange(g.n))
     assert np.array_equal(perm, cm_order_reference(g))
     h.close()
+
+
+@pytest.mark.parametrize("name,K", [("square_2k", 4), ("swiss_3k", 8), ("sphere_3k", 16),
+                                    ("ring_203", 8), ("grid_bipartite", 4)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_global_addressing_identical(me, name, K, precision):
+    """The 64-bit-address form of the product kernels (taken for arrays of
+    2 GiB and more) visits the entries in the same order as the 32-bit buffer
+    form: the same eps and the same pairs, bit for bit."""
+    g, _ = oracle_ops(name)
+    h1 = me.build_graph_ops(g, precision=precision)
+    h2 = me.build_graph_ops(g, precision=precision, addressing="global")
+    assert h1.eps == h2.eps
+    X1, l1, i1 = me.embed(h1, K, tol=1e-8, seed=2, precision=precision)
+    X2, l2, i2 = me.embed(h2, K, tol=1e-8, seed=2, precision=precision, addressing="global")
+    assert i1["status"] in (0, 2) and i1["iterations"] == i2["iterations"], (i1, i2)
+    assert torch.equal(X1, X2) and torch.equal(l1, l2)
+    h1.close()
+    h2.close()
