@@ -91,7 +91,9 @@ typedef struct {
   int precond;        /* ME_PRECOND_CHEBYSHEV (default), _JACOBI or _NONE           */
   int max_iter;       /* LOBPCG iteration cap for the embedding solve (default 20000) */
   int eps_max_iter;   /* iteration cap for the eps = lambda_2(Q) solve (default 20000) */
-  double eps_tol;     /* relative residual target of the eps solve (default 1e-8)   */
+  double eps_tol;     /* relative residual target of the eps solve (default 1e-6;
+                         the Rayleigh quotient's error is of order eps_tol^2 times
+                         lambda_2 over the gap to the eigenvalues past the block) */
   int check_every;    /* iterations enqueued between host convergence reads (default 16) */
   uint64_t seed;      /* seed of the library's starting blocks (default 0)          */
   int cheb_degree;    /* Chebyshev preconditioner degree, 2..256 (default 128)      */

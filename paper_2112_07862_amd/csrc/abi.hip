@@ -34,7 +34,7 @@ void me_opts_default(me_opts* o) {
   o->precond = ME_PRECOND_CHEBYSHEV;
   o->max_iter = 20000;
   o->eps_max_iter = 20000;
-  o->eps_tol = 1e-8;
+  o->eps_tol = 1e-6;
   o->check_every = 16;
   o->seed = 0;
   o->cheb_degree = 128;

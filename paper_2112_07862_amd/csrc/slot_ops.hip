@@ -147,49 +147,70 @@ template <typename T, int KB, bool BUF>
 __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const SlotDev* __restrict__ sl,
                                                          const Tile* __restrict__ tiles,
                                                          int64_t ntiles, int k, int r, int yin,
-                                                         int yout) {
+                                                         int yout, int single) {
   using C = RowCfg<T, KB>;
   const int64_t b = xcd_block(ntiles);
   if (b >= ntiles) return;
-  const Tile t = tiles[b];
+  // a launch over one slot needs no work list: tile b is block b
+  const Tile t = single >= 0 ? Tile{single, (int32_t)b} : tiles[b];
   const SlotDev& d = sl[t.slot];
-  if (slot_done(d)) return;
   const int64_t row = (int64_t)t.blk * kGatherRows + threadIdx.x / C::G;
   const int q = threadIdx.x % C::G;
   const bool live = row < d.n;
-  const T* yi_p = SB<T>::blk(d, yin);
   const int ch = q % C::NCH;
+  const T sd = (T)d.cheb_s_diag;
   T yi[C::V16], acc[C::V16];
   if constexpr (BUF) {
-    const BufRsrc rx = buf_rsrc(yi_p, d.n * KB * (int64_t)sizeof(T));
-    const auto own = buf_vec16<T, C::V16>(
-        rx, (uint32_t)(live ? row : 0) * (uint32_t)(KB * sizeof(T)) + (uint32_t)(ch * 16));
+    // Everything the row needs besides its neighbours is requested before
+    // the slot's done flag is tested (all of it in bounds either way), so the
+    // flag, the row bounds and the row's own data share one memory latency.
+    const int64_t rs = live ? row : 0;
+    const uint32_t oo = (uint32_t)rs * (uint32_t)(KB * sizeof(T)) + (uint32_t)(ch * 16);
+    const int64_t xb = d.n * KB * (int64_t)sizeof(T);
+    const BufRsrc rx = buf_rsrc(SB<T>::blk(d, yin), xb);
+    const auto own = buf_vec16<T, C::V16>(rx, oo);
+    const auto ri = buf_vec16<T, C::V16>(buf_rsrc(SB<T>::blk(d, r), xb), oo);
+    auto yo = buf_vec16<T, C::V16>(buf_rsrc(SB<T>::blk(d, yout), xb), oo);  // y_{k-1}
+    const T cd = glob(SB<T>::cdinv(d))[rs];
+    const T alpha = (T)*glob(&d.cheb->alpha[k]);
+    const T bk = (T)*glob(&d.cheb->beta[k]);
+    const RowSpan sp = row_span(live, row, d.a_rp, d.a_tp, d.cheb_range);
+    asm volatile("" ::: "memory");  // keeps the requests above ahead of the test
+    if (slot_done(d)) return;
 #pragma unroll
     for (int v = 0; v < C::V16; ++v) yi[v] = own.v[v];
-    const RowSpan sp = row_span(live, row, d.a_rp, d.a_tp, d.cheb_range);
     spmm_span_buf<T, KB>(sp.ws, sp.nw, sp.ts, sp.len, q, buf_rsrc(d.a_col, d.nnz_ops * 4),
                          buf_rsrc(SB<T>::w(d), d.nnz_ops * (int64_t)sizeof(T)), rx, (T)d.c_t,
                          yi, acc);
+    if (!live || q >= C::NCH) return;
+    // lane q < NCH updates chunk q of the row
+    const T beta = bk * cd;
+#pragma unroll
+    for (int v = 0; v < C::V16; ++v) {
+      const T res = ri.v[v] - (acc[v] + sd * yi[v]);
+      yo.v[v] = yi[v] + (alpha * (yi[v] - yo.v[v]) + beta * res);
+    }
+    stv<T, C::V16>(SB<T>::blk(d, yout) + row * KB + q * C::V16, yo);
   } else {
+    if (slot_done(d)) return;
+    const T* yi_p = SB<T>::blk(d, yin);
     load_chunk<T, C::V16>(yi_p + (live ? row : 0) * KB + ch * C::V16, yi);
     spmm_row<T, KB>(live, row, q, d.a_rp, d.a_tp, d.a_col, SB<T>::w(d), (T)d.c_t,
                     d.cheb_range, yi_p, yi, acc);
-  }
-  if (!live || q >= C::NCH) return;
-  // lane q < NCH updates chunk q of the row
-  const T sd = (T)d.cheb_s_diag;
-  const T alpha = (T)*glob(&d.cheb->alpha[k]);
-  const T beta = (T)*glob(&d.cheb->beta[k]) * glob(SB<T>::cdinv(d))[row];
-  const int64_t o = row * KB + q * C::V16;
-  const auto ri = ldv<T, C::V16>(SB<T>::blk(d, r) + o);
-  T* yo_p = SB<T>::blk(d, yout);
-  auto yo = ldv<T, C::V16>(yo_p + o);  // y_{k-1} of this row
+    if (!live || q >= C::NCH) return;
+    const T alpha = (T)*glob(&d.cheb->alpha[k]);
+    const T beta = (T)*glob(&d.cheb->beta[k]) * glob(SB<T>::cdinv(d))[row];
+    const int64_t o = row * KB + q * C::V16;
+    const auto ri = ldv<T, C::V16>(SB<T>::blk(d, r) + o);
+    T* yo_p = SB<T>::blk(d, yout);
+    auto yo = ldv<T, C::V16>(yo_p + o);  // y_{k-1} of this row
 #pragma unroll
-  for (int v = 0; v < C::V16; ++v) {
-    const T res = ri.v[v] - (acc[v] + sd * yi[v]);
-    yo.v[v] = yi[v] + (alpha * (yi[v] - yo.v[v]) + beta * res);
+    for (int v = 0; v < C::V16; ++v) {
+      const T res = ri.v[v] - (acc[v] + sd * yi[v]);
+      yo.v[v] = yi[v] + (alpha * (yi[v] - yo.v[v]) + beta * res);
+    }
+    stv<T, C::V16>(yo_p + o, yo);
   }
-  stv<T, C::V16>(yo_p + o, yo);
 }
 
 template <typename T>
@@ -207,10 +228,10 @@ void sl_cheb_step(const SlotDev* sl, const TileSet& ts, int k, int r, int yin, i
     static_assert(RowCfg<T, KB>::ROWS == kGatherRows, "gather tile rows");
     if (ts.buf)
       k_sl_cheb_step<T, KB, true><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
-          sl, ts.gather, ts.n_gather, k, r, yin, yout);
+          sl, ts.gather, ts.n_gather, k, r, yin, yout, ts.nslots == 1 ? ts.ids[0] : -1);
     else
       k_sl_cheb_step<T, KB, false><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
-          sl, ts.gather, ts.n_gather, k, r, yin, yout);
+          sl, ts.gather, ts.n_gather, k, r, yin, yout, ts.nslots == 1 ? ts.ids[0] : -1);
   });
 }
 template void sl_cheb_first<double>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);

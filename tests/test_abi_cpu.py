@@ -38,7 +38,7 @@ def test_host_only_entry_points():
     o = _lib.MeOpts()
     lib.me_opts_default(ctypes.byref(o))
     assert o.precond == _lib.ME_PRECOND_CHEBYSHEV and o.max_iter > 0 and o.check_every > 0
-    assert 0 < o.eps_tol < 1e-6
+    assert 0 < o.eps_tol <= 1e-6
     for st in list(_lib.STATUS_NAMES):
         assert lib.me_status_string(st).decode()
     assert lib.me_embed_workspace_bytes(None, 4, None) == 0
