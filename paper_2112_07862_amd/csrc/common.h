@@ -30,6 +30,7 @@ constexpr int kMaxBasis = 48;        // 3 x kMaxBlockCols: Rayleigh-Ritz basis s
 constexpr int kDenseMaxN = 48;       // graphs up to this size are solved densely
 constexpr int kPartialBlocks = 256;  // grid of the reducing streaming kernels
 constexpr int kMaxChebDegree = 256;  // largest Chebyshev preconditioner degree
+constexpr int kRhoHist = 32;         // residual history kept per solve
 constexpr int kXcd = 8;              // accelerator complex dies (one L2 each)
 // largest array (bytes) the buffer-resource kernels address with 32-bit offsets
 constexpr int64_t kBufMaxBytes = (int64_t)1 << 31;
@@ -89,6 +90,9 @@ struct Ctrl {
   double orth;               // max |X^T B X - I| at exit
   double rho[kMaxBlockCols]; // last residuals
   double lam[kMaxBlockCols]; // Ritz values of the certificate pass
+  // largest residual of the required columns at iteration i, at
+  // rho_hist[i % kRhoHist] (the host's convergence-rate estimate)
+  double rho_hist[kRhoHist];
 };
 
 // Packed graph operators (device pointers into one allocation).

@@ -236,8 +236,6 @@ class Engine {
   std::vector<int> active_;
   std::vector<TileSet> sets_;  // work lists of active_, one per block width
   // convergence history per slot (largest required rho at the last check)
-  std::vector<double> rho_prev_;
-  std::vector<int> it_prev_;
   std::vector<int> iter0_;
   bool round_open_ = false;
   int round_length();

@@ -67,8 +67,6 @@ Engine::Engine(hipStream_t s, const me_opts& o, int capacity, bool timed)
 int Engine::init() {
   sh_.assign(cap_, SlotHost());
   res_.assign(cap_, SlotResult());
-  rho_prev_.assign(cap_, 0.0);
-  it_prev_.assign(cap_, -1);
   hdev_.assign(cap_, SlotDev());
   ME_TRY(hipMallocAsync((void**)&d_slots_, sizeof(SlotDev) * cap_, s_));
   ME_TRY(hipMallocAsync((void**)&d_ctrl_, sizeof(Ctrl) * cap_, s_));
@@ -130,7 +128,6 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
   h.sp = sp;
   bytes_in_use_ += need;
   res_[id] = SlotResult();
-  it_prev_[id] = -1;
 
   SlotDev d{};
   Arena a{(char*)ws, need, 0};
@@ -481,11 +478,16 @@ int Engine::round_length() {
   const int ce = o_.check_every > 0 ? o_.check_every : 16;
   double best = 1e300;
   for (int id : active_) {
+    // rate of the last (up to) 8 iterations from the device's residual
+    // history; iterations 0 .. iter - 1 have entries
     const Ctrl& c = h_ctrl_[id];
-    double rho = 0.0;
-    for (int j = 0; j < sh_[id].sp.need; ++j) rho = std::max(rho, c.rho[j]);
-    if (it_prev_[id] >= 0 && c.iter > it_prev_[id] && rho > 0.0 && rho < rho_prev_[id]) {
-      const double rate = std::log(rho_prev_[id] / rho) / (double)(c.iter - it_prev_[id]);
+    const int last = c.iter - 1;
+    const int m = std::min(8, std::min(last, kRhoHist - 1));
+    if (m < 2) continue;
+    const double rho = c.rho_hist[last % kRhoHist];
+    const double old = c.rho_hist[(last - m) % kRhoHist];
+    if (rho > 0.0 && rho < old) {
+      const double rate = std::log(old / rho) / (double)m;
       const double rem = rho > sh_[id].sp.tol ? std::log(rho / sh_[id].sp.tol) / rate : 0.0;
       best = std::min(best, rem);
     }
@@ -526,13 +528,6 @@ int Engine::begin_round() {
   if (timed_) phase_ = ktimer_new_phase();
   tag_ = 0;
   const int ce = round_length();
-  for (size_t q = 0; q < active_.size(); ++q) {
-    const int id = active_[q];
-    double rho = 0.0;
-    for (int j = 0; j < sh_[id].sp.need; ++j) rho = std::max(rho, h_ctrl_[id].rho[j]);
-    rho_prev_[id] = rho;
-    it_prev_[id] = iter0_[q] > 0 ? iter0_[q] : -1;
-  }
   for (int q = 0; q < ce; ++q)
     for (auto& ts : sets_) iteration(ts);
   round_open_ = true;

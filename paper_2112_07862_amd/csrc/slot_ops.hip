@@ -350,6 +350,7 @@ __global__ void __launch_bounds__(kWave) k_sl_resid_finalize(const SlotDev* __re
   __syncthreads();
   const double* lam = d.lam;
   int conv = 0, bad = 0;
+  double worst = 0.0;  // largest residual of the required columns
   if (lane < KB) {
     const double al = fabs(lam[lane]);
     const double den = (al >= ctrl->lam_floor ? al : ctrl->lam_scale) * sqrt(tot[KB + lane]);
@@ -357,14 +358,17 @@ __global__ void __launch_bounds__(kWave) k_sl_resid_finalize(const SlotDev* __re
     ctrl->rho[lane] = rho;
     if (final_pass) ctrl->lam[lane] = lam[lane];
     conv = (lane < ctrl->need) && (rho <= ctrl->tol);
+    if (lane < ctrl->need) worst = rho;
     bad = !isfinite(rho);
   }
   const int nc = __popcll(__ballot(conv));
   const int nb = __popcll(__ballot(bad));
+  for (int o = kWave / 2; o > 0; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o));
   if (lane == 0) {
     ctrl->nconv = nc;
     if (nb) ctrl->nonfinite = 1;
     if (!final_pass) {
+      ctrl->rho_hist[ctrl->iter % kRhoHist] = worst;
       if (nc >= ctrl->need || nb || ctrl->iter >= ctrl->max_iter) ctrl->done = 1;
       else ctrl->iter += 1;
     }
