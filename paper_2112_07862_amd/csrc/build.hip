@@ -391,10 +391,26 @@ __device__ __forceinline__ int32_t ld_coherent(const int32_t* p) {
 
 constexpr int kBfsThreads = 1024;
 
+// A frontier of at most kBfsThreads nodes staged in LDS: node ids, first
+// edges and the exclusive scan of their degrees, so that one thread per edge
+// finds its node by a binary search in LDS.
+struct FrontierLds {
+  int32_t off[kBfsThreads + 1];
+  int32_t u[kBfsThreads];
+  int64_t rs[kBfsThreads];
+};
+
+__device__ __forceinline__ int32_t find_owner(const int32_t* off, int32_t n, int32_t e);
+
+// Stages fin[0..nin) (nin <= kBfsThreads); returns the number of edges.
+__device__ __forceinline__ int32_t stage_frontier(const int64_t* __restrict__ rp,
+                                                  const int32_t* fin, int32_t nin,
+                                                  FrontierLds* f, int32_t* s_wave);
+
 __device__ __forceinline__ int32_t bfs_levels(const int64_t* __restrict__ rp,
                                               const int32_t* __restrict__ col, int32_t* level,
                                               int32_t* fa, int32_t* fb, int32_t start,
-                                              int32_t* s_cnt) {
+                                              int32_t* s_cnt, FrontierLds* f, int32_t* s_wave) {
   const int tid = threadIdx.x;
   if (tid == 0) {
     level[start] = 0;
@@ -409,13 +425,23 @@ __device__ __forceinline__ int32_t bfs_levels(const int64_t* __restrict__ rp,
     const int32_t nin = s_cnt[0];
     if (tid == 0) s_cnt[1] = 0;
     __syncthreads();
-    for (int32_t i = tid; i < nin; i += kBfsThreads) {
-      const int32_t u = fin[i];
-      for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
-        const int32_t v = col[t];
-        if (ld_coherent(&level[v]) < 0 &&
-            atomicCAS(&level[v], -1, lev + 1) == -1)
+    if (nin <= kBfsThreads) {
+      // narrow level: one thread per frontier edge
+      const int32_t m = stage_frontier(rp, fin, nin, f, s_wave);
+      for (int32_t e = tid; e < m; e += kBfsThreads) {
+        const int32_t i = find_owner(f->off, nin, e);
+        const int32_t v = col[f->rs[i] + (e - f->off[i])];
+        if (ld_coherent(&level[v]) < 0 && atomicCAS(&level[v], -1, lev + 1) == -1)
           fout[atomicAdd(&s_cnt[1], 1)] = v;
+      }
+    } else {
+      for (int32_t i = tid; i < nin; i += kBfsThreads) {
+        const int32_t u = fin[i];
+        for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
+          const int32_t v = col[t];
+          if (ld_coherent(&level[v]) < 0 && atomicCAS(&level[v], -1, lev + 1) == -1)
+            fout[atomicAdd(&s_cnt[1], 1)] = v;
+        }
       }
     }
     __syncthreads();
@@ -474,6 +500,23 @@ __device__ __forceinline__ int32_t find_owner(const int32_t* off, int32_t n, int
   return lo;
 }
 
+__device__ __forceinline__ int32_t stage_frontier(const int64_t* __restrict__ rp,
+                                                  const int32_t* fin, int32_t nin,
+                                                  FrontierLds* f, int32_t* s_wave) {
+  const int tid = threadIdx.x;
+  if (tid < nin) {
+    const int32_t u = fin[tid];
+    const int64_t rs = rp[u];
+    f->u[tid] = u;
+    f->rs[tid] = rs;
+    f->off[tid] = (int32_t)(rp[u + 1] - rs);
+  }
+  __syncthreads();
+  const int32_t m = block_exclusive_scan(f->off, nin, s_wave);
+  __syncthreads();
+  return m;
+}
+
 // One component of the Cuthill-McKee order: perm[off] = start, levels from
 // lev0.  Scratch: key (n ints, INT32_MAX for unvisited nodes), eoff (n ints)
 // and ev, ei, ef (one int per edge).  Every level-l node claims its
@@ -490,7 +533,8 @@ __device__ __forceinline__ int64_t cm_component(const int64_t* __restrict__ rp,
                                                 int32_t* key, int32_t* eoff, int32_t* ev,
                                                 int32_t* ei, int32_t* ef, int32_t* perm,
                                                 int64_t off, int32_t start, int32_t lev0,
-                                                int32_t* s_wave, int32_t* last_lev) {
+                                                int32_t* s_wave, FrontierLds* f,
+                                                int32_t* last_lev) {
   const int tid = threadIdx.x;
   if (tid == 0) {
     level[start] = lev0;
@@ -539,16 +583,10 @@ __device__ __forceinline__ int64_t cm_component(const int64_t* __restrict__ rp,
       }
     } else {
       // narrow level: one thread per frontier edge
-      for (int32_t i = tid; i < nin; i += kBfsThreads) {
-        const int32_t u = fin[i];
-        eoff[i] = (int32_t)(rp[u + 1] - rp[u]);
-      }
-      __syncthreads();
-      const int32_t m = block_exclusive_scan(eoff, nin, s_wave);
+      const int32_t m = stage_frontier(rp, fin, nin, f, s_wave);
       for (int32_t e = tid; e < m; e += kBfsThreads) {
-        const int32_t i = find_owner(eoff, nin, e);
-        const int32_t u = fin[i];
-        const int32_t v = col[rp[u] + (e - eoff[i])];
+        const int32_t i = find_owner(f->off, nin, e);
+        const int32_t v = col[f->rs[i] + (e - f->off[i])];
         ev[e] = v;
         ei[e] = i;
         int32_t lv = ld_coherent(&level[v]);
@@ -587,10 +625,12 @@ __global__ void __launch_bounds__(kBfsThreads) k_pseudo_peripheral(int64_t n, co
                                                                    int32_t* fb, int32_t* out) {
   __shared__ int32_t s_cnt[2];
   __shared__ int32_t s_min;
+  __shared__ int32_t s_wave[kBfsThreads / kWave];
+  __shared__ FrontierLds f;
   const int tid = threadIdx.x;
   for (int64_t i = tid; i < n; i += kBfsThreads) level[i] = -1;
   __syncthreads();
-  const int32_t last = bfs_levels(rp, col, level, fa, fb, 0, s_cnt);
+  const int32_t last = bfs_levels(rp, col, level, fa, fb, 0, s_cnt, &f, s_wave);
   if (tid == 0) s_min = INT32_MAX;
   __syncthreads();
   for (int64_t i = tid; i < n; i += kBfsThreads)
@@ -606,6 +646,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_cm_order(int64_t n, const int64
                                                           int32_t* start, int32_t* perm) {
   __shared__ int32_t s_wave[kBfsThreads / kWave];
   __shared__ int32_t s_min;
+  __shared__ FrontierLds f;
   const int tid = threadIdx.x;
   for (int64_t i = tid; i < n; i += kBfsThreads) {
     level[i] = -1;
@@ -614,7 +655,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_cm_order(int64_t n, const int64
   __syncthreads();
   int32_t last = 0;
   int64_t off =
-      cm_component(rp, col, level, key, eoff, ev, ei, ef, perm, 0, *start, 0, s_wave, &last);
+      cm_component(rp, col, level, key, eoff, ev, ei, ef, perm, 0, *start, 0, s_wave, &f, &last);
   // further components: the lowest unvisited node only grows
   int64_t ptr = 0;
   for (;;) {
@@ -631,7 +672,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_cm_order(int64_t n, const int64
     __syncthreads();
     if (nxt == INT32_MAX) break;
     off += cm_component(rp, col, level, key, eoff, ev, ei, ef, perm, off, nxt, last + 1, s_wave,
-                        &last);
+                        &f, &last);
   }
   if (tid == 0) start[1] = last;
 }
@@ -997,8 +1038,6 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   // ---- Q diagonal, mu denominators, packed operator
   k_invt<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->t_cnt, g->invt, g->invt32);
   unsigned long long* maxden_bits = reinterpret_cast<unsigned long long*>(dflags + 4);
-  unsigned long long* maxdiag_bits = reinterpret_cast<unsigned long long*>(dflags + 6);
-  unsigned long long* maxratio_bits = reinterpret_cast<unsigned long long*>(dflags + 8);
   k_qdiag<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->t_rp, g->t_col, g->invt, g->qdiag,
                                                  g->qinv, g->qinv32, maxden_bits);
   // locality order of the solver and the packed operator in that order
