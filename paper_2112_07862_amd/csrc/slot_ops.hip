@@ -15,6 +15,7 @@
 //             - mu sum_{j in T_i} (1/T_i + 1/T_j) (x_i - x_j) + eps x_i
 //   (Q x)_i = sum_{j in T_i} (1/T_i + 1/T_j) (x_i - x_j)
 #include <cmath>
+#include <cstdlib>
 
 #include "common.h"
 #include "engine.h"
@@ -425,23 +426,41 @@ struct Ids {
   int v[3];
 };
 
-template <int KB>
-__device__ __forceinline__ double load_cat(const SlotDev& d, const Ids& ids, int nblk,
-                                           int64_t row, int col, int64_t r1) {
-  const int blk = col / KB;
-  if (row >= r1 || blk >= nblk) return 0.0;
-  return d.b64[ids.v[blk]][row * KB + (col % KB)];
+// Grams of one reduction tile, G1 = U^T diag(b) V and G2 = U^T V2, where V's
+// blocks are blocks of U (vsel[i] = position in U of V's block i).  Each wave
+// takes 16-row chunks (rows r0 + 16 wave, + 16 NW, ...): it stages the chunk
+// of every U and V2 block in its own LDS area with one contiguous load per
+// block (a 16-row chunk of a row-major n x KB block is 16 KB contiguous
+// doubles), then feeds the FP64 MFMA 16x16x4 from LDS.  The waves' sums are
+// added in wave order in LDS and written as the tile's partial.
+template <int KB, int NU, int NV, int NV2>
+struct GramCfg {
+  static constexpr int MU = NU * KB, MV = NV * KB, MV2 = NV2 * KB;
+  static constexpr int TU = (MU + 15) / 16, TV = (MV + 15) / 16, TV2 = (MV2 + 15) / 16;
+  static constexpr int E1 = MU * MV, E2 = MU * MV2;
+  static constexpr int NB = NU + NV2;         // staged blocks
+  static constexpr int LD = NB * KB + 1;      // LDS row stride (doubles)
+  static constexpr int NW = kBlock / kWave;
+  static constexpr int WAVE_LDS = 16 * LD + 16;  // chunk + row weights
+  static constexpr int LDS = NW * WAVE_LDS > E1 + E2 ? NW * WAVE_LDS : E1 + E2;
+  static constexpr int EPL = KB / 4;          // doubles per lane when staging
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int KB, int NU, int NV, int NV2>
 __global__ void __launch_bounds__(kBlock) k_sl_gram(const SlotDev* __restrict__ sl,
-                                                    const Tile* __restrict__ tiles, Ids u, Ids v,
+                                                    const Tile* __restrict__ tiles, Ids u, Ids vsel,
                                                     Ids v2, int use_b, int cert) {
-  constexpr int MU = NU * KB, MV = NV * KB, MV2 = NV2 * KB;
-  constexpr int TU = (MU + 15) / 16, TV = (MV + 15) / 16, TV2 = (MV2 + 15) / 16;
-  constexpr int E1 = MU * MV, E2 = MU * MV2;
+  using C = GramCfg<KB, NU, NV, NV2>;
+  constexpr int MU = C::MU, MV = C::MV, MV2 = C::MV2, TU = C::TU, TV = C::TV, TV2 = C::TV2;
+  constexpr int E1 = C::E1, E2 = C::E2, LD = C::LD, NW = C::NW, EPL = C::EPL;
   using Acc = typename Mfma<double>::Acc;
-  __shared__ double sh[E1 + E2];
+  __shared__ double lds[C::LDS];
   const Tile t = tiles[blockIdx.x];
   const SlotDev& d = sl[t.slot];
   if (skip_slot(d, cert)) return;
@@ -458,33 +477,63 @@ __global__ void __launch_bounds__(kBlock) k_sl_gram(const SlotDev* __restrict__ 
   const int64_t r0 = (int64_t)t.blk * d.per;
   const int64_t r1 = r0 + d.per < d.n ? r0 + d.per : d.n;
   const double* wd = use_b ? d.bdiag : nullptr;
+  const double* bp[C::NB];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) bp[i] = d.b64[u.v[i]];
+#pragma unroll
+  for (int i = 0; i < NV2; ++i) bp[NU + i] = d.b64[v2.v[i]];
+  // LDS column of V's column j (V's block j / KB is U's block vsel)
+  int vcol[TV > 0 ? TV : 1];
   const int li = lane % 16, lk = lane / 16;
-  constexpr int NW = kBlock / kWave;
+#pragma unroll
+  for (int b = 0; b < TV; ++b) {
+    const int j = 16 * b + li;
+    vcol[b] = j < MV ? vsel.v[j / KB] * KB + j % KB : -1;
+  }
+  double* st = lds + wave * C::WAVE_LDS;
+  const int se = lane * EPL, sr = se / KB, sc = se % KB;  // staging: row, column
   for (int64_t base = r0 + 16 * wave; base < r1; base += 16 * NW) {
-    double ua[4][TU], vb[4][TV > 0 ? TV : 1], v2b[4][TV2 > 0 ? TV2 : 1];
+    const bool ok = base + sr < r1;
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const int64_t row = base + 4 * ks + lk;
-      const bool ok = row < r1;
+    for (int bi = 0; bi < C::NB; ++bi) {
+      VecT<double, EPL> x;
+      if (ok) {
+        x = ldv<double, EPL>(bp[bi] + (base + sr) * KB + sc);
+      } else {
 #pragma unroll
-      for (int a = 0; a < TU; ++a) ua[ks][a] = ok ? load_cat<KB>(d, u, NU, row, 16 * a + li, r1) : 0.0;
-      const double wr = (ok && TV > 0) ? (wd ? wd[row] : 1.0) : 0.0;
+        for (int q = 0; q < EPL; ++q) x.v[q] = 0.0;
+      }
 #pragma unroll
-      for (int b = 0; b < TV; ++b) vb[ks][b] = ok ? wr * load_cat<KB>(d, v, NV, row, 16 * b + li, r1) : 0.0;
-#pragma unroll
-      for (int b = 0; b < TV2; ++b) v2b[ks][b] = ok ? load_cat<KB>(d, v2, NV2, row, 16 * b + li, r1) : 0.0;
+      for (int q = 0; q < EPL; ++q) st[sr * LD + bi * KB + sc + q] = x.v[q];
     }
+    if (lane < 16)
+      st[16 * LD + lane] = (base + lane < r1) ? (wd ? glob(wd)[base + lane] : 1.0) : 0.0;
+    wave_lds_sync();
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
+      const int row = 4 * ks + lk;
+      const double* sr_p = st + row * LD;
+      double ua[TU], vb[TV > 0 ? TV : 1], v2b[TV2 > 0 ? TV2 : 1];
+#pragma unroll
+      for (int a = 0; a < TU; ++a) ua[a] = 16 * a + li < MU ? sr_p[16 * a + li] : 0.0;
+      const double wr = TV > 0 ? st[16 * LD + row] : 0.0;
+#pragma unroll
+      for (int b = 0; b < TV; ++b) vb[b] = vcol[b] >= 0 ? wr * sr_p[vcol[b]] : 0.0;
+#pragma unroll
+      for (int b = 0; b < TV2; ++b)
+        v2b[b] = 16 * b + li < MV2 ? sr_p[NU * KB + 16 * b + li] : 0.0;
 #pragma unroll
       for (int a = 0; a < TU; ++a) {
 #pragma unroll
-        for (int b = 0; b < TV; ++b) acc1[a][b] = Mfma<double>::step(ua[ks][a], vb[ks][b], acc1[a][b]);
+        for (int b = 0; b < TV; ++b) acc1[a][b] = Mfma<double>::step(ua[a], vb[b], acc1[a][b]);
 #pragma unroll
-        for (int b = 0; b < TV2; ++b) acc2[a][b] = Mfma<double>::step(ua[ks][a], v2b[ks][b], acc2[a][b]);
+        for (int b = 0; b < TV2; ++b) acc2[a][b] = Mfma<double>::step(ua[a], v2b[b], acc2[a][b]);
       }
     }
+    wave_lds_sync();  // the chunk is read before the next one overwrites it
   }
+  __syncthreads();  // staging areas are reused for the sums
+  double* sh = lds;
   for (int wv = 0; wv < NW; ++wv) {
     if (wave == wv) {
 #pragma unroll
@@ -523,7 +572,13 @@ void sl_gram(const SlotDev* sl, const TileSet& ts, int nu, const int* u, int nv,
   if (ts.n_red == 0) return;
   Ids iu{{0, 0, 0}}, iv{{0, 0, 0}}, iv2{{0, 0, 0}};
   for (int i = 0; i < nu; ++i) iu.v[i] = u[i];
-  for (int i = 0; i < nv; ++i) iv.v[i] = v[i];
+  // V's blocks are blocks of U: pass their positions in U
+  for (int i = 0; i < nv; ++i) {
+    iv.v[i] = -1;
+    for (int j = 0; j < nu; ++j)
+      if (u[j] == v[i]) iv.v[i] = j;
+    if (iv.v[i] < 0) std::abort();  // no caller asks for a V outside U
+  }
   for (int i = 0; i < nv2; ++i) iv2.v[i] = v2[i];
 #define ME_SL_GRAM(NU_, NV_, NV2_)                                                           \
   if (nu == NU_ && nv == NV_ && nv2 == NV2_) {                                               \
