@@ -695,40 +695,79 @@ __global__ void k_invert_perm(int64_t n, const int32_t* perm, int32_t* iperm) {
 }
 
 // perm (solver index -> user index), iperm (user -> solver).
-static int locality_order(GraphOps* g, int32_t* perm, int32_t* iperm, hipStream_t s) {
+// The locality order runs on a stream of its own: its searches occupy one
+// workgroup, so the two-hop construction and the connectivity pass of the
+// main stream run beside them.  begin() enqueues everything; end() waits and
+// reads the number of levels.  The destructor cleans up after an early
+// return of the caller.
+struct OrderJob {
+  hipStream_t s = nullptr;
+  hipEvent_t ready = nullptr;
+  void* mem = nullptr;
+  int32_t* start = nullptr;
+  ~OrderJob() { release(); }
+  void release() {
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      if (mem) (void)hipFree(mem);
+      (void)hipStreamDestroy(s);
+    }
+    if (ready) (void)hipEventDestroy(ready);
+    s = nullptr;
+    ready = nullptr;
+    mem = nullptr;
+  }
+};
+
+// perm (solver index -> user index), iperm (user -> solver), levels; W must
+// be validated on `main` before the call.
+static int order_begin(GraphOps* g, int32_t* perm, int32_t* iperm, hipStream_t main,
+                       OrderJob* job) {
   const int64_t n = g->n;
+  ME_TRY(hipStreamCreateWithFlags(&job->s, hipStreamNonBlocking));
+  ME_TRY(hipEventCreateWithFlags(&job->ready, hipEventDisableTiming));
+  ME_TRY(hipEventRecord(job->ready, main));
+  ME_TRY(hipStreamWaitEvent(job->s, job->ready, 0));
+  hipStream_t s = job->s;
   if (n <= kDenseMaxN) {
     k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, perm);
     k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, iperm);
-    g->max_level = 0;
     return ME_OK;
   }
   const int64_t nnz = g->nnz_w;
   const size_t bytes =
       Arena::round((n + 2) * 4) * 3 + Arena::round((nnz + 2) * 4) * 3 + Arena::round(64);
-  void* mem = nullptr;
-  ME_TRY(hipMallocAsync(&mem, bytes, s));
-  Arena a{(char*)mem, bytes, 0};
+  ME_TRY(hipMallocAsync(&job->mem, bytes, s));
+  Arena a{(char*)job->mem, bytes, 0};
   int32_t* level = a.take<int32_t>(n + 2);
   int32_t* fa = a.take<int32_t>(n + 2);
   int32_t* fb = a.take<int32_t>(n + 2);
   int32_t* ev = a.take<int32_t>(nnz + 2);
   int32_t* ei = a.take<int32_t>(nnz + 2);
   int32_t* ef = a.take<int32_t>(nnz + 2);
-  int32_t* start = a.take<int32_t>(16);
+  job->start = a.take<int32_t>(16);
   // pseudo-peripheral start, then the Cuthill-McKee order from it (fa, fb
   // serve as the frontiers of the first search and as the key and frontier
   // edge offsets of the second)
-  k_pseudo_peripheral<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb, start);
-  k_cm_order<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb, ev, ei, ef, start,
-                                       perm);
+  k_pseudo_peripheral<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb,
+                                                job->start);
+  k_cm_order<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb, ev, ei, ef,
+                                       job->start, perm);
   k_invert_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, perm, iperm);
   k_gather_level<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, perm, level, g->lev_s);
+  return ME_OK;
+}
+
+static int order_end(GraphOps* g, OrderJob* job) {
   int32_t hl[2] = {0, 0};
-  ME_TRY(hipMemcpyAsync(hl, start, 8, hipMemcpyDeviceToHost, s));
-  ME_TRY(hipStreamSynchronize(s));
+  if (job->start) ME_TRY(hipMemcpyAsync(hl, job->start, 8, hipMemcpyDeviceToHost, job->s));
+  ME_TRY(hipStreamSynchronize(job->s));
   g->max_level = hl[1];
-  ME_TRY(hipFreeAsync(mem, s));
+  if (job->mem) {
+    ME_TRY(hipFree(job->mem));
+    job->mem = nullptr;
+  }
+  job->release();
   return ME_OK;
 }
 
@@ -980,6 +1019,10 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   ME_TRY_STATUS(read_scalar(dflags, &hflags, s));
   if (hflags) return flags_to_status(hflags);
 
+  // ---- locality order (second stream), beside the two-hop construction
+  OrderJob order;
+  ME_TRY_STATUS(order_begin(g, g->perm, g->iperm, s, &order));
+
   // ---- two-hop pattern: count
   int32_t* big_list = reinterpret_cast<int32_t*>(g->r);  // n int32 fit in n doubles
   int32_t* big_count = dflags + 1;
@@ -1041,7 +1084,7 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   k_qdiag<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->t_rp, g->t_col, g->invt, g->qdiag,
                                                  g->qinv, g->qinv32, maxden_bits);
   // locality order of the solver and the packed operator in that order
-  ME_TRY_STATUS(locality_order(g, g->perm, g->iperm, s));
+  ME_TRY_STATUS(order_end(g, &order));
   int32_t* wlen = reinterpret_cast<int32_t*>(g->r);  // 2n int32 fit in n doubles
   int32_t* tlen = wlen + n;
   k_row_len_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->w_rp, g->t_rp, wlen, tlen);

@@ -478,22 +478,26 @@ int Engine::round_length() {
   const int ce = o_.check_every > 0 ? o_.check_every : 16;
   double best = 1e300;
   for (int id : active_) {
-    // rate of the last (up to) 8 iterations from the device's residual
-    // history; iterations 0 .. iter - 1 have entries
+    // convergence rate from the device's residual history (iterations
+    // 0 .. iter - 1 have entries), the faster of the last 4 and the last 8
+    // iterations: a round that ends early costs one host read, an iteration
+    // past convergence costs a round of launches that do nothing
     const Ctrl& c = h_ctrl_[id];
     const int last = c.iter - 1;
-    const int m = std::min(8, std::min(last, kRhoHist - 1));
-    if (m < 2) continue;
-    const double rho = c.rho_hist[last % kRhoHist];
-    const double old = c.rho_hist[(last - m) % kRhoHist];
-    if (rho > 0.0 && rho < old) {
-      const double rate = std::log(old / rho) / (double)m;
+    const double rho = last >= 0 ? c.rho_hist[last % kRhoHist] : 0.0;
+    double rate = 0.0;
+    for (int m : {4, 8}) {
+      if (m > last || m >= kRhoHist) continue;
+      const double old = c.rho_hist[(last - m) % kRhoHist];
+      if (rho > 0.0 && rho < old) rate = std::max(rate, std::log(old / rho) / (double)m);
+    }
+    if (rate > 0.0) {
       const double rem = rho > sh_[id].sp.tol ? std::log(rho / sh_[id].sp.tol) / rate : 0.0;
       best = std::min(best, rem);
     }
   }
   if (best >= 1e300) return ce;
-  return (int)std::max(1.0, std::min((double)ce, std::ceil(best) + 1.0));
+  return (int)std::max(1.0, std::min((double)ce, std::ceil(best)));
 }
 
 // Starts the slots added since the last round, then enqueues one round of
