@@ -11,7 +11,8 @@ namespace me {
 void free_graph_ops(GraphOps& g) {
   if (g.mem) (void)hipFree(g.mem);
   if (g.mem2) (void)hipFree(g.mem2);
-  g.mem = g.mem2 = nullptr;
+  if (g.ord_mem) (void)hipFree(g.ord_mem);
+  g.mem = g.mem2 = g.ord_mem = nullptr;
 }
 }  // namespace me
 

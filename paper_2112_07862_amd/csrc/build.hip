@@ -619,10 +619,15 @@ __device__ __forceinline__ int64_t cm_component(const int64_t* __restrict__ rp,
   return placed;
 }
 
-__global__ void __launch_bounds__(kBfsThreads) k_pseudo_peripheral(int64_t n, const int64_t* rp,
-                                                                   const int32_t* col,
-                                                                   int32_t* level, int32_t* fa,
-                                                                   int32_t* fb, int32_t* out) {
+__global__ void __launch_bounds__(kBfsThreads) k_pseudo_peripheral(const OrderArgs* args) {
+  const OrderArgs& ga = args[blockIdx.x];
+  const int64_t n = ga.n;
+  const int64_t* rp = ga.rp;
+  const int32_t* col = ga.col;
+  int32_t* level = ga.level;
+  int32_t* fa = ga.fa;
+  int32_t* fb = ga.fb;
+  int32_t* out = ga.start;
   __shared__ int32_t s_cnt[2];
   __shared__ int32_t s_min;
   __shared__ int32_t s_wave[kBfsThreads / kWave];
@@ -639,11 +644,15 @@ __global__ void __launch_bounds__(kBfsThreads) k_pseudo_peripheral(int64_t n, co
   if (tid == 0) *out = s_min;
 }
 
-__global__ void __launch_bounds__(kBfsThreads) k_cm_order(int64_t n, const int64_t* rp,
-                                                          const int32_t* col, int32_t* level,
-                                                          int32_t* key, int32_t* eoff,
-                                                          int32_t* ev, int32_t* ei, int32_t* ef,
-                                                          int32_t* start, int32_t* perm) {
+__global__ void __launch_bounds__(kBfsThreads) k_cm_order(const OrderArgs* args) {
+  const OrderArgs& ga = args[blockIdx.x];
+  const int64_t n = ga.n;
+  const int64_t* rp = ga.rp;
+  const int32_t* col = ga.col;
+  int32_t* level = ga.level;
+  int32_t* key = ga.fa;   // the first search's frontiers serve as key ...
+  int32_t* eoff = ga.fb;  // ... and frontier edge offsets
+  int32_t *ev = ga.ev, *ei = ga.ei, *ef = ga.ef, *start = ga.start, *perm = ga.perm;
   __shared__ int32_t s_wave[kBfsThreads / kWave];
   __shared__ int32_t s_min;
   __shared__ FrontierLds f;
@@ -674,7 +683,10 @@ __global__ void __launch_bounds__(kBfsThreads) k_cm_order(int64_t n, const int64
     off += cm_component(rp, col, level, key, eoff, ev, ei, ef, perm, off, nxt, last + 1, s_wave,
                         &f, &last);
   }
-  if (tid == 0) start[1] = last;
+  if (tid == 0) {
+    start[1] = last;
+    *ga.maxlev = last;
+  }
 }
 
 // lev_s[i'] = breadth-first level of solver row i'
@@ -695,81 +707,106 @@ __global__ void k_invert_perm(int64_t n, const int32_t* perm, int32_t* iperm) {
 }
 
 // perm (solver index -> user index), iperm (user -> solver).
-// The locality order runs on a stream of its own: its searches occupy one
-// workgroup, so the two-hop construction and the connectivity pass of the
-// main stream run beside them.  begin() enqueues everything; end() waits and
-// reads the number of levels.  The destructor cleans up after an early
-// return of the caller.
-struct OrderJob {
-  hipStream_t s = nullptr;
-  hipEvent_t ready = nullptr;
-  void* mem = nullptr;
-  int32_t* start = nullptr;
-  ~OrderJob() { release(); }
-  void release() {
-    if (s) {
-      (void)hipStreamSynchronize(s);
-      if (mem) (void)hipFree(mem);
-      (void)hipStreamDestroy(s);
-    }
-    if (ready) (void)hipEventDestroy(ready);
-    s = nullptr;
-    ready = nullptr;
-    mem = nullptr;
-  }
-};
-
-// perm (solver index -> user index), iperm (user -> solver), levels; W must
-// be validated on `main` before the call.
-static int order_begin(GraphOps* g, int32_t* perm, int32_t* iperm, hipStream_t main,
-                       OrderJob* job) {
+// Scratch and arguments of a graph's searches (graphs of at most kDenseMaxN
+// nodes take the identity order and need none).
+static int order_alloc(GraphOps* g, hipStream_t s) {
   const int64_t n = g->n;
-  ME_TRY(hipStreamCreateWithFlags(&job->s, hipStreamNonBlocking));
-  ME_TRY(hipEventCreateWithFlags(&job->ready, hipEventDisableTiming));
-  ME_TRY(hipEventRecord(job->ready, main));
-  ME_TRY(hipStreamWaitEvent(job->s, job->ready, 0));
-  hipStream_t s = job->s;
-  if (n <= kDenseMaxN) {
-    k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, perm);
-    k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, iperm);
-    return ME_OK;
-  }
+  g->ord = OrderArgs{};
+  g->ord.n = n;
+  g->ord.perm = g->perm;
+  if (n <= kDenseMaxN) return ME_OK;
   const int64_t nnz = g->nnz_w;
   const size_t bytes =
       Arena::round((n + 2) * 4) * 3 + Arena::round((nnz + 2) * 4) * 3 + Arena::round(64);
-  ME_TRY(hipMallocAsync(&job->mem, bytes, s));
-  Arena a{(char*)job->mem, bytes, 0};
-  int32_t* level = a.take<int32_t>(n + 2);
-  int32_t* fa = a.take<int32_t>(n + 2);
-  int32_t* fb = a.take<int32_t>(n + 2);
-  int32_t* ev = a.take<int32_t>(nnz + 2);
-  int32_t* ei = a.take<int32_t>(nnz + 2);
-  int32_t* ef = a.take<int32_t>(nnz + 2);
-  job->start = a.take<int32_t>(16);
-  // pseudo-peripheral start, then the Cuthill-McKee order from it (fa, fb
-  // serve as the frontiers of the first search and as the key and frontier
-  // edge offsets of the second)
-  k_pseudo_peripheral<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb,
-                                                job->start);
-  k_cm_order<<<1, kBfsThreads, 0, s>>>(n, g->w_rp, g->w_col, level, fa, fb, ev, ei, ef,
-                                       job->start, perm);
-  k_invert_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, perm, iperm);
-  k_gather_level<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, perm, level, g->lev_s);
+  ME_TRY(hipMallocAsync(&g->ord_mem, bytes, s));
+  Arena a{(char*)g->ord_mem, bytes, 0};
+  g->ord.rp = g->w_rp;
+  g->ord.col = g->w_col;
+  g->ord.level = a.take<int32_t>(n + 2);
+  g->ord.fa = a.take<int32_t>(n + 2);
+  g->ord.fb = a.take<int32_t>(n + 2);
+  g->ord.ev = a.take<int32_t>(nnz + 2);
+  g->ord.ei = a.take<int32_t>(nnz + 2);
+  g->ord.ef = a.take<int32_t>(nnz + 2);
+  g->ord.start = a.take<int32_t>(16);
   return ME_OK;
 }
 
-static int order_end(GraphOps* g, OrderJob* job) {
-  int32_t hl[2] = {0, 0};
-  if (job->start) ME_TRY(hipMemcpyAsync(hl, job->start, 8, hipMemcpyDeviceToHost, job->s));
-  ME_TRY(hipStreamSynchronize(job->s));
-  g->max_level = hl[1];
-  if (job->mem) {
-    ME_TRY(hipFree(job->mem));
-    job->mem = nullptr;
+// The pseudo-peripheral starts and the Cuthill-McKee orders of G graphs
+// (one workgroup per graph in each launch), then iperm and the solver-order
+// levels of each.  *args_mem receives the argument array (device) that
+// order_finish releases.
+int order_launch(GraphOps* const* gs, int G, hipStream_t s, void** args_mem) {
+  *args_mem = nullptr;
+  std::vector<OrderArgs> host;
+  for (int i = 0; i < G; ++i)
+    if (gs[i]->ord_mem) host.push_back(gs[i]->ord);
+  const int m = (int)host.size();
+  const size_t bytes = Arena::round(sizeof(OrderArgs) * (m > 0 ? m : 1)) + Arena::round(4 * G + 4);
+  ME_TRY(hipMallocAsync(args_mem, bytes, s));
+  OrderArgs* dargs = (OrderArgs*)*args_mem;
+  int32_t* maxlev = (int32_t*)((char*)*args_mem + Arena::round(sizeof(OrderArgs) * (m > 0 ? m : 1)));
+  for (int q = 0; q < m; ++q) host[q].maxlev = maxlev + q;
+  if (m > 0) {
+    ME_TRY(hipMemcpyAsync(dargs, host.data(), sizeof(OrderArgs) * m, hipMemcpyHostToDevice, s));
+    k_pseudo_peripheral<<<m, kBfsThreads, 0, s>>>(dargs);
+    k_cm_order<<<m, kBfsThreads, 0, s>>>(dargs);
   }
-  job->release();
+  for (int i = 0; i < G; ++i) {
+    GraphOps* g = gs[i];
+    const int64_t n = g->n;
+    if (!g->ord_mem) {
+      k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm);
+      k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->iperm);
+      continue;
+    }
+    k_invert_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->iperm);
+    k_gather_level<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->ord.level, g->lev_s);
+  }
   return ME_OK;
 }
+
+// Waits for the searches, reads the deepest levels, frees their scratch.
+int order_finish(GraphOps* const* gs, int G, hipStream_t s, void* args_mem) {
+  int m = 0;
+  for (int i = 0; i < G; ++i) m += gs[i]->ord_mem ? 1 : 0;
+  std::vector<int32_t> lev(m > 0 ? m : 1, 0);
+  const size_t off = Arena::round(sizeof(OrderArgs) * (m > 0 ? m : 1));
+  if (m > 0 && args_mem)
+    ME_TRY(hipMemcpyAsync(lev.data(), (char*)args_mem + off, 4 * m, hipMemcpyDeviceToHost, s));
+  ME_TRY(hipStreamSynchronize(s));
+  int q = 0;
+  for (int i = 0; i < G; ++i) {
+    GraphOps* g = gs[i];
+    g->max_level = g->ord_mem ? lev[q++] : 0;
+    if (g->ord_mem) ME_TRY(hipFreeAsync(g->ord_mem, s));
+    g->ord_mem = nullptr;
+  }
+  if (args_mem) ME_TRY(hipFreeAsync(args_mem, s));
+  return ME_OK;
+}
+
+// A side stream for one graph's searches: they occupy one workgroup, so the
+// two-hop construction and the connectivity pass of the main stream run
+// beside them.  The destructor waits for it after an early return.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t ready = nullptr;
+  ~SideStream() {
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+    if (ready) (void)hipEventDestroy(ready);
+  }
+  int fork(hipStream_t main) {
+    ME_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    ME_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    ME_TRY(hipEventRecord(ready, main));
+    ME_TRY(hipStreamWaitEvent(s, ready, 0));
+    return ME_OK;
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Per-node scalars
@@ -940,7 +977,36 @@ static int read_scalar(const T* dev, T* host, hipStream_t s) {
 // Everything up to eps: validation, degrees, T, Q, the locality order and
 // the packed operator.  g->needs_eps tells whether eps = lambda_2(Q) must be
 // computed (connected two-hop graph); otherwise eps = 0 (ME_WARN_EPS_ZERO).
+static int build_pre_a_impl(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g,
+                            SideStream* side, void** args);
+
 int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
+  SideStream side;
+  void* args = nullptr;
+  struct Pending {  // releases the search arguments if a step fails
+    void** args;
+    ~Pending() {
+      if (*args) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(*args);
+      }
+    }
+  } pending{&args};
+  ME_TRY_STATUS(build_pre_a_impl(W, o, s, g, &side, &args));
+  const int st = order_finish(&g, 1, side.s, args);
+  args = nullptr;  // released by order_finish
+  if (st < 0) return st;
+  return build_pre_b(g, s);
+}
+
+int build_pre_a(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
+  return build_pre_a_impl(W, o, s, g, nullptr, nullptr);
+}
+
+// side != null: the graph's searches start on a side stream right after
+// validation and run beside the two-hop construction.
+static int build_pre_a_impl(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g,
+                            SideStream* side, void** args) {
   const int64_t n = W->n, nnz = W->nnz;
   if (n < 1 || nnz < 0 || !W->rowptr || (nnz > 0 && (!W->col || !W->val)))
     return ME_ERR_INVALID_ARG;
@@ -995,8 +1061,8 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   g->b32_s = ar.take<float>(n);
   g->dinv32_s = ar.take<float>(n);
   g->pdinv32_s = ar.take<float>(n);
-  int64_t* woff = ar.take<int64_t>(n + 1);
-  int64_t* toff = ar.take<int64_t>(n + 1);
+  g->woff = ar.take<int64_t>(n + 1);
+  g->toff = ar.take<int64_t>(n + 1);
   int* dflags = ar.take<int>(64);
   if (!dflags) return ME_ERR_HIP;
   g->scratch_d = scratch_d;
@@ -1019,9 +1085,11 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   ME_TRY_STATUS(read_scalar(dflags, &hflags, s));
   if (hflags) return flags_to_status(hflags);
 
-  // ---- locality order (second stream), beside the two-hop construction
-  OrderJob order;
-  ME_TRY_STATUS(order_begin(g, g->perm, g->iperm, s, &order));
+  ME_TRY_STATUS(order_alloc(g, s));
+  if (side) {
+    ME_TRY_STATUS(side->fork(s));
+    ME_TRY_STATUS(order_launch(&g, 1, side->s, args));
+  }
 
   // ---- two-hop pattern: count
   int32_t* big_list = reinterpret_cast<int32_t*>(g->r);  // n int32 fit in n doubles
@@ -1083,8 +1151,17 @@ int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
   unsigned long long* maxden_bits = reinterpret_cast<unsigned long long*>(dflags + 4);
   k_qdiag<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->t_rp, g->t_col, g->invt, g->qdiag,
                                                  g->qinv, g->qinv32, maxden_bits);
-  // locality order of the solver and the packed operator in that order
-  ME_TRY_STATUS(order_end(g, &order));
+  return ME_OK;
+}
+
+// The operator packed in the solver order (perm, iperm set), the solver-order
+// copies of the per-node arrays, the connectivity and mu denominator reads.
+int build_pre_b(GraphOps* g, hipStream_t s) {
+  const int64_t n = g->n, nnz = g->nnz_w;
+  int64_t* tile_tmp = reinterpret_cast<int64_t*>(g->scratch_d);
+  int64_t *woff = g->woff, *toff = g->toff;
+  int* roots = g->dflags + 2;
+  unsigned long long* maxden_bits = reinterpret_cast<unsigned long long*>(g->dflags + 4);
   int32_t* wlen = reinterpret_cast<int32_t*>(g->r);  // 2n int32 fit in n doubles
   int32_t* tlen = wlen + n;
   k_row_len_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->w_rp, g->t_rp, wlen, tlen);

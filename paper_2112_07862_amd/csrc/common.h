@@ -95,6 +95,16 @@ struct Ctrl {
   double rho_hist[kRhoHist];
 };
 
+// Arguments of the breadth-first searches of one graph (device scratch; one
+// workgroup per graph).
+struct OrderArgs {
+  int64_t n;
+  const int64_t* rp;
+  const int32_t* col;
+  int32_t *level, *fa, *fb, *ev, *ei, *ef, *start, *perm;
+  int32_t* maxlev;  // receives the deepest level
+};
+
 // Packed graph operators (device pointers into one allocation).
 struct GraphOps {
   int64_t n = 0, nnz_w = 0, nnz_t = 0;
@@ -143,6 +153,9 @@ struct GraphOps {
   double* a_w = nullptr;       // w_ij at the W positions, 1/T_i + 1/T_j at the T positions
   float* a_w32 = nullptr;
   double* scratch_d = nullptr;  // n doubles of build scratch
+  int64_t *woff = nullptr, *toff = nullptr;  // row offsets of the packed blocks
+  OrderArgs ord{};              // search arguments while the order is pending
+  void* ord_mem = nullptr;      // their scratch
   int* dflags = nullptr;        // 64 ints of build flags and reductions
   bool needs_eps = false;       // two-hop graph connected: eps = lambda_2(Q) > 0
   void* mem = nullptr;   // per-node arrays, W copy
@@ -155,7 +168,14 @@ struct GraphOps {
 int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g, me_info* info);
 // option ranges of me_opts (shared by every entry point that takes them)
 bool opts_valid(const me_opts& o);
+// build_pre = build_pre_a (validation, T, Q_ii, connectivity; the order's
+// scratch) + the locality order + build_pre_b (operator packed in that
+// order).  Batches run the searches of all graphs in one launch.
 int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g);
+int build_pre_a(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g);
+int order_launch(GraphOps* const* gs, int G, hipStream_t s, void** args_mem);
+int order_finish(GraphOps* const* gs, int G, hipStream_t s, void* args_mem);
+int build_pre_b(GraphOps* g, hipStream_t s);
 int build_post(GraphOps* g, double eps, int eps_iters, hipStream_t s);
 
 // ---- launchers: dense.hip -------------------------------------------------

@@ -193,8 +193,20 @@ int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opt
     if (!Xs[i] || !lams[i]) st[i] = ME_ERR_INVALID_ARG;
     else if (Ks[i] < 1 || Ks[i] > kMaxBlockCols) st[i] = ME_ERR_K_RANGE;
     if (st[i] < 0) continue;
-    st[i] = build_pre(&Ws[i], o, s, &gs[i]);
+    st[i] = build_pre_a(&Ws[i], o, s, &gs[i]);
     if (st[i] >= 0) st[i] = check_k_range(gs[i], Ks[i]);
+  }
+  // the breadth-first searches of every graph in one launch, then each
+  // graph's operator in its order
+  {
+    std::vector<GraphOps*> ok;
+    for (int i = 0; i < G; ++i)
+      if (st[i] >= 0) ok.push_back(&gs[i]);
+    void* args = nullptr;
+    ME_TRY_STATUS(order_launch(ok.data(), (int)ok.size(), s, &args));
+    ME_TRY_STATUS(order_finish(ok.data(), (int)ok.size(), s, args));
+    for (int i = 0; i < G; ++i)
+      if (st[i] >= 0) st[i] = build_pre_b(&gs[i], s);
   }
   // eps
   std::vector<double> eps(G, 0.0);
