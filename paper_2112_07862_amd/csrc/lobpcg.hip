@@ -6,13 +6,48 @@
 //     (A, B), B-orthonormal.
 // Graphs of at most kDenseMaxN nodes are solved densely instead.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "engine.h"
 
 namespace me {
+
+// Host threads of the per-graph build steps of a batch.
+constexpr int kBuildThreads = 8;
+
+// Runs fn(i, stream) for i in [0, G) on up to kBuildThreads host threads,
+// each with a stream of its own: the per-graph build steps wait on the host
+// several times, so graphs overlap across threads.  Every stream is idle on
+// return.
+template <typename F>
+static void for_each_graph(int G, F fn) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    (void)hipSetDevice(dev);
+    hipStream_t ws = nullptr;
+    if (hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) ws = nullptr;
+    for (int i; (i = next.fetch_add(1)) < G;) {
+      fn(i, ws);
+      (void)hipStreamSynchronize(ws);
+    }
+    if (ws) (void)hipStreamDestroy(ws);
+  };
+  std::vector<std::thread> th;
+  const int nt = std::max(1, std::min(G, kBuildThreads));
+  try {
+    for (int t = 1; t < nt; ++t) th.emplace_back(work);
+  } catch (...) {
+    // no more threads: the calling thread takes the rest
+  }
+  work();
+  for (auto& x : th) x.join();
+}
 
 SlotSpec eps_slot_spec(const GraphOps& g, const me_opts* o) {
   SlotSpec sp;
@@ -189,13 +224,14 @@ int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opt
   } release{gs};
   std::vector<int> st(G, ME_OK);
   std::vector<double> ms_build(G, 0.0);
-  for (int i = 0; i < G; ++i) {
+  ME_TRY(hipStreamSynchronize(s));  // the caller's graphs are in place
+  for_each_graph(G, [&](int i, hipStream_t ws) {
     if (!Xs[i] || !lams[i]) st[i] = ME_ERR_INVALID_ARG;
     else if (Ks[i] < 1 || Ks[i] > kMaxBlockCols) st[i] = ME_ERR_K_RANGE;
-    if (st[i] < 0) continue;
-    st[i] = build_pre_a(&Ws[i], o, s, &gs[i]);
+    if (st[i] < 0) return;
+    st[i] = build_pre_a(&Ws[i], o, ws, &gs[i]);
     if (st[i] >= 0) st[i] = check_k_range(gs[i], Ks[i]);
-  }
+  });
   // the breadth-first searches of every graph in one launch, then each
   // graph's operator in its order
   {
@@ -205,8 +241,9 @@ int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opt
     void* args = nullptr;
     ME_TRY_STATUS(order_launch(ok.data(), (int)ok.size(), s, &args));
     ME_TRY_STATUS(order_finish(ok.data(), (int)ok.size(), s, args));
-    for (int i = 0; i < G; ++i)
-      if (st[i] >= 0) st[i] = build_pre_b(&gs[i], s);
+    for_each_graph(G, [&](int i, hipStream_t ws) {
+      if (st[i] >= 0) st[i] = build_pre_b(&gs[i], ws);
+    });
   }
   // eps
   std::vector<double> eps(G, 0.0);
@@ -235,12 +272,13 @@ int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opt
       else eps[i] = r.lam[0];
     }
   }
-  for (int i = 0; i < G; ++i) {
-    if (st[i] < 0) continue;
-    st[i] = build_post(&gs[i], eps[i], eps_it[i], s);
+  for_each_graph(G, [&](int i, hipStream_t ws) {
+    if (st[i] < 0) return;
+    st[i] = build_post(&gs[i], eps[i], eps_it[i], ws);
+    (void)hipStreamSynchronize(ws);
     ms_build[i] =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  }
+  });
   // embedding
   const auto t1 = std::chrono::steady_clock::now();
   {
