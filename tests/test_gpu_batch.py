@@ -25,7 +25,8 @@ def me():
 
 
 def _mix():
-    """Uneven sizes, all three block widths, an eps = 0 graph, a dense one."""
+    """Uneven sizes, all three block widths, eps = 0 graphs, a dense one, a
+    disconnected one."""
     return [
         ("square_1500", sg.manifold_graph("square", 1500, 8, 11), 4),
         ("swiss_2000", sg.manifold_graph("swiss_roll", 2000, 8, 12), 8),
@@ -35,6 +36,9 @@ def _mix():
         ("grid_bipartite", sg.grid(20, 25), 4),
         ("ring_203", sg.ring(203, 3), 5),
         ("tri_mesh", sg.tri_mesh(3), 3),
+        # two components: the order's search moves on to the second one
+        ("two_squares", sg.disjoint_union([sg.manifold_graph("square", 400, 8, 16),
+                                           sg.manifold_graph("square", 300, 8, 17)]), 4),
     ]
 
 
