@@ -370,11 +370,56 @@ def main() -> int:
             "bytes_per_launch": kt["bytes"] / max(kt["launches"], 1),
         },
     }
+    # context for the roofline, outside the timed region: a plain device copy
+    # moving the same bytes as one launch (and a large one), and the other
+    # row-streaming kernels of the solve measured the same way
+    bpl = kt["bytes"] / max(kt["launches"], 1)
+    same = copy_rate(int(bpl), stream)
+    large = copy_rate(2 << 30, stream)
+    out["roofline"]["copy_same_bytes_GBps"] = same
+    out["roofline"]["copy_2GiB_GBps"] = large
+    out["roofline"]["frac_of_copy_same_bytes"] = achieved / same if same > 0 else None
+    others = {}
+    for kname in ("spmm", "gram"):
+        me.kernel_timing(KERNELS[kname])
+        step()
+        stream.synchronize()
+        k2 = me.kernel_timing_read()
+        me.kernel_timing(0)
+        if k2["launches"]:
+            ms = k2["total_ms"] / k2["launches"]
+            gbs = k2["bytes"] / k2["launches"] / (ms * 1e-3) / 1e9
+            others[kname] = {"kernel": KERNEL_NAMES[kname], "achieved": gbs, "unit": "GB/s",
+                             "frac": gbs / HBM_PEAK_GBS, "avg_us": ms * 1e3,
+                             "launches": k2["launches"],
+                             "bytes_per_launch": k2["bytes"] / k2["launches"]}
+    out["other_kernels"] = others
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(kind, args.cpu_sample_n, knn, K, 0)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def copy_rate(traffic_bytes: int, stream, reps: int = 50) -> float:
+    """GB/s of torch's device-to-device copy moving `traffic_bytes` (half
+    read, half written), timed with events on `stream`."""
+    import torch
+    n = max(traffic_bytes // 8, 1)  # floats per buffer: n * 4 read + n * 4 written
+    a = torch.empty(n, dtype=torch.float32, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    with torch.cuda.stream(stream):
+        for _ in range(5):
+            b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record(stream)
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return 8.0 * n / sec / 1e9
 
 
 if __name__ == "__main__":

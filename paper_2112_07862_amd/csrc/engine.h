@@ -110,9 +110,11 @@ void sl_spmm(const SlotDev* sl, const TileSet& ts, int in, int out, int cert, hi
 // y <- D^-1 R / theta, yprev <- 0; then y_{k+1} into yout (which holds y_{k-1})
 template <typename T>
 void sl_cheb_first(const SlotDev* sl, const TileSet& ts, int r, int y, int yprev, hipStream_t s);
+// host_sl: the host copy of the slot table (a one-slot set passes its
+// slot's pointers in the kernel arguments)
 template <typename T>
-void sl_cheb_step(const SlotDev* sl, const TileSet& ts, int k, int r, int yin, int yout,
-                  hipStream_t s);
+void sl_cheb_step(const SlotDev* sl, const SlotDev* host_sl, const TileSet& ts, int k, int r,
+                  int yin, int yout, hipStream_t s);
 // R = AX - B X Lambda (-> block w unless w < 0; Jacobi-scaled if jacobi),
 // per-tile sums of |r|^2, |Bx|^2, x^T D x.
 void sl_resid(const SlotDev* sl, const TileSet& ts, int w, int jacobi, int cert, hipStream_t s);

@@ -357,8 +357,8 @@ void Engine::iteration(const TileSet& ts) {
     {
       KScope ks(tm ? KT_CHEB : -1, s_, (deg - 1) * cb, tag_, deg - 1);
       for (int k = 1; k < deg; ++k) {
-        if (cheb32_) sl_cheb_step<float>(d_slots_, ts, k, r, cur, nxt, s_);
-        else sl_cheb_step<double>(d_slots_, ts, k, r, cur, nxt, s_);
+        if (cheb32_) sl_cheb_step<float>(d_slots_, hdev_.data(), ts, k, r, cur, nxt, s_);
+        else sl_cheb_step<double>(d_slots_, hdev_.data(), ts, k, r, cur, nxt, s_);
         std::swap(cur, nxt);
       }
     }
@@ -377,8 +377,8 @@ void Engine::iteration(const TileSet& ts) {
   if (tm) {
     for (int id : ts.ids) {
       const GraphOps& g = *sh_[id].sp.g;
-      // column index of every entry, W weights, row bounds, 1/T_i, x in, y out
-      sb += 4.0 * (double)(g.nnz_w + g.nnz_t) + 8.0 * (double)g.nnz_w + (double)g.n * 16.0 +
+      // column index and weight of every entry, row bounds, x in, y out
+      sb += 12.0 * (double)(g.nnz_w + g.nnz_t) + (double)g.n * 8.0 +
             2.0 * (double)g.n * kb * 8.0;
       blk += (double)g.n * kb * 8.0;
     }

@@ -90,6 +90,12 @@ __device__ __forceinline__ VecT<T, V> buf_vec16(BufRsrc r, uint32_t off) {
   return __builtin_bit_cast(VecT<T, V>, me_buf_load_v4i32(r, off, 0, 0));
 }
 
+// Multiply-adds of the products and recurrences are written out, so that
+// every kernel form of the same arithmetic rounds identically, whatever the
+// compiler would contract on its own.
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 #define ME_DISPATCH_KB(kb, ...)                       \
   switch (kb) {                                       \
     case 4: { constexpr int KB = 4; __VA_ARGS__; } break;   \
@@ -149,8 +155,10 @@ __device__ __forceinline__ RowSpan row_span(bool live, int64_t row,
 // The row product over buffer resources: rc / rw hold the column indices and
 // weights, rx the block.  Lane q takes the entries e0, e0 + EPL, ... of the
 // span; an entry past the span loads column 0 and weight 0 (out-of-range
-// loads) and adds 0 * (x_i - x_0).  Loop counts are per lane.
-template <typename T, int KB>
+// loads) and adds 0 * (x_i - x_0).  Loop counts are per lane.  RANGE fixes
+// the entry kinds at compile time (kRangeW: W only, kRangeT: T only) or
+// leaves them to the span (-1).
+template <typename T, int KB, int RANGE = -1>
 __device__ __forceinline__ void spmm_span_buf(int32_t ws, int32_t nw, int32_t ts, int32_t len,
                                               int q, BufRsrc rc, BufRsrc rw, BufRsrc rx,
                                               T c_t, const T (&xi)[RowCfg<T, KB>::V16],
@@ -167,19 +175,35 @@ __device__ __forceinline__ void spmm_span_buf(int32_t ws, int32_t nw, int32_t ts
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int32_t k = (r + u) * EPL + e0;
-      const bool isw = k < nw;
-      const uint32_t at = (uint32_t)((isw ? ws : ts) + k);
       const bool ok = r + u < mine;
-      c[u] = buf_i32(rc, ok ? at * 4u : kBufOut);
-      const T w = buf_scalar<T>(rw, ok ? at * (uint32_t)sizeof(T) : kBufOut);
-      cf[u] = isw ? w : c_t * w;
+      if constexpr (RANGE == kRangeW) {
+        const uint32_t at = (uint32_t)(ws + k);
+        c[u] = buf_i32(rc, ok ? at * 4u : kBufOut);
+        cf[u] = buf_scalar<T>(rw, ok ? at * (uint32_t)sizeof(T) : kBufOut);
+      } else if constexpr (RANGE == kRangeT) {
+        const uint32_t at = (uint32_t)(ts + k);
+        c[u] = buf_i32(rc, ok ? at * 4u : kBufOut);
+        cf[u] = c_t * buf_scalar<T>(rw, ok ? at * (uint32_t)sizeof(T) : kBufOut);
+      } else {
+        const bool isw = k < nw;
+        const uint32_t at = (uint32_t)((isw ? ws : ts) + k);
+        c[u] = buf_i32(rc, ok ? at * 4u : kBufOut);
+        const T w = buf_scalar<T>(rw, ok ? at * (uint32_t)sizeof(T) : kBufOut);
+        cf[u] = isw ? w : c_t * w;
+      }
     }
+    VecT<T, V> xj[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+      xj[u] = buf_vec16<T, V>(rx, (uint32_t)c[u] * (uint32_t)(KB * sizeof(T)) +
+                                      (uint32_t)(ch * 16));
+    // every gather of the round is in flight before the first is used (the
+    // scheduler would otherwise trade them for registers)
+    asm volatile("" ::: "memory");
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      const auto xj = buf_vec16<T, V>(rx, (uint32_t)c[u] * (uint32_t)(KB * sizeof(T)) +
-                                              (uint32_t)(ch * 16));
 #pragma unroll
-      for (int v = 0; v < V; ++v) acc[v] += cf[u] * (xi[v] - xj.v[v]);
+      for (int v = 0; v < V; ++v) acc[v] = fmaT(cf[u], xi[v] - xj[u].v[v], acc[v]);
     }
   }
 #pragma unroll
@@ -249,7 +273,7 @@ __device__ __forceinline__ void spmm_row(bool live, int64_t row, int q,
 #pragma unroll
     for (int u = 0; u < UNR; ++u)
 #pragma unroll
-      for (int v = 0; v < V; ++v) acc[v] += cf[u] * (xi[v] - xj[u][v]);
+      for (int v = 0; v < V; ++v) acc[v] = fmaT(cf[u], xi[v] - xj[u][v], acc[v]);
   }
 #pragma unroll
   for (int v = 0; v < V; ++v)

@@ -15,6 +15,7 @@
 //             - mu sum_{j in T_i} (1/T_i + 1/T_j) (x_i - x_j) + eps x_i
 //   (Q x)_i = sum_{j in T_i} (1/T_i + 1/T_j) (x_i - x_j)
 #include <cmath>
+#include <cstddef>
 #include <cstdlib>
 
 #include "common.h"
@@ -93,7 +94,7 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_spmm(const Slot
   const T sd = (T)d.s_diag;
   VecT<T, C::V16> o;
 #pragma unroll
-  for (int v = 0; v < C::V16; ++v) o.v[v] = acc[v] + sd * xi[v];
+  for (int v = 0; v < C::V16; ++v) o.v[v] = fmaT(sd, xi[v], acc[v]);
   stv<T, C::V16>(SB<T>::blk(d, out) + row * KB + q * C::V16, o);
 }
 
@@ -144,55 +145,105 @@ __global__ void __launch_bounds__(kBlock) k_sl_cheb_first(const SlotDev* __restr
   stv<T, E::VEC>(SB<T>::blk(d, yprev) + o, v);
 }
 
+// What one step needs of a slot, gathered in one place: read from the slot
+// table by the work-list kernel, passed by value (kernel arguments, one
+// scalar load) by the one-slot kernel.
+template <typename T>
+struct ChebView {
+  int64_t n, nnz_ops;
+  const int32_t *a_rp, *a_tp, *a_col;
+  const T *a_w, *cdinv, *yin, *r;
+  T* yout;
+  const double *alpha, *beta;
+  const int* done;
+  double c_t, s_diag;
+  int range;
+};
+
+template <typename T>
+__device__ __forceinline__ ChebView<T> cheb_view(const SlotDev& d, int r, int yin, int yout) {
+  ChebView<T> v;
+  v.n = d.n;
+  v.nnz_ops = d.nnz_ops;
+  v.a_rp = d.a_rp;
+  v.a_tp = d.a_tp;
+  v.a_col = d.a_col;
+  v.a_w = SB<T>::w(d);
+  v.cdinv = SB<T>::cdinv(d);
+  v.yin = SB<T>::blk(d, yin);
+  v.r = SB<T>::blk(d, r);
+  v.yout = SB<T>::blk(d, yout);
+  v.alpha = d.cheb->alpha;
+  v.beta = d.cheb->beta;
+  v.done = &d.ctrl->done;
+  v.c_t = d.c_t;
+  v.s_diag = d.cheb_s_diag;
+  v.range = d.cheb_range;
+  return v;
+}
+
+// Rows of block `blk` through buffer resources.  Everything a row needs
+// besides its neighbours is requested before the slot's done flag is tested
+// (all of it in bounds either way), so the flag, the row bounds and the
+// row's own data share one memory latency.
+template <typename T, int KB, int RANGE>
+__device__ __forceinline__ void cheb_step_rows(const ChebView<T>& d, int64_t blk, int k) {
+  using C = RowCfg<T, KB>;
+  const int64_t row = blk * kGatherRows + threadIdx.x / C::G;
+  const int q = threadIdx.x % C::G;
+  const bool live = row < d.n;
+  const int ch = q % C::NCH;
+  const T sd = (T)d.s_diag;
+  T yi[C::V16], acc[C::V16];
+  const int64_t rs = live ? row : 0;
+  const uint32_t oo = (uint32_t)rs * (uint32_t)(KB * sizeof(T)) + (uint32_t)(ch * 16);
+  const int64_t xb = d.n * KB * (int64_t)sizeof(T);
+  const BufRsrc rx = buf_rsrc(d.yin, xb);
+  const auto own = buf_vec16<T, C::V16>(rx, oo);
+  const auto ri = buf_vec16<T, C::V16>(buf_rsrc(d.r, xb), oo);
+  auto yo = buf_vec16<T, C::V16>(buf_rsrc(d.yout, xb), oo);  // y_{k-1}
+  const T cd = glob(d.cdinv)[rs];
+  const T alpha = (T)*glob(&d.alpha[k]);
+  const T bk = (T)*glob(&d.beta[k]);
+  const RowSpan sp = row_span(live, row, d.a_rp, d.a_tp, d.range);
+  asm volatile("" ::: "memory");  // keeps the requests above ahead of the test
+  if (*glob(d.done)) return;
+#pragma unroll
+  for (int v = 0; v < C::V16; ++v) yi[v] = own.v[v];
+  spmm_span_buf<T, KB, RANGE>(sp.ws, sp.nw, sp.ts, sp.len, q, buf_rsrc(d.a_col, d.nnz_ops * 4),
+                              buf_rsrc(d.a_w, d.nnz_ops * (int64_t)sizeof(T)), rx, (T)d.c_t, yi,
+                              acc);
+  if (!live || q >= C::NCH) return;
+  // lane q < NCH updates chunk q of the row
+  const T beta = bk * cd;
+#pragma unroll
+  for (int v = 0; v < C::V16; ++v) {
+    const T res = ri.v[v] - fmaT(sd, yi[v], acc[v]);
+    yo.v[v] = yi[v] + fmaT(alpha, yi[v] - yo.v[v], beta * res);
+  }
+  stv<T, C::V16>(d.yout + row * KB + q * C::V16, yo);
+}
+
+// Work-list form (any number of slots).
 template <typename T, int KB, bool BUF>
 __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const SlotDev* __restrict__ sl,
                                                          const Tile* __restrict__ tiles,
                                                          int64_t ntiles, int k, int r, int yin,
-                                                         int yout, int single) {
+                                                         int yout) {
   using C = RowCfg<T, KB>;
   const int64_t b = xcd_block(ntiles);
   if (b >= ntiles) return;
-  // a launch over one slot needs no work list: tile b is block b
-  const Tile t = single >= 0 ? Tile{single, (int32_t)b} : tiles[b];
+  const Tile t = tiles[b];
   const SlotDev& d = sl[t.slot];
-  const int64_t row = (int64_t)t.blk * kGatherRows + threadIdx.x / C::G;
-  const int q = threadIdx.x % C::G;
-  const bool live = row < d.n;
-  const int ch = q % C::NCH;
-  const T sd = (T)d.cheb_s_diag;
-  T yi[C::V16], acc[C::V16];
   if constexpr (BUF) {
-    // Everything the row needs besides its neighbours is requested before
-    // the slot's done flag is tested (all of it in bounds either way), so the
-    // flag, the row bounds and the row's own data share one memory latency.
-    const int64_t rs = live ? row : 0;
-    const uint32_t oo = (uint32_t)rs * (uint32_t)(KB * sizeof(T)) + (uint32_t)(ch * 16);
-    const int64_t xb = d.n * KB * (int64_t)sizeof(T);
-    const BufRsrc rx = buf_rsrc(SB<T>::blk(d, yin), xb);
-    const auto own = buf_vec16<T, C::V16>(rx, oo);
-    const auto ri = buf_vec16<T, C::V16>(buf_rsrc(SB<T>::blk(d, r), xb), oo);
-    auto yo = buf_vec16<T, C::V16>(buf_rsrc(SB<T>::blk(d, yout), xb), oo);  // y_{k-1}
-    const T cd = glob(SB<T>::cdinv(d))[rs];
-    const T alpha = (T)*glob(&d.cheb->alpha[k]);
-    const T bk = (T)*glob(&d.cheb->beta[k]);
-    const RowSpan sp = row_span(live, row, d.a_rp, d.a_tp, d.cheb_range);
-    asm volatile("" ::: "memory");  // keeps the requests above ahead of the test
-    if (slot_done(d)) return;
-#pragma unroll
-    for (int v = 0; v < C::V16; ++v) yi[v] = own.v[v];
-    spmm_span_buf<T, KB>(sp.ws, sp.nw, sp.ts, sp.len, q, buf_rsrc(d.a_col, d.nnz_ops * 4),
-                         buf_rsrc(SB<T>::w(d), d.nnz_ops * (int64_t)sizeof(T)), rx, (T)d.c_t,
-                         yi, acc);
-    if (!live || q >= C::NCH) return;
-    // lane q < NCH updates chunk q of the row
-    const T beta = bk * cd;
-#pragma unroll
-    for (int v = 0; v < C::V16; ++v) {
-      const T res = ri.v[v] - (acc[v] + sd * yi[v]);
-      yo.v[v] = yi[v] + (alpha * (yi[v] - yo.v[v]) + beta * res);
-    }
-    stv<T, C::V16>(SB<T>::blk(d, yout) + row * KB + q * C::V16, yo);
+    cheb_step_rows<T, KB, -1>(cheb_view<T>(d, r, yin, yout), t.blk, k);
   } else {
+    const int64_t row = (int64_t)t.blk * kGatherRows + threadIdx.x / C::G;
+    const int q = threadIdx.x % C::G;
+    const bool live = row < d.n;
+    const int ch = q % C::NCH;
+    const T sd = (T)d.cheb_s_diag;
+    T yi[C::V16], acc[C::V16];
     if (slot_done(d)) return;
     const T* yi_p = SB<T>::blk(d, yin);
     load_chunk<T, C::V16>(yi_p + (live ? row : 0) * KB + ch * C::V16, yi);
@@ -207,11 +258,22 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const
     auto yo = ldv<T, C::V16>(yo_p + o);  // y_{k-1} of this row
 #pragma unroll
     for (int v = 0; v < C::V16; ++v) {
-      const T res = ri.v[v] - (acc[v] + sd * yi[v]);
-      yo.v[v] = yi[v] + (alpha * (yi[v] - yo.v[v]) + beta * res);
+      const T res = ri.v[v] - fmaT(sd, yi[v], acc[v]);
+      yo.v[v] = yi[v] + fmaT(alpha, yi[v] - yo.v[v], beta * res);
     }
     stv<T, C::V16>(yo_p + o, yo);
   }
+}
+
+// One-slot form: the slot's view arrives in the kernel arguments and tile b
+// is block b, so no table is read before the rows; the entry range is a
+// template argument.
+template <typename T, int KB, int RANGE>
+__global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step1(ChebView<T> v,
+                                                                        int64_t ntiles, int k) {
+  const int64_t b = xcd_block(ntiles);
+  if (b >= ntiles) return;
+  cheb_step_rows<T, KB, RANGE>(v, b, k);
 }
 
 template <typename T>
@@ -221,26 +283,67 @@ void sl_cheb_first(const SlotDev* sl, const TileSet& ts, int r, int y, int yprev
   if (nt == 0) return;
   ME_DISPATCH_KB(ts.kb, { k_sl_cheb_first<T, KB><<<nt, kBlock, 0, s>>>(sl, tl, r, y, yprev); });
 }
+// The view of a slot from the host copy of its descriptor (device
+// addresses of the same fields the device-side view reads).
 template <typename T>
-void sl_cheb_step(const SlotDev* sl, const TileSet& ts, int k, int r, int yin, int yout,
-                  hipStream_t s) {
+static ChebView<T> cheb_view_host(const SlotDev& d, int r, int yin, int yout) {
+  ChebView<T> v;
+  v.n = d.n;
+  v.nnz_ops = d.nnz_ops;
+  v.a_rp = d.a_rp;
+  v.a_tp = d.a_tp;
+  v.a_col = d.a_col;
+  if constexpr (sizeof(T) == 8) {
+    v.a_w = d.a_w;
+    v.cdinv = d.cheb_dinv;
+    v.yin = d.b64[yin];
+    v.r = d.b64[r];
+    v.yout = d.b64[yout];
+  } else {
+    v.a_w = d.a_w32;
+    v.cdinv = d.cheb_dinv32;
+    v.yin = d.b32[yin];
+    v.r = d.b32[r];
+    v.yout = d.b32[yout];
+  }
+  v.alpha = (const double*)((const char*)d.cheb + offsetof(ChebCoef, alpha));
+  v.beta = (const double*)((const char*)d.cheb + offsetof(ChebCoef, beta));
+  v.done = (const int*)((const char*)d.ctrl + offsetof(Ctrl, done));
+  v.c_t = d.c_t;
+  v.s_diag = d.cheb_s_diag;
+  v.range = d.cheb_range;
+  return v;
+}
+
+template <typename T>
+void sl_cheb_step(const SlotDev* sl, const SlotDev* host_sl, const TileSet& ts, int k, int r,
+                  int yin, int yout, hipStream_t s) {
   if (ts.n_gather == 0) return;
   ME_DISPATCH_KB(ts.kb, {
     static_assert(RowCfg<T, KB>::ROWS == kGatherRows, "gather tile rows");
-    if (ts.buf)
+    if (ts.buf && ts.nslots == 1) {
+      const ChebView<T> v = cheb_view_host<T>(host_sl[ts.ids[0]], r, yin, yout);
+      const dim3 grid(xcd_grid(ts.n_gather)), blk(RowCfg<T, KB>::THREADS);
+      if (v.range == kRangeW)
+        k_sl_cheb_step1<T, KB, kRangeW><<<grid, blk, 0, s>>>(v, ts.n_gather, k);
+      else if (v.range == kRangeT)
+        k_sl_cheb_step1<T, KB, kRangeT><<<grid, blk, 0, s>>>(v, ts.n_gather, k);
+      else
+        k_sl_cheb_step1<T, KB, kRangeAll><<<grid, blk, 0, s>>>(v, ts.n_gather, k);
+    } else if (ts.buf)
       k_sl_cheb_step<T, KB, true><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
-          sl, ts.gather, ts.n_gather, k, r, yin, yout, ts.nslots == 1 ? ts.ids[0] : -1);
+          sl, ts.gather, ts.n_gather, k, r, yin, yout);
     else
       k_sl_cheb_step<T, KB, false><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
-          sl, ts.gather, ts.n_gather, k, r, yin, yout, ts.nslots == 1 ? ts.ids[0] : -1);
+          sl, ts.gather, ts.n_gather, k, r, yin, yout);
   });
 }
 template void sl_cheb_first<double>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
 template void sl_cheb_first<float>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
-template void sl_cheb_step<double>(const SlotDev*, const TileSet&, int, int, int, int,
-                                   hipStream_t);
-template void sl_cheb_step<float>(const SlotDev*, const TileSet&, int, int, int, int,
-                                  hipStream_t);
+template void sl_cheb_step<double>(const SlotDev*, const SlotDev*, const TileSet&, int, int,
+                                   int, int, hipStream_t);
+template void sl_cheb_step<float>(const SlotDev*, const SlotDev*, const TileSet&, int, int, int,
+                                  int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Residual R = AX - B X Lambda; W = R or D^-1 R (Jacobi); per tile: column

@@ -45,7 +45,7 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_spmm(int64_t n, co
   if (!live || q >= C::NCH) return;
   VecT<T, C::V16> o;
 #pragma unroll
-  for (int v = 0; v < C::V16; ++v) o.v[v] = acc[v] + s_diag * xi[v];
+  for (int v = 0; v < C::V16; ++v) o.v[v] = fmaT(s_diag, xi[v], acc[v]);
   stv<T, C::V16>(y + row * KB + q * C::V16, o);
 }
 
