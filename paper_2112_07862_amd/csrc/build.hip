@@ -867,34 +867,56 @@ __global__ void k_row_len_perm(int64_t n, const int32_t* perm, const int64_t* w_
 // of all rows ([a_rp[i], a_rp[i+1]), weight w_ij), then the T entries of all
 // rows ([a_tp[i], a_tp[i+1]), stored weight 1/T_i + 1/T_j).  A solve that
 // reads one kind of entry reads whole cache lines of it.
-__global__ void k_pack_perm(int64_t n, int64_t nnz_w, const int32_t* perm, const int32_t* iperm,
-                            const int64_t* woff, const int64_t* toff, const int64_t* w_rp,
-                            const int32_t* w_col, const double* w_val, const int64_t* t_rp,
-                            const int32_t* t_col, const double* invt, int32_t* a_rp,
-                            int32_t* a_tp, int32_t* a_col, double* a_w, float* a_w32) {
+// Packed preconditioner entry: column - row in the low 16 bits (two's
+// complement, clamped: only used when every offset fits), FP16 weight above.
+__device__ __forceinline__ uint32_t pack_entry(int64_t row, int32_t col, double w) {
+  int64_t d = (int64_t)col - row;
+  d = d > 32767 ? 32767 : (d < -32768 ? -32768 : d);
+  const _Float16 h = (_Float16)(float)w;
+  return (uint32_t)(uint16_t)(int16_t)d | ((uint32_t)__builtin_bit_cast(uint16_t, h) << 16);
+}
+
+__global__ void __launch_bounds__(kBlock) k_pack_perm(
+    int64_t n, int64_t nnz_w, const int32_t* perm, const int32_t* iperm, const int64_t* woff,
+    const int64_t* toff, const int64_t* w_rp, const int32_t* w_col, const double* w_val,
+    const int64_t* t_rp, const int32_t* t_col, const double* invt, int32_t* a_rp, int32_t* a_tp,
+    int32_t* a_col, double* a_w, float* a_w32, uint32_t* a_pk, int* max_offset) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i > n) return;
-  const int64_t ws = woff[i], ts = nnz_w + toff[i];
-  a_rp[i] = (int32_t)ws;
-  a_tp[i] = (int32_t)ts;
-  if (i == n) return;
-  const int32_t o = perm[i];
-  const int64_t nw = w_rp[o + 1] - w_rp[o];
-  for (int64_t t = 0; t < nw; ++t) {
-    a_col[ws + t] = iperm[w_col[w_rp[o] + t]];
-    const double v = w_val[w_rp[o] + t];
-    a_w[ws + t] = v;
-    a_w32[ws + t] = (float)v;
+  int64_t far = 0;  // largest |column - row| of this row
+  if (i <= n) {
+    const int64_t ws = woff[i], ts = nnz_w + toff[i];
+    a_rp[i] = (int32_t)ws;
+    a_tp[i] = (int32_t)ts;
   }
-  // T entries: weight 1/T_i + 1/T_j of the two-hop term (eq. (Q), reading R1)
-  const int64_t tb = t_rp[o], te = t_rp[o + 1];
-  for (int64_t t = tb; t < te; ++t) {
-    const int64_t k = ts + (t - tb);
-    a_col[k] = iperm[t_col[t]];
-    const double q = invt[o] + invt[t_col[t]];
-    a_w[k] = q;
-    a_w32[k] = (float)q;
+  if (i < n) {
+    const int64_t ws = woff[i], ts = nnz_w + toff[i];
+    const int32_t o = perm[i];
+    const int64_t nw = w_rp[o + 1] - w_rp[o];
+    for (int64_t t = 0; t < nw; ++t) {
+      const int32_t c = iperm[w_col[w_rp[o] + t]];
+      const double v = w_val[w_rp[o] + t];
+      a_col[ws + t] = c;
+      a_w[ws + t] = v;
+      a_w32[ws + t] = (float)v;
+      a_pk[ws + t] = pack_entry(i, c, v);
+      far = max(far, (int64_t)llabs((int64_t)c - i));
+    }
+    // T entries: weight 1/T_i + 1/T_j of the two-hop term (eq. (Q), reading R1)
+    const int64_t tb = t_rp[o], te = t_rp[o + 1];
+    for (int64_t t = tb; t < te; ++t) {
+      const int64_t k = ts + (t - tb);
+      const int32_t c = iperm[t_col[t]];
+      const double q = invt[o] + invt[t_col[t]];
+      a_col[k] = c;
+      a_w[k] = q;
+      a_w32[k] = (float)q;
+      a_pk[k] = pack_entry(i, c, q);
+      far = max(far, (int64_t)llabs((int64_t)c - i));
+    }
   }
+  int32_t f = far > INT32_MAX ? INT32_MAX : (int32_t)far;
+  for (int o = kWave / 2; o > 0; o >>= 1) f = max(f, __shfl_xor(f, o));
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(max_offset, f);
 }
 
 // dst[i'] = src[perm[i']] for a double array and its FP32 copy
@@ -1120,7 +1142,7 @@ static int build_pre_a_impl(const me_csr* W, const me_opts* o, hipStream_t s, Gr
 
   // ---- allocation 2: T columns and the merged operator
   size_t b2 = Arena::round(nnz_t * 4 + 4) + Arena::round((nnz + nnz_t) * 4 + 4) +
-              Arena::round((nnz + nnz_t) * 8 + 8) + Arena::round((nnz + nnz_t) * 4 + 4);
+              Arena::round((nnz + nnz_t) * 8 + 8) + 2 * Arena::round((nnz + nnz_t) * 4 + 4);
   void* mem2 = nullptr;
   ME_TRY(hipMallocAsync(&mem2, b2, s));
   g->mem2 = mem2;
@@ -1129,6 +1151,7 @@ static int build_pre_a_impl(const me_csr* W, const me_opts* o, hipStream_t s, Gr
   g->a_col = ar2.take<int32_t>(nnz + nnz_t + 1);
   g->a_w = ar2.take<double>(nnz + nnz_t + 1);
   g->a_w32 = ar2.take<float>(nnz + nnz_t + 1);
+  g->a_pk = ar2.take<uint32_t>(nnz + nnz_t + 1);
   g->mem_bytes += b2;
 
   k_twohop_lds<<<grid_lds, kWave, 0, s>>>(n, g->w_rp, g->w_col, 1, g->t_cnt, g->t_rp, g->t_col,
@@ -1167,19 +1190,25 @@ int build_pre_b(GraphOps* g, hipStream_t s) {
   k_row_len_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->w_rp, g->t_rp, wlen, tlen);
   scan_counts(n, wlen, woff, tile_tmp, s);
   scan_counts(n, tlen, toff, tile_tmp, s);
+  int* max_offset = g->dflags + 12;
   k_pack_perm<<<ceil_div(n + 1, kBlock), kBlock, 0, s>>>(
       n, nnz, g->perm, g->iperm, woff, toff, g->w_rp, g->w_col, g->w_val, g->t_rp, g->t_col,
-      g->invt, g->a_rp, g->a_tp, g->a_col, g->a_w, g->a_w32);
+      g->invt, g->a_rp, g->a_tp, g->a_col, g->a_w, g->a_w32, g->a_pk, max_offset);
   k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->qinv, g->qinv_s,
                                                        g->qinv32_s);
-  int hroots = 0;
+  // roots (2), the mu denominator's bits (4, 5) and the largest offset (12)
+  // in one read
+  int hf[16];
+  ME_TRY(hipMemcpyAsync(hf, g->dflags, sizeof(hf), hipMemcpyDeviceToHost, s));
+  ME_TRY(hipStreamSynchronize(s));
+  const int hroots = hf[roots - g->dflags];
   unsigned long long hmaxden = 0;
-  ME_TRY_STATUS(read_scalar(roots, &hroots, s));
-  ME_TRY_STATUS(read_scalar(maxden_bits, &hmaxden, s));
+  std::memcpy(&hmaxden, &hf[(int*)maxden_bits - g->dflags], 8);
   g->components = hroots;
   double maxden;
   std::memcpy(&maxden, &hmaxden, 8);
   g->maxden = maxden;
+  g->pk_ok = hf[12] <= 32767;
 
   g->needs_eps = !(hroots > 1 || n < 2);
   return ME_OK;

@@ -152,6 +152,11 @@ struct GraphOps {
   int32_t* a_col = nullptr;    // int32[nnz_w + nnz_t]
   double* a_w = nullptr;       // w_ij at the W positions, 1/T_i + 1/T_j at the T positions
   float* a_w32 = nullptr;
+  // the same entries packed for the FP32 preconditioner: bits 0-15 the
+  // column minus the row (int16), bits 16-31 the weight (FP16); usable when
+  // every |column - row| fits (pk_ok)
+  uint32_t* a_pk = nullptr;
+  bool pk_ok = false;
   double* scratch_d = nullptr;  // n doubles of build scratch
   int64_t *woff = nullptr, *toff = nullptr;  // row offsets of the packed blocks
   OrderArgs ord{};              // search arguments while the order is pending

@@ -41,6 +41,8 @@ struct SlotDev {
   const double* a_w;
   const float* a_w32;
   int64_t nnz_ops;  // entries of a_col / a_w (W and T)
+  const uint32_t* a_pk;  // packed entries of the FP32 preconditioner (pk_ok)
+  int pk_ok;
   double c_t, s_diag;
   const double* bdiag;  // null: B = I
   const double* dinv;   // diag(Op)^-1 (Jacobi preconditioner)
@@ -97,6 +99,7 @@ struct TileSet {
   const Tile* red = nullptr;       // reduction tiles (slot.per rows)
   int64_t n_gather = 0, n_elem64 = 0, n_elem32 = 0, n_red = 0;
   bool buf = false;                // every array below kBufMaxBytes (buffer loads)
+  bool pk = false;                 // every slot has packed preconditioner entries
   void* mem = nullptr;             // device allocation behind the lists
   std::vector<char> host;          // staging copy (kept until the next sync)
   std::vector<int> ids;            // slot ids (host)

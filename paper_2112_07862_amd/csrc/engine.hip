@@ -157,6 +157,8 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
   d.a_w = g.a_w;
   d.a_w32 = g.a_w32;
   d.nnz_ops = g.nnz_w + g.nnz_t + 1;
+  d.a_pk = g.a_pk;
+  d.pk_ok = g.pk_ok ? 1 : 0;
   if (sp.op == OP_A) {
     d.c_t = -g.mu;
     d.s_diag = g.eps;
@@ -231,9 +233,11 @@ int Engine::build_set(const std::vector<int>& ids, int kb, TileSet* ts) {
   const int rb64 = kBlock / lpr64(kb), rb32 = kBlock / lpr32(kb);
   std::vector<Tile> gat, e64, e32, red;
   ts->buf = o_.addressing == ME_ADDR_AUTO;
+  ts->pk = true;
   for (int id : ids) {
     const SlotDev& d = hdev_[id];
     ts->buf = ts->buf && d.n * kb * 8 < kBufMaxBytes && d.nnz_ops * 8 < kBufMaxBytes;
+    ts->pk = ts->pk && d.pk_ok;
     for (int64_t b = 0; b < ceil_div(d.n, kGatherRows); ++b) gat.push_back({id, (int32_t)b});
     for (int64_t b = 0; b < ceil_div(d.n, rb64); ++b) e64.push_back({id, (int32_t)b});
     for (int64_t b = 0; b < ceil_div(d.n, rb32); ++b) e32.push_back({id, (int32_t)b});

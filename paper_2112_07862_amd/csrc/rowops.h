@@ -211,6 +211,77 @@ __device__ __forceinline__ void spmm_span_buf(int32_t ws, int32_t nw, int32_t ts
     for (int o = C::NCH; o < C::G; o <<= 1) acc[v] += __shfl_xor(acc[v], o);
 }
 
+// The FP32 row product over packed entries (column - row in 16 bits, FP16
+// weight): one 32-bit load per entry.  rs is the row, clamped to 0 past the
+// end; an entry past the span (its load gives 0, by the buffer's range check
+// or by the explicit test of the 64-bit form) points at row rs with weight 0
+// and adds exactly 0.  BUFA selects buffer or 64-bit global addressing; both
+// visit the entries in the same order.
+template <int KB, int RANGE, bool BUFA>
+__device__ __forceinline__ void spmm_span_pk(int32_t ws, int32_t nw, int32_t ts, int32_t len,
+                                             int q, int64_t rs, const uint32_t* __restrict__ a_pk,
+                                             int64_t nnz_ops, const float* __restrict__ x,
+                                             int64_t n, float c_t,
+                                             const float (&xi)[RowCfg<float, KB>::V16],
+                                             float (&acc)[RowCfg<float, KB>::V16]) {
+  using C = RowCfg<float, KB>;
+  constexpr int V = C::V16, EPL = C::EPL, UNR = C::UNR;
+  const int ch = q % C::NCH, e0 = q / C::NCH;
+  BufRsrc rp{}, rx{};
+  if constexpr (BUFA) {
+    rp = buf_rsrc(a_pk, nnz_ops * 4);
+    rx = buf_rsrc(x, n * KB * 4);
+  }
+  const ME_GLOBAL uint32_t* gp = glob(a_pk);
+#pragma unroll
+  for (int v = 0; v < V; ++v) acc[v] = 0;
+  const int32_t mine = len > e0 ? (len - e0 + EPL - 1) / EPL : 0;  // this lane's entries
+  for (int32_t r = 0; r < mine; r += UNR) {
+    int32_t c[UNR];
+    float cf[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int32_t k = (r + u) * EPL + e0;
+      const bool ok = r + u < mine;
+      bool isw;
+      uint32_t at;
+      if constexpr (RANGE == kRangeW) {
+        isw = true;
+        at = (uint32_t)(ws + k);
+      } else if constexpr (RANGE == kRangeT) {
+        isw = false;
+        at = (uint32_t)(ts + k);
+      } else {
+        isw = k < nw;
+        at = (uint32_t)((isw ? ws : ts) + k);
+      }
+      uint32_t pv;
+      if constexpr (BUFA) pv = (uint32_t)buf_i32(rp, ok ? at * 4u : kBufOut);
+      else pv = ok ? gp[at] : 0u;
+      c[u] = (int32_t)rs + (int32_t)(int16_t)(pv & 0xffffu);
+      const float w = (float)__builtin_bit_cast(_Float16, (uint16_t)(pv >> 16));
+      cf[u] = isw ? w : c_t * w;
+    }
+    VecT<float, V> xj[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      if constexpr (BUFA)
+        xj[u] = buf_vec16<float, V>(rx, (uint32_t)c[u] * (uint32_t)(KB * 4) + (uint32_t)(ch * 16));
+      else
+        xj[u] = ldv<float, V>(x + (int64_t)c[u] * KB + ch * V);
+    }
+    asm volatile("" ::: "memory");  // every gather of the round in flight first
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v] = fmaT(cf[u], xi[v] - xj[u].v[v], acc[v]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+    for (int o = C::NCH; o < C::G; o <<= 1) acc[v] += __shfl_xor(acc[v], o);
+}
+
 template <typename T, int KB>
 __device__ __forceinline__ void spmm_row(bool live, int64_t row, int q,
                                          const int32_t* __restrict__ a_rp,

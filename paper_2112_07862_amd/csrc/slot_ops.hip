@@ -152,6 +152,7 @@ template <typename T>
 struct ChebView {
   int64_t n, nnz_ops;
   const int32_t *a_rp, *a_tp, *a_col;
+  const uint32_t* a_pk;
   const T *a_w, *cdinv, *yin, *r;
   T* yout;
   const double *alpha, *beta;
@@ -168,6 +169,7 @@ __device__ __forceinline__ ChebView<T> cheb_view(const SlotDev& d, int r, int yi
   v.a_rp = d.a_rp;
   v.a_tp = d.a_tp;
   v.a_col = d.a_col;
+  v.a_pk = d.a_pk;
   v.a_w = SB<T>::w(d);
   v.cdinv = SB<T>::cdinv(d);
   v.yin = SB<T>::blk(d, yin);
@@ -186,7 +188,7 @@ __device__ __forceinline__ ChebView<T> cheb_view(const SlotDev& d, int r, int yi
 // besides its neighbours is requested before the slot's done flag is tested
 // (all of it in bounds either way), so the flag, the row bounds and the
 // row's own data share one memory latency.
-template <typename T, int KB, int RANGE>
+template <typename T, int KB, int RANGE, bool PK>
 __device__ __forceinline__ void cheb_step_rows(const ChebView<T>& d, int64_t blk, int k) {
   using C = RowCfg<T, KB>;
   const int64_t row = blk * kGatherRows + threadIdx.x / C::G;
@@ -210,9 +212,15 @@ __device__ __forceinline__ void cheb_step_rows(const ChebView<T>& d, int64_t blk
   if (*glob(d.done)) return;
 #pragma unroll
   for (int v = 0; v < C::V16; ++v) yi[v] = own.v[v];
-  spmm_span_buf<T, KB, RANGE>(sp.ws, sp.nw, sp.ts, sp.len, q, buf_rsrc(d.a_col, d.nnz_ops * 4),
-                              buf_rsrc(d.a_w, d.nnz_ops * (int64_t)sizeof(T)), rx, (T)d.c_t, yi,
-                              acc);
+  if constexpr (PK) {
+    static_assert(sizeof(T) == 4, "packed entries serve the FP32 preconditioner");
+    spmm_span_pk<KB, RANGE, true>(sp.ws, sp.nw, sp.ts, sp.len, q, rs, d.a_pk, d.nnz_ops, d.yin,
+                                  d.n, (float)d.c_t, yi, acc);
+  } else {
+    spmm_span_buf<T, KB, RANGE>(sp.ws, sp.nw, sp.ts, sp.len, q, buf_rsrc(d.a_col, d.nnz_ops * 4),
+                                buf_rsrc(d.a_w, d.nnz_ops * (int64_t)sizeof(T)), rx, (T)d.c_t,
+                                yi, acc);
+  }
   if (!live || q >= C::NCH) return;
   // lane q < NCH updates chunk q of the row
   const T beta = bk * cd;
@@ -225,7 +233,7 @@ __device__ __forceinline__ void cheb_step_rows(const ChebView<T>& d, int64_t blk
 }
 
 // Work-list form (any number of slots).
-template <typename T, int KB, bool BUF>
+template <typename T, int KB, bool BUF, bool PK>
 __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const SlotDev* __restrict__ sl,
                                                          const Tile* __restrict__ tiles,
                                                          int64_t ntiles, int k, int r, int yin,
@@ -236,7 +244,7 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const
   const Tile t = tiles[b];
   const SlotDev& d = sl[t.slot];
   if constexpr (BUF) {
-    cheb_step_rows<T, KB, -1>(cheb_view<T>(d, r, yin, yout), t.blk, k);
+    cheb_step_rows<T, KB, -1, PK>(cheb_view<T>(d, r, yin, yout), t.blk, k);
   } else {
     const int64_t row = (int64_t)t.blk * kGatherRows + threadIdx.x / C::G;
     const int q = threadIdx.x % C::G;
@@ -247,8 +255,15 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const
     if (slot_done(d)) return;
     const T* yi_p = SB<T>::blk(d, yin);
     load_chunk<T, C::V16>(yi_p + (live ? row : 0) * KB + ch * C::V16, yi);
-    spmm_row<T, KB>(live, row, q, d.a_rp, d.a_tp, d.a_col, SB<T>::w(d), (T)d.c_t,
-                    d.cheb_range, yi_p, yi, acc);
+    if constexpr (PK) {
+      static_assert(sizeof(T) == 4, "packed entries serve the FP32 preconditioner");
+      const RowSpan sp = row_span(live, row, d.a_rp, d.a_tp, d.cheb_range);
+      spmm_span_pk<KB, -1, false>(sp.ws, sp.nw, sp.ts, sp.len, q, live ? row : 0, d.a_pk,
+                                  d.nnz_ops, yi_p, d.n, (float)d.c_t, yi, acc);
+    } else {
+      spmm_row<T, KB>(live, row, q, d.a_rp, d.a_tp, d.a_col, SB<T>::w(d), (T)d.c_t,
+                      d.cheb_range, yi_p, yi, acc);
+    }
     if (!live || q >= C::NCH) return;
     const T alpha = (T)*glob(&d.cheb->alpha[k]);
     const T beta = (T)*glob(&d.cheb->beta[k]) * glob(SB<T>::cdinv(d))[row];
@@ -268,12 +283,12 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const
 // One-slot form: the slot's view arrives in the kernel arguments and tile b
 // is block b, so no table is read before the rows; the entry range is a
 // template argument.
-template <typename T, int KB, int RANGE>
+template <typename T, int KB, int RANGE, bool PK>
 __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step1(ChebView<T> v,
                                                                         int64_t ntiles, int k) {
   const int64_t b = xcd_block(ntiles);
   if (b >= ntiles) return;
-  cheb_step_rows<T, KB, RANGE>(v, b, k);
+  cheb_step_rows<T, KB, RANGE, PK>(v, b, k);
 }
 
 template <typename T>
@@ -293,6 +308,7 @@ static ChebView<T> cheb_view_host(const SlotDev& d, int r, int yin, int yout) {
   v.a_rp = d.a_rp;
   v.a_tp = d.a_tp;
   v.a_col = d.a_col;
+  v.a_pk = d.a_pk;
   if constexpr (sizeof(T) == 8) {
     v.a_w = d.a_w;
     v.cdinv = d.cheb_dinv;
@@ -315,27 +331,39 @@ static ChebView<T> cheb_view_host(const SlotDev& d, int r, int yin, int yout) {
   return v;
 }
 
+template <typename T, int KB, bool PK>
+static void launch_cheb_step(const SlotDev* sl, const SlotDev* host_sl, const TileSet& ts, int k,
+                             int r, int yin, int yout, hipStream_t s) {
+  const dim3 grid(xcd_grid(ts.n_gather)), blk(RowCfg<T, KB>::THREADS);
+  if (ts.buf && ts.nslots == 1) {
+    const ChebView<T> v = cheb_view_host<T>(host_sl[ts.ids[0]], r, yin, yout);
+    if (v.range == kRangeW)
+      k_sl_cheb_step1<T, KB, kRangeW, PK><<<grid, blk, 0, s>>>(v, ts.n_gather, k);
+    else if (v.range == kRangeT)
+      k_sl_cheb_step1<T, KB, kRangeT, PK><<<grid, blk, 0, s>>>(v, ts.n_gather, k);
+    else
+      k_sl_cheb_step1<T, KB, kRangeAll, PK><<<grid, blk, 0, s>>>(v, ts.n_gather, k);
+  } else if (ts.buf) {
+    k_sl_cheb_step<T, KB, true, PK><<<grid, blk, 0, s>>>(sl, ts.gather, ts.n_gather, k, r, yin,
+                                                          yout);
+  } else {
+    k_sl_cheb_step<T, KB, false, PK><<<grid, blk, 0, s>>>(sl, ts.gather, ts.n_gather, k, r, yin,
+                                                           yout);
+  }
+}
+
 template <typename T>
 void sl_cheb_step(const SlotDev* sl, const SlotDev* host_sl, const TileSet& ts, int k, int r,
                   int yin, int yout, hipStream_t s) {
   if (ts.n_gather == 0) return;
   ME_DISPATCH_KB(ts.kb, {
     static_assert(RowCfg<T, KB>::ROWS == kGatherRows, "gather tile rows");
-    if (ts.buf && ts.nslots == 1) {
-      const ChebView<T> v = cheb_view_host<T>(host_sl[ts.ids[0]], r, yin, yout);
-      const dim3 grid(xcd_grid(ts.n_gather)), blk(RowCfg<T, KB>::THREADS);
-      if (v.range == kRangeW)
-        k_sl_cheb_step1<T, KB, kRangeW><<<grid, blk, 0, s>>>(v, ts.n_gather, k);
-      else if (v.range == kRangeT)
-        k_sl_cheb_step1<T, KB, kRangeT><<<grid, blk, 0, s>>>(v, ts.n_gather, k);
-      else
-        k_sl_cheb_step1<T, KB, kRangeAll><<<grid, blk, 0, s>>>(v, ts.n_gather, k);
-    } else if (ts.buf)
-      k_sl_cheb_step<T, KB, true><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
-          sl, ts.gather, ts.n_gather, k, r, yin, yout);
-    else
-      k_sl_cheb_step<T, KB, false><<<xcd_grid(ts.n_gather), RowCfg<T, KB>::THREADS, 0, s>>>(
-          sl, ts.gather, ts.n_gather, k, r, yin, yout);
+    if constexpr (sizeof(T) == 4) {
+      if (ts.pk) launch_cheb_step<T, KB, true>(sl, host_sl, ts, k, r, yin, yout, s);
+      else launch_cheb_step<T, KB, false>(sl, host_sl, ts, k, r, yin, yout, s);
+    } else {
+      launch_cheb_step<T, KB, false>(sl, host_sl, ts, k, r, yin, yout, s);
+    }
   });
 }
 template void sl_cheb_first<double>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
