@@ -400,6 +400,15 @@ struct FrontierLds {
   int64_t rs[kBfsThreads];
 };
 
+// The edges of a narrow level in LDS (neighbour, frontier position, "my
+// child" flag) when there are at most kEdgeLds of them.
+constexpr int kEdgeLds = 8192;
+struct EdgeLds {
+  int32_t ev[kEdgeLds];
+  int32_t ei[kEdgeLds];
+  int32_t ef[kEdgeLds];
+};
+
 __device__ __forceinline__ int32_t find_owner(const int32_t* off, int32_t n, int32_t e);
 
 // Stages fin[0..nin) (nin <= kBfsThreads); returns the number of edges.
@@ -533,7 +542,7 @@ __device__ __forceinline__ int64_t cm_component(const int64_t* __restrict__ rp,
                                                 int32_t* key, int32_t* eoff, int32_t* ev,
                                                 int32_t* ei, int32_t* ef, int32_t* perm,
                                                 int64_t off, int32_t start, int32_t lev0,
-                                                int32_t* s_wave, FrontierLds* f,
+                                                int32_t* s_wave, FrontierLds* f, EdgeLds* el,
                                                 int32_t* last_lev) {
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -584,6 +593,38 @@ __device__ __forceinline__ int64_t cm_component(const int64_t* __restrict__ rp,
     } else {
       // narrow level: one thread per frontier edge
       const int32_t m = stage_frontier(rp, fin, nin, f, s_wave);
+      if (m <= kEdgeLds) {
+        // edges, flags and their scan in LDS
+        for (int32_t e = tid; e < m; e += kBfsThreads) {
+          const int32_t i = find_owner(f->off, nin, e);
+          const int32_t v = col[f->rs[i] + (e - f->off[i])];
+          el->ev[e] = v;
+          el->ei[e] = i;
+          int32_t lv = ld_coherent(&level[v]);
+          if (lv < 0) {
+            const int32_t old = atomicCAS(&level[v], -1, lev + 1);
+            lv = old < 0 ? lev + 1 : old;
+          }
+          if (lv == lev + 1) atomicMin(&key[v], i);
+        }
+        __syncthreads();
+        for (int32_t e = tid; e < m; e += kBfsThreads) {
+          const int32_t v = el->ev[e];
+          el->ef[e] = (ld_coherent(&level[v]) == lev + 1 && ld_coherent(&key[v]) == el->ei[e]);
+        }
+        __syncthreads();
+        nout = block_exclusive_scan(el->ef, m, s_wave);
+        for (int32_t e = tid; e < m; e += kBfsThreads) {
+          const int32_t nxt = e + 1 < m ? el->ef[e + 1] : nout;
+          if (nxt != el->ef[e]) fout[el->ef[e]] = el->ev[e];
+        }
+        __syncthreads();
+        if (nout == 0) break;
+        placed += nout;
+        nin = nout;
+        ++lev;
+        continue;
+      }
       for (int32_t e = tid; e < m; e += kBfsThreads) {
         const int32_t i = find_owner(f->off, nin, e);
         const int32_t v = col[f->rs[i] + (e - f->off[i])];
@@ -656,6 +697,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_cm_order(const OrderArgs* args)
   __shared__ int32_t s_wave[kBfsThreads / kWave];
   __shared__ int32_t s_min;
   __shared__ FrontierLds f;
+  __shared__ EdgeLds el;
   const int tid = threadIdx.x;
   for (int64_t i = tid; i < n; i += kBfsThreads) {
     level[i] = -1;
@@ -664,7 +706,8 @@ __global__ void __launch_bounds__(kBfsThreads) k_cm_order(const OrderArgs* args)
   __syncthreads();
   int32_t last = 0;
   int64_t off =
-      cm_component(rp, col, level, key, eoff, ev, ei, ef, perm, 0, *start, 0, s_wave, &f, &last);
+      cm_component(rp, col, level, key, eoff, ev, ei, ef, perm, 0, *start, 0, s_wave, &f, &el,
+                   &last);
   // further components: the lowest unvisited node only grows
   int64_t ptr = 0;
   for (;;) {
@@ -681,7 +724,7 @@ __global__ void __launch_bounds__(kBfsThreads) k_cm_order(const OrderArgs* args)
     __syncthreads();
     if (nxt == INT32_MAX) break;
     off += cm_component(rp, col, level, key, eoff, ev, ei, ef, perm, off, nxt, last + 1, s_wave,
-                        &f, &last);
+                        &f, &el, &last);
   }
   if (tid == 0) {
     start[1] = last;

@@ -336,16 +336,17 @@ void Engine::iteration(const TileSet& ts) {
     if (tm) {
       for (int id : ts.ids) {
         const GraphOps& g = *sh_[id].sp.g;
-        // algorithmic bytes of one step: column index and weight of every
-        // entry of the preconditioner's operator, row bounds (8 B), D^-1_i,
-        // and the blocks y_k (neighbour rows counted once), y_{k-1}, R read
-        // and y_{k+1} written
+        // algorithmic bytes of one step: every entry of the preconditioner's
+        // operator (packed: 4 B; else column index and weight), row bounds
+        // (8 B), D^-1_i, and the blocks y_k (neighbour rows counted once),
+        // y_{k-1}, R read and y_{k+1} written
         const double sz = cheb32_ ? 4.0 : 8.0;
+        const double ent = (cheb32_ && ts.pk) ? 4.0 : 4.0 + sz;
         const int rg = hdev_[id].cheb_range;
         const double nnz = rg == kRangeW ? (double)g.nnz_w
                                          : (rg == kRangeT ? (double)g.nnz_t
                                                           : (double)(g.nnz_w + g.nnz_t));
-        cb += (4.0 + sz) * nnz + (double)g.n * (8.0 + sz) + 4.0 * (double)g.n * kb * sz;
+        cb += ent * nnz + (double)g.n * (8.0 + sz) + 4.0 * (double)g.n * kb * sz;
       }
     }
     const int w = cheb32_ ? BW32 : BW, y = cheb32_ ? BY32 : BY;

@@ -320,3 +320,37 @@ def test_global_addressing_identical(me, name, K, precision):
     assert torch.equal(X1, X2) and torch.equal(l1, l2)
     h1.close()
     h2.close()
+
+
+def test_mixed_without_packed_entries(me):
+    """An expander has no locality order that keeps every column within 2^15
+    of its row, so the FP32 preconditioner reads the full entry arrays
+    instead of the packed ones.  Sampled rows of A X - B X Lambda (the
+    oracle's row-wise operator) meet the certified bound, X is B-orthonormal,
+    and the eigenvalues agree with the FP64 solve."""
+    n = 70000
+    rng = np.random.default_rng(9)
+    i = np.concatenate([np.arange(n), np.repeat(np.arange(n), 2)])
+    j = np.concatenate([(np.arange(n) + 1) % n, rng.integers(0, n, 2 * n)])
+    g = sg.from_edges(n, i, j, np.ones(i.size))
+    h = me.build_graph_ops(g, precision="mixed")
+    iperm = np.empty(n, dtype=np.int64)
+    iperm[_np(h.order()).astype(np.int64)] = np.arange(n)
+    rows_all = np.repeat(np.arange(n), np.diff(g.rowptr))
+    assert np.abs(iperm[rows_all] - iperm[g.col]).max() > 32767
+    tol = 1e-6
+    X, lam, info = me.embed(h, 4, tol=tol, seed=0, precision="mixed")
+    assert info["status"] == 0, info
+    X, lam = _np(X), _np(lam)
+    b = _np(h.export()["b"])
+    G = X.T @ (b[:, None] * X)
+    assert np.abs(G - np.eye(4)).max() <= 1e-10
+    rows = np.sort(np.random.default_rng(3).choice(n, 200, replace=False)).tolist()
+    AX = oracle.operator_a_rows(g.n, g.rowptr, g.col, g.val, rows, h.mu, h.eps, X)
+    R = AX - b[rows, None] * X[rows] * lam[None, :]
+    bound = tol * np.abs(lam) * np.linalg.norm(b[:, None] * X, axis=0)
+    assert np.all(np.abs(R) <= bound[None, :] * 1.001), np.abs(R).max(axis=0) / bound
+    X2, lam2, info2 = me.embed(h, 4, tol=1e-8, seed=0, precision="fp64")
+    assert info2["status"] == 0, info2
+    np.testing.assert_allclose(lam, _np(lam2), rtol=1e-6)
+    h.close()
