@@ -69,43 +69,33 @@ __device__ __forceinline__ void load_compact(SmallWS& w, int m, const double* ga
   __syncthreads();
 }
 
-// LDS writes of one lane become visible to the other lanes of its wave.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Right-looking Cholesky of w.L (ma x ma, ma <= kMaxBasis <= one wave) in
-// place, by the first wave: lane i owns row i, so a column step needs only
-// the wave's own ordering, no workgroup barrier.  A column whose pivot falls
-// below `tol` is skipped (keep[k] = 0): its entries are zeroed and it takes
-// no part in later updates, so the factor restricted to the kept columns is
-// the Cholesky factor of the kept principal submatrix.
+// Right-looking Cholesky of w.L (ma x ma) in place.  A column whose pivot
+// falls below `tol` is skipped (keep[k] = 0): its entries are zeroed and it
+// takes no part in later updates, so the factor restricted to the kept
+// columns is the Cholesky factor of the kept principal submatrix.
 __device__ __forceinline__ void cholesky_skip(SmallWS& w, int ma, double tol) {
-  static_assert(kMaxBasis <= kWave, "one lane per row");
-  const int lane = threadIdx.x;
-  if (lane < kWave) {
-    for (int k = 0; k < ma; ++k) {
-      wave_lds_sync();
+  const int tid = threadIdx.x;
+  for (int k = 0; k < ma; ++k) {
+    if (tid == 0) {
       const double piv = w.L[k][k];
       const bool ok = piv > tol;
-      const double rk = ok ? 1.0 / sqrt(piv) : 0.0;
-      wave_lds_sync();
-      if (lane == 0) {
-        w.keep[k] = ok;
-        w.L[k][k] = ok ? sqrt(piv) : 1.0;
-        w.ev[k] = rk;
-      }
-      if (lane > k && lane < ma) w.L[lane][k] *= rk;
-      wave_lds_sync();
-      if (rk != 0.0 && lane > k && lane < ma) {
-        const double lik = w.L[lane][k];
-        for (int j = k + 1; j <= lane; ++j) w.L[lane][j] -= lik * w.L[j][k];
+      w.keep[k] = ok;
+      w.L[k][k] = ok ? sqrt(piv) : 1.0;
+      w.ev[k] = ok ? 1.0 / sqrt(piv) : 0.0;
+    }
+    __syncthreads();
+    const double rk = w.ev[k];
+    for (int i = k + 1 + tid; i < ma; i += blockDim.x) w.L[i][k] *= rk;
+    __syncthreads();
+    if (rk != 0.0) {
+      const int r = ma - k - 1;  // trailing size
+      for (int u = tid; u < r * r; u += blockDim.x) {
+        const int i = k + 1 + u / r, j = k + 1 + u % r;
+        if (j <= i) w.L[i][j] -= w.L[i][k] * w.L[j][k];
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // Keeps the columns with keep[] set: compacts idx, dsc, A (scaled G_A) and
@@ -152,8 +142,7 @@ __device__ __forceinline__ void compact_kept(SmallWS& w, int ma) {
   __syncthreads();
 }
 
-// Li = L^-1 by columns: thread j forms column j top to bottom from its own
-// earlier entries and rows of L, so no barrier is needed inside.
+// Li = L^-1 row by row: row i needs rows < i; entries of a row in parallel.
 __device__ __forceinline__ void tri_inverse(SmallWS& w, int ma) {
   const int tid = threadIdx.x;
   for (int i = tid; i < ma; i += blockDim.x) w.ev[i] = 1.0 / w.L[i][i];
@@ -162,14 +151,14 @@ __device__ __forceinline__ void tri_inverse(SmallWS& w, int ma) {
     if (j > i) w.Li[i][j] = 0.0;
   }
   __syncthreads();
-  for (int j = tid; j < ma; j += blockDim.x) {
-    for (int i = j; i < ma; ++i) {
+  for (int i = 0; i < ma; ++i) {
+    for (int j = tid; j <= i; j += blockDim.x) {
       double s = (i == j) ? 1.0 : 0.0;
       for (int k = j; k < i; ++k) s -= w.L[i][k] * w.Li[k][j];
       w.Li[i][j] = s * w.ev[i];
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // A <- Li A Li^T (symmetrised), using V as temporary.

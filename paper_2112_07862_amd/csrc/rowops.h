@@ -123,11 +123,12 @@ struct RowCfg {
   static constexpr int V16 = 16 / (int)sizeof(T);      // values per 16-byte chunk
   static constexpr int NCH = KB * (int)sizeof(T) / 16; // chunks per row
   // lanes per row: two entries per round (four for one-chunk rows), eight
-  // rounds in flight; fewer lanes per row and more loads in flight per lane
-  // measured faster than wider lane groups on the gather-bound products
+  // rounds in flight (six for one-chunk rows); fewer lanes per row and more
+  // loads in flight per lane measured faster than wider lane groups on the
+  // gather-bound products
   static constexpr int G = NCH == 1 ? 4 : 2 * NCH;
   static constexpr int EPL = G / NCH;                  // entries per round
-  static constexpr int UNR = 8;                        // rounds in flight
+  static constexpr int UNR = NCH == 1 ? 6 : 8;         // rounds in flight
   static constexpr int ROWS = 32;                      // rows per workgroup
   static constexpr int THREADS = ROWS * G;
 };
