@@ -5,7 +5,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmembed.so")
+# MEMBED_LIBRARY names another build of the library (the tuner's variants);
+# by default the in-tree build is loaded
+LIB_PATH = os.environ.get("MEMBED_LIBRARY") or os.path.join(_HERE, "libmembed.so")
 
 c_int, c_int64, c_double, c_void_p, c_size_t, c_uint64 = (
     ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t,

@@ -118,17 +118,36 @@ __device__ __forceinline__ double fmaT(double a, double b, double c) { return __
 // entry ranges of a row of the merged operator
 enum { kRangeAll = 0, kRangeW = 1, kRangeT = 2 };
 
+// Row mapping of the gathering kernels (build-time parameters; the defaults
+// are the fastest measured by paper_2112_07862_amd.tune on the manifold
+// workloads): lanes per row for one-chunk rows, entries per round for wider
+// rows, rounds in flight for each.
+#ifndef ME_ROW_LANES_1
+#define ME_ROW_LANES_1 4
+#endif
+#ifndef ME_ROW_EPL
+#define ME_ROW_EPL 2
+#endif
+#ifndef ME_ROW_UNR_1
+#define ME_ROW_UNR_1 6
+#endif
+#ifndef ME_ROW_UNR
+#define ME_ROW_UNR 8
+#endif
+
 template <typename T, int KB>
 struct RowCfg {
   static constexpr int V16 = 16 / (int)sizeof(T);      // values per 16-byte chunk
   static constexpr int NCH = KB * (int)sizeof(T) / 16; // chunks per row
-  // lanes per row: two entries per round (four for one-chunk rows), eight
-  // rounds in flight (six for one-chunk rows); fewer lanes per row and more
-  // loads in flight per lane measured faster than wider lane groups on the
-  // gather-bound products
-  static constexpr int G = NCH == 1 ? 4 : 2 * NCH;
+  // lanes per row (a power of two up to 32): by default two entries per
+  // round (four lanes for one-chunk rows), eight rounds in flight (six for
+  // one-chunk rows); fewer lanes per row and more loads in flight per lane
+  // measured faster than wider lane groups on the gather-bound products
+  static constexpr int G = NCH == 1 ? ME_ROW_LANES_1 : ME_ROW_EPL * NCH;
   static constexpr int EPL = G / NCH;                  // entries per round
-  static constexpr int UNR = NCH == 1 ? 6 : 8;         // rounds in flight
+  static constexpr int UNR = NCH == 1 ? ME_ROW_UNR_1 : ME_ROW_UNR;  // rounds in flight
+  static_assert(G >= NCH && G <= 32 && (G & (G - 1)) == 0, "lanes per row");
+  static_assert(UNR >= 1, "rounds in flight");
   static constexpr int ROWS = 32;                      // rows per workgroup
   static constexpr int THREADS = ROWS * G;
 };
