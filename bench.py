@@ -43,12 +43,30 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2112_07862_amd", "csrc", f)
                   for f in ("slot_ops.hip", "rowops.h", "engine.h", "common.h")]
 
 
-def kernel_source_hash() -> str:
+def code_text(text: str) -> str:
+    """Source text without // comments, trailing blanks and empty lines:
+    edits to comments leave the kernels, and their counters, unchanged."""
+    import re
+    out = []
+    for line in text.splitlines():
+        line = re.sub(r"//.*$", "", line).rstrip()
+        if line:
+            out.append(line)
+    return "\n".join(out)
+
+
+def kernel_source_hash(texts=None) -> str:
+    """sha256 of the code (comments stripped) of the kernel sources, or of
+    `texts` given in the same order."""
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+    if texts is None:
+        texts = []
+        for f in KERNEL_SOURCES:
+            with open(f, encoding="utf-8") as fh:
+                texts.append(fh.read())
+    for t in texts:
+        h.update(code_text(t).encode())
     return h.hexdigest()
 
 

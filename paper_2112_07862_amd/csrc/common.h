@@ -144,8 +144,7 @@ struct GraphOps {
   int32_t* iperm = nullptr;    // user index -> solver index
   double *qinv_s = nullptr, *b_s = nullptr, *dinv_s = nullptr, *pdinv_s = nullptr;
   float *qinv32_s = nullptr, *b32_s = nullptr, *dinv32_s = nullptr, *pdinv32_s = nullptr;
-  // merged difference-form operator in solver order: row i = [W cols | T cols]
-  // solver-order operator: W entries of row i at [a_rp[i], a_rp[i+1]),
+  // difference-form operator in solver order: W entries of row i at [a_rp[i], a_rp[i+1]),
   // T entries at [a_tp[i], a_tp[i+1]) (all W entries precede all T entries)
   int32_t* a_rp = nullptr;     // int32[n+1]
   int32_t* a_tp = nullptr;     // int32[n+1]

@@ -5,12 +5,13 @@
 //
 // Blocks are row-major n x KB.  Elementwise kernels give each row
 // LPR = KB / VEC lanes with one 16-byte vector each; the gathering kernels
-// (operator products) give each row G lanes (8 to 32 by row size) that
-// split the row's entries, 32 rows per workgroup.
+// (operator products) give each row G lanes (RowCfg: two entries per round
+// per 16-byte chunk by default) that split the row's entries, 32 rows per
+// workgroup.
 //
 // Difference-form operator (eq. (obj2) with the Laplacian identity of
-// Section 3.1): with the merged row [W columns | T columns] (T entries carry
-// the weight 1/T_i + 1/T_j),
+// Section 3.1): with a row's W entries (weight w_ij) and T entries (weight
+// 1/T_i + 1/T_j),
 //   (A x)_i = sum_{j in N(i)} w_ij (x_i - x_j)
 //             - mu sum_{j in T_i} (1/T_i + 1/T_j) (x_i - x_j) + eps x_i
 //   (Q x)_i = sum_{j in T_i} (1/T_i + 1/T_j) (x_i - x_j)

@@ -3,7 +3,7 @@
 // (operator assembly, sign convention and output copy), and small copies.
 //
 // Difference-form operator (eq. (obj2) with the Laplacian identity of
-// Section 3.1): with the merged row [W columns | T columns],
+// Section 3.1): with a row's W entries and T entries,
 //   (A x)_i = sum_{j in N(i)} w_ij (x_i - x_j)
 //             - mu sum_{j in T_i} (1/T_i + 1/T_j) (x_i - x_j) + eps x_i
 //   (Q x)_i = sum_{j in T_i} (1/T_i + 1/T_j) (x_i - x_j)
