@@ -362,12 +362,12 @@ __global__ void k_uf_count_roots(int64_t n, int32_t* parent, int* roots) {
 // Locality order of the solver.  The LOBPCG kernels gather the rows of the
 // neighbours (one- and two-hop) of every row; with the caller's node order
 // (random for sampled point clouds) each gather touches its own cache line.
-// Nodes are ordered by breadth-first level from a pseudo-peripheral node
-// (the lowest-numbered node on the last level of a search from node 0),
-// ties by node id, components one after the other: neighbours then lie
-// within a few level widths of each other.  Levels come from a
-// level-synchronous search; the order from a stable LSD radix sort on the
-// level, so the permutation is deterministic.
+// Nodes are put in Cuthill-McKee order from a pseudo-peripheral node (the
+// lowest-numbered node on the last level of a search from node 0),
+// components one after the other: neighbours then lie within a few level
+// widths of each other.  Both searches are level-synchronous, one workgroup
+// per graph (a batch runs the searches of all its graphs in one launch), and
+// deterministic: the order equals that of the sequential algorithm.
 // ---------------------------------------------------------------------------
 
 
@@ -531,11 +531,13 @@ __device__ __forceinline__ int32_t stage_frontier(const int64_t* __restrict__ rp
 // and ev, ei, ef (one int per edge).  Every level-l node claims its
 // unvisited neighbours and lowers their key to its own position (atomic
 // min); a child belongs to the node whose position is its key.  A narrow
-// level works on its frontier's edges in (frontier position, neighbour id)
-// order, one thread per edge, and an exclusive scan of the "my child" flags
-// over the edges places every child; a wide level (one thread per frontier
-// node) scans per-node child counts and each node writes its children in
-// row order.  Both give the sequential Cuthill-McKee order.
+// level (fewer than kBfsThreads nodes, staged in LDS) works on its
+// frontier's edges in (frontier position, neighbour id) order, one thread
+// per edge, and an exclusive scan of the "my child" flags over the edges
+// places every child (edges and flags in LDS up to kEdgeLds of them); a wide
+// level (one thread per frontier node) scans per-node child counts and each
+// node writes its children in row order.  Both give the sequential
+// Cuthill-McKee order.
 // Returns the number of nodes placed; *last_lev receives the last level.
 __device__ __forceinline__ int64_t cm_component(const int64_t* __restrict__ rp,
                                                 const int32_t* __restrict__ col, int32_t* level,
