@@ -14,7 +14,9 @@
 //   Rayleigh-Ritz in FP64                               one workgroup per slot
 //   P <- W C_W + P C_P,  X <- X C_X + P                 combine (also AX, AP)
 // Kernels skip slots whose device `done` flag is set, so the host enqueues
-// `check_every` iterations between reads of the flags.  A slot that stops
+// a round of iterations between reads of the flags: at most `check_every`,
+// fewer when the device's residual history says the first slot to finish
+// needs fewer.  A slot that stops
 // is certified (fresh A X, Rayleigh-Ritz on X, FP64 residuals); if the
 // certificate misses the tolerance the slot iterates again (at most three
 // times).
