@@ -93,6 +93,9 @@ struct Ctrl {
   // largest residual of the required columns at iteration i, at
   // rho_hist[i % kRhoHist] (the host's convergence-rate estimate)
   double rho_hist[kRhoHist];
+  // 1 / |r_j| of the last residual block: the FP16 preconditioner path
+  // scales its input columns to unit norm (FP16's range)
+  double rinv[kMaxBlockCols];
 };
 
 // Arguments of the breadth-first searches of one graph (device scratch; one

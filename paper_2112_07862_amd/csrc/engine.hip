@@ -335,6 +335,9 @@ void Engine::iteration(const TileSet& ts) {
   if (cheb_) {
     const int deg = o_.cheb_degree;
     double cb = 0.0;
+    bool h16 = cheb32_ && o_.cheb_iterates != ME_ITER_FP32 && sl_cheb_h_ok(hdev_.data(), ts);
+    if (h16 && o_.cheb_iterates == ME_ITER_AUTO)
+      h16 = (double)hdev_[ts.ids[0]].n * kb >= (double)(1 << 22);
     if (tm) {
       for (int id : ts.ids) {
         const GraphOps& g = *sh_[id].sp.g;
@@ -348,14 +351,20 @@ void Engine::iteration(const TileSet& ts) {
         const double nnz = rg == kRangeW ? (double)g.nnz_w
                                          : (rg == kRangeT ? (double)g.nnz_t
                                                           : (double)(g.nnz_w + g.nnz_t));
-        cb += ent * nnz + (double)g.n * (8.0 + sz) + 4.0 * (double)g.n * kb * sz;
+        if (h16)  // y_k, y_{k-1} read and y_{k+1} written in FP16, R in FP32
+          cb += 4.0 * nnz + (double)g.n * 12.0 + 10.0 * (double)g.n * kb;
+        else
+          cb += ent * nnz + (double)g.n * (8.0 + sz) + 4.0 * (double)g.n * kb * sz;
       }
     }
     const int w = cheb32_ ? BW32 : BW, y = cheb32_ ? BY32 : BY;
     const int r = cheb32_ ? BR32 : BR;
     int cur = ((deg - 1) % 2 == 0) ? w : y;
     int nxt = cur == w ? y : w;
-    if (cheb32_) {
+    if (h16) {
+      sl_to32_scaled(d_slots_, ts, BR, BR32, s_);
+      sl_cheb_first_h(d_slots_, ts, r, cur, nxt, s_);
+    } else if (cheb32_) {
       sl_to32(d_slots_, ts, BR, BR32, s_);
       sl_cheb_first<float>(d_slots_, ts, r, cur, nxt, s_);
     } else {
@@ -364,12 +373,14 @@ void Engine::iteration(const TileSet& ts) {
     {
       KScope ks(tm ? KT_CHEB : -1, s_, (deg - 1) * cb, tag_, deg - 1);
       for (int k = 1; k < deg; ++k) {
-        if (cheb32_) sl_cheb_step<float>(d_slots_, hdev_.data(), ts, k, r, cur, nxt, s_);
+        if (h16) sl_cheb_step_h(hdev_.data(), ts, k, r, cur, nxt, s_);
+        else if (cheb32_) sl_cheb_step<float>(d_slots_, hdev_.data(), ts, k, r, cur, nxt, s_);
         else sl_cheb_step<double>(d_slots_, hdev_.data(), ts, k, r, cur, nxt, s_);
         std::swap(cur, nxt);
       }
     }
-    if (cheb32_) sl_to64(d_slots_, ts, BW32, BW, s_);
+    if (h16) sl_to64_h(d_slots_, ts, BW32, BW, s_);
+    else if (cheb32_) sl_to64(d_slots_, ts, BW32, BW, s_);
   }
   sl_deflate(d_slots_, ts, BW, 0, s_);
   // W <- (W - X C) R^-1

@@ -302,6 +302,63 @@ __device__ __forceinline__ void spmm_span_pk(int32_t ws, int32_t nw, int32_t ts,
     for (int o = C::NCH; o < C::G; o <<= 1) acc[v] += __shfl_xor(acc[v], o);
 }
 
+// The same product over a block stored in FP16 (arithmetic in FP32): one
+// 16-byte chunk is 8 values.
+template <int KB, int RANGE>
+__device__ __forceinline__ void spmm_span_pk_h(int32_t ws, int32_t nw, int32_t ts, int32_t len,
+                                               int q, int64_t rs, const uint32_t* __restrict__ a_pk,
+                                               int64_t nnz_ops, const _Float16* __restrict__ x,
+                                               int64_t n, float c_t, const float (&xi)[8],
+                                               float (&acc)[8]) {
+  using C = RowCfg<_Float16, KB>;
+  constexpr int V = C::V16, EPL = C::EPL, UNR = C::UNR;
+  static_assert(V == 8, "8 FP16 values per chunk");
+  const int ch = q % C::NCH, e0 = q / C::NCH;
+  const BufRsrc rp = buf_rsrc(a_pk, nnz_ops * 4);
+  const BufRsrc rx = buf_rsrc(x, n * KB * 2);
+#pragma unroll
+  for (int v = 0; v < V; ++v) acc[v] = 0;
+  const int32_t mine = len > e0 ? (len - e0 + EPL - 1) / EPL : 0;  // this lane's entries
+  for (int32_t r = 0; r < mine; r += UNR) {
+    int32_t c[UNR];
+    float cf[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int32_t k = (r + u) * EPL + e0;
+      const bool ok = r + u < mine;
+      bool isw;
+      uint32_t at;
+      if constexpr (RANGE == kRangeW) {
+        isw = true;
+        at = (uint32_t)(ws + k);
+      } else if constexpr (RANGE == kRangeT) {
+        isw = false;
+        at = (uint32_t)(ts + k);
+      } else {
+        isw = k < nw;
+        at = (uint32_t)((isw ? ws : ts) + k);
+      }
+      const uint32_t pv = (uint32_t)buf_i32(rp, ok ? at * 4u : kBufOut);
+      c[u] = (int32_t)rs + (int32_t)(int16_t)(pv & 0xffffu);
+      const float w = (float)__builtin_bit_cast(_Float16, (uint16_t)(pv >> 16));
+      cf[u] = isw ? w : c_t * w;
+    }
+    VecT<_Float16, V> xj[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+      xj[u] = buf_vec16<_Float16, V>(rx, (uint32_t)c[u] * (uint32_t)(KB * 2) + (uint32_t)(ch * 16));
+    asm volatile("" ::: "memory");  // every gather of the round in flight first
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v] = fmaT(cf[u], xi[v] - (float)xj[u].v[v], acc[v]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+    for (int o = C::NCH; o < C::G; o <<= 1) acc[v] += __shfl_xor(acc[v], o);
+}
+
 template <typename T, int KB>
 __device__ __forceinline__ void spmm_row(bool live, int64_t row, int q,
                                          const int32_t* __restrict__ a_rp,

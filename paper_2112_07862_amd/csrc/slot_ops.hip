@@ -367,6 +367,157 @@ void sl_cheb_step(const SlotDev* sl, const SlotDev* host_sl, const TileSet& ts, 
     }
   });
 }
+// FP16 storage of the iterates (arithmetic in FP32), one slot, W entries
+// only, packed entries: the input block is the FP32 residual scaled per
+// column to unit norm, so the iterates sit well inside FP16's range; the
+// column scale leaves the span of the preconditioned block unchanged.
+struct ChebViewH {
+  int64_t n, nnz_ops;
+  const int32_t *a_rp, *a_tp;
+  const uint32_t* a_pk;
+  const float *cdinv, *r;
+  const _Float16* yin;
+  _Float16* yout;
+  const double *alpha, *beta;
+  const int* done;
+  double s_diag;
+};
+
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_sl_cheb_first_h(const SlotDev* __restrict__ sl,
+                                                            const Tile* __restrict__ tiles, int r,
+                                                            int y, int yprev) {
+  using E = ElemCfg<float, KB>;
+  const Tile t = tiles[blockIdx.x];
+  const SlotDev& d = sl[t.slot];
+  if (slot_done(d)) return;
+  const int64_t row = (int64_t)t.blk * E::RB + threadIdx.x / E::LPR;
+  const int sub = threadIdx.x % E::LPR;
+  if (row >= d.n) return;
+  const float sc = (float)(1.0 / *glob(&d.cheb->theta)) * glob(d.cheb_dinv32)[row];
+  const int64_t o = row * KB + sub * E::VEC;
+  const auto v = ldv<float, E::VEC>(d.b32[r] + o);
+  VecT<_Float16, E::VEC> h, z;
+#pragma unroll
+  for (int q = 0; q < E::VEC; ++q) {
+    h.v[q] = (_Float16)(v.v[q] * sc);
+    z.v[q] = (_Float16)0;
+  }
+  stv<_Float16, E::VEC>((_Float16*)d.b32[y] + o, h);
+  stv<_Float16, E::VEC>((_Float16*)d.b32[yprev] + o, z);
+}
+
+template <int KB>
+__global__ void __launch_bounds__((RowCfg<_Float16, KB>::THREADS)) k_sl_cheb_step_h(ChebViewH d,
+                                                                                 int64_t ntiles,
+                                                                                 int k) {
+  using C = RowCfg<_Float16, KB>;
+  constexpr int V = C::V16;
+  const int64_t blk = xcd_block(ntiles);
+  if (blk >= ntiles) return;
+  const int64_t row = blk * kGatherRows + threadIdx.x / C::G;
+  const int q = threadIdx.x % C::G;
+  const bool live = row < d.n;
+  const int ch = q % C::NCH;
+  const int64_t rs = live ? row : 0;
+  const uint32_t oh = (uint32_t)rs * (uint32_t)(KB * 2) + (uint32_t)(ch * 16);
+  const uint32_t of = (uint32_t)rs * (uint32_t)(KB * 4) + (uint32_t)(ch * 32);
+  const BufRsrc rx = buf_rsrc(d.yin, d.n * KB * 2);
+  const BufRsrc rr = buf_rsrc(d.r, d.n * KB * 4);
+  const auto own = buf_vec16<_Float16, V>(rx, oh);
+  const auto r0 = buf_vec16<float, 4>(rr, of);
+  const auto r1 = buf_vec16<float, 4>(rr, of + 16);
+  const auto yo = buf_vec16<_Float16, V>(buf_rsrc(d.yout, d.n * KB * 2), oh);  // y_{k-1}
+  const float cd = glob(d.cdinv)[rs];
+  const float alpha = (float)*glob(&d.alpha[k]);
+  const float bk = (float)*glob(&d.beta[k]);
+  const RowSpan sp = row_span(live, row, d.a_rp, d.a_tp, kRangeW);
+  asm volatile("" ::: "memory");  // keeps the requests above ahead of the test
+  if (*glob(d.done)) return;
+  float yi[V], acc[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) yi[v] = (float)own.v[v];
+  spmm_span_pk_h<KB, kRangeW>(sp.ws, sp.nw, sp.ts, sp.len, q, rs, d.a_pk, d.nnz_ops, d.yin, d.n,
+                              0.0f, yi, acc);
+  if (!live || q >= C::NCH) return;
+  const float beta = bk * cd, sd = (float)d.s_diag;
+  VecT<_Float16, V> out;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const float ri = v < 4 ? r0.v[v] : r1.v[v - 4];
+    const float res = ri - fmaT(sd, yi[v], acc[v]);
+    out.v[v] = (_Float16)(yi[v] + fmaT(alpha, yi[v] - (float)yo.v[v], beta * res));
+  }
+  stv<_Float16, V>(d.yout + row * KB + q * V, out);
+}
+
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_sl_to64_h(const SlotDev* __restrict__ sl,
+                                                      const Tile* __restrict__ tiles, int from,
+                                                      int to) {
+  using E = ElemCfg<float, KB>;
+  const Tile t = tiles[blockIdx.x];
+  const SlotDev& d = sl[t.slot];
+  if (slot_done(d)) return;
+  const int64_t row = (int64_t)t.blk * E::RB + threadIdx.x / E::LPR;
+  const int sub = threadIdx.x % E::LPR;
+  if (row >= d.n) return;
+  const int64_t o = row * KB + sub * E::VEC;
+  const auto h = ldv<_Float16, E::VEC>((const _Float16*)d.b32[from] + o);
+#pragma unroll
+  for (int p = 0; p < E::VEC / 2; ++p) {
+    VecT<double, 2> v;
+    v.v[0] = (double)h.v[2 * p];
+    v.v[1] = (double)h.v[2 * p + 1];
+    stv<double, 2>(d.b64[to] + o + 2 * p, v);
+  }
+}
+
+bool sl_cheb_h_ok(const SlotDev* host_sl, const TileSet& ts) {
+  return ts.buf && ts.pk && ts.nslots == 1 && (ts.kb == 8 || ts.kb == 16) &&
+         host_sl[ts.ids[0]].cheb_range == kRangeW;
+}
+
+void sl_cheb_first_h(const SlotDev* sl, const TileSet& ts, int r, int y, int yprev,
+                     hipStream_t s) {
+  if (ts.n_elem32 == 0) return;
+  ME_DISPATCH_KB(ts.kb, { k_sl_cheb_first_h<KB><<<ts.n_elem32, kBlock, 0, s>>>(sl, ts.elem32, r, y, yprev); });
+}
+
+void sl_cheb_step_h(const SlotDev* host_sl, const TileSet& ts, int k, int r, int yin, int yout,
+                    hipStream_t s) {
+  if (ts.n_gather == 0) return;
+  const SlotDev& h = host_sl[ts.ids[0]];
+  ChebViewH v;
+  v.n = h.n;
+  v.nnz_ops = h.nnz_ops;
+  v.a_rp = h.a_rp;
+  v.a_tp = h.a_tp;
+  v.a_pk = h.a_pk;
+  v.cdinv = h.cheb_dinv32;
+  v.r = h.b32[r];
+  v.yin = (const _Float16*)h.b32[yin];
+  v.yout = (_Float16*)h.b32[yout];
+  v.alpha = (const double*)((const char*)h.cheb + offsetof(ChebCoef, alpha));
+  v.beta = (const double*)((const char*)h.cheb + offsetof(ChebCoef, beta));
+  v.done = (const int*)((const char*)h.ctrl + offsetof(Ctrl, done));
+  v.s_diag = h.cheb_s_diag;
+  const dim3 grid(xcd_grid(ts.n_gather));
+  if (ts.kb == 8) {
+    static_assert(RowCfg<_Float16, 8>::ROWS == kGatherRows, "gather tile rows");
+    k_sl_cheb_step_h<8><<<grid, RowCfg<_Float16, 8>::THREADS, 0, s>>>(v, ts.n_gather, k);
+  } else if (ts.kb == 16) {
+    k_sl_cheb_step_h<16><<<grid, RowCfg<_Float16, 16>::THREADS, 0, s>>>(v, ts.n_gather, k);
+  } else {
+    abort();
+  }
+}
+
+void sl_to64_h(const SlotDev* sl, const TileSet& ts, int from, int to, hipStream_t s) {
+  if (ts.n_elem32 == 0) return;
+  ME_DISPATCH_KB(ts.kb, { k_sl_to64_h<KB><<<ts.n_elem32, kBlock, 0, s>>>(sl, ts.elem32, from, to); });
+}
+
 template void sl_cheb_first<double>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
 template void sl_cheb_first<float>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
 template void sl_cheb_step<double>(const SlotDev*, const SlotDev*, const TileSet&, int, int,
@@ -489,6 +640,7 @@ __global__ void __launch_bounds__(kWave) k_sl_resid_finalize(const SlotDev* __re
     const double den = (al >= ctrl->lam_floor ? al : ctrl->lam_scale) * sqrt(tot[KB + lane]);
     const double rho = sqrt(tot[lane]) / den;
     ctrl->rho[lane] = rho;
+    ctrl->rinv[lane] = tot[lane] > 0.0 ? 1.0 / sqrt(tot[lane]) : 0.0;
     if (final_pass) ctrl->lam[lane] = lam[lane];
     conv = (lane < ctrl->need) && (rho <= ctrl->tol);
     if (lane < ctrl->need) worst = rho;
@@ -908,7 +1060,7 @@ void sl_deflate(const SlotDev* sl, const TileSet& ts, int blk, int cert, hipStre
 // FP64 <-> FP32 copies of a block (mixed-precision preconditioner)
 // ---------------------------------------------------------------------------
 
-template <int KB, bool TO32>
+template <int KB, bool TO32, bool SC = false>
 __global__ void __launch_bounds__(kBlock) k_sl_convert(const SlotDev* __restrict__ sl,
                                                        const Tile* __restrict__ tiles, int b64,
                                                        int b32) {
@@ -928,8 +1080,14 @@ __global__ void __launch_bounds__(kBlock) k_sl_convert(const SlotDev* __restrict
 #pragma unroll
     for (int h = 0; h < VEC / 2; ++h) {
       const auto v = ldv<double, 2>(p64 + 2 * h);
-      f.v[2 * h] = (float)v.v[0];
-      f.v[2 * h + 1] = (float)v.v[1];
+      if constexpr (SC) {  // columns scaled by 1 / |r_j|
+        const double* ri = d.ctrl->rinv + sub * VEC + 2 * h;
+        f.v[2 * h] = (float)(v.v[0] * glob(ri)[0]);
+        f.v[2 * h + 1] = (float)(v.v[1] * glob(ri)[1]);
+      } else {
+        f.v[2 * h] = (float)v.v[0];
+        f.v[2 * h + 1] = (float)v.v[1];
+      }
     }
     stv<float, VEC>(p32, f);
   } else {
@@ -948,6 +1106,12 @@ void sl_to32(const SlotDev* sl, const TileSet& ts, int from64, int to32, hipStre
   if (ts.n_elem32 == 0) return;
   ME_DISPATCH_KB(ts.kb, {
     k_sl_convert<KB, true><<<ts.n_elem32, kBlock, 0, s>>>(sl, ts.elem32, from64, to32);
+  });
+}
+void sl_to32_scaled(const SlotDev* sl, const TileSet& ts, int from64, int to32, hipStream_t s) {
+  if (ts.n_elem32 == 0) return;
+  ME_DISPATCH_KB(ts.kb, {
+    k_sl_convert<KB, true, true><<<ts.n_elem32, kBlock, 0, s>>>(sl, ts.elem32, from64, to32);
   });
 }
 void sl_to64(const SlotDev* sl, const TileSet& ts, int from32, int to64, hipStream_t s) {

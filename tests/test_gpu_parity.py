@@ -247,6 +247,32 @@ def test_embed_mixed_precision_matches_oracle(me, name, K):
     assert np.all(oracle.relative_residuals(ops["A"], ops["b"], X, lam) <= tol * 1.01 + 1e-12)
 
 
+@pytest.mark.parametrize("name,K", [("sphere_3k", 16), ("torus_2500", 8), ("swiss_3k", 8),
+                                    ("random_300", 5)])
+def test_embed_fp16_iterates_matches_oracle(me, name, K):
+    """FP16 storage of the Chebyshev iterates (block widths 8 and 16): the
+    same bar as the FP32 form.  The run differs from the FP32 one, so the FP16
+    kernels did the preconditioning; on graphs this small the automatic choice
+    is FP32, bit for bit."""
+    g, ops = oracle_ops(name)
+    lam_o, V_o = oracle.generalized_eigs(ops["A"], ops["b"], K)
+    relgap = (lam_o[K] - lam_o[K - 1]) / lam_o[K - 1]
+    tol = min(1e-6, 1e-5 * relgap / 4)
+    X, lam, info = me.embed(g, K, tol=tol, seed=1, precision="mixed", cheb_iterates="fp16")
+    assert info["status"] == 0, info
+    X, lam = _np(X), _np(lam)
+    np.testing.assert_array_less(np.abs(lam - lam_o[:K]) / np.abs(lam_o[:K]), 1e-6)
+    assert oracle.sin_principal_angle_b(X, V_o[:, :K], ops["b"]) <= 1e-5
+    assert oracle.b_orthonormality_error(X, ops["b"]) <= 1e-10
+    assert np.all(oracle.relative_residuals(ops["A"], ops["b"], X, lam) <= tol * 1.01 + 1e-12)
+    X32, _, i32 = me.embed(g, K, tol=tol, seed=1, precision="mixed", cheb_iterates="fp32")
+    Xa, _, ia = me.embed(g, K, tol=tol, seed=1, precision="mixed")
+    print(f"[gpu] {name} K={K} iterations fp16 {info['iterations']} fp32 {i32['iterations']}",
+          flush=True)
+    assert not np.array_equal(_np(X32), X)
+    assert torch.equal(Xa, torch.as_tensor(_np(X32)).to(Xa.device)) and ia["iterations"] == i32["iterations"]
+
+
 def cm_order_reference(g):
     """Cuthill-McKee order (pure Python, sequential): start at the lowest
     node on the last breadth-first level of a search from node 0; scan each
@@ -353,4 +379,11 @@ def test_mixed_without_packed_entries(me):
     X2, lam2, info2 = me.embed(h, 4, tol=1e-8, seed=0, precision="fp64")
     assert info2["status"] == 0, info2
     np.testing.assert_allclose(lam, _np(lam2), rtol=1e-6)
+    # the 64-bit-address form of the unpacked FP32 step: the same pairs, bit for bit
+    h3 = me.build_graph_ops(g, precision="mixed", addressing="global")
+    assert h3.eps == h.eps
+    X3, lam3, info3 = me.embed(h3, 4, tol=tol, seed=0, precision="mixed", addressing="global")
+    assert info3["iterations"] == info["iterations"]
+    assert np.array_equal(_np(X3), X) and np.array_equal(_np(lam3), lam)
+    h3.close()
     h.close()
