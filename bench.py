@@ -38,7 +38,12 @@ KERNEL_NAMES = {"spmm": "k_spmm (difference-form SpMM of A on the LOBPCG block)"
                 "cheb": "k_cheb_step (Chebyshev preconditioner step: fused SpMM + recurrence)"}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cheb_step_swiss_roll_100k_hbm_bytes.txt")
+# committed rocprofv3 counter summaries of the Chebyshev step, by (workload,
+# precision, iterate storage), each taken at the default degree and eps target
+TRAFFIC_FILES = {
+    ("swiss_roll_100k", "mixed", "fp32"): "cheb_step_swiss_roll_100k_hbm_bytes.txt",
+    ("sphere_1m", "mixed", "fp16"): "cheb_step_fp16_sphere_1m.txt",
+}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2112_07862_amd", "csrc", f)
                   for f in ("slot_ops.hip", "rowops.h", "engine.h", "common.h")]
 
@@ -70,13 +75,17 @@ def kernel_source_hash(texts=None) -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(args):
     """HBM bytes per launch of the Chebyshev step from the committed
-    rocprofv3 counter summary, or None when the kernel sources changed since
-    the counters were taken."""
+    rocprofv3 counter summary of this workload and configuration, or None
+    when there is none or the kernel sources changed since the counters were
+    taken."""
+    name = TRAFFIC_FILES.get((args.workload, args.precision, args.cheb_iterates))
+    if name is None or args.cheb_degree != 128 or args.eps_tol is not None:
+        return None
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as fh:
+        with open(os.path.join(ROOT, "profiles", name)) as fh:
             for line in fh:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
@@ -273,6 +282,8 @@ def main() -> int:
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--time-kernel", default="cheb", choices=list(KERNELS))
     ap.add_argument("--cheb-degree", type=int, default=128)
+    ap.add_argument("--cheb-iterates", default="fp32", choices=["fp32", "fp16"],
+                    help="storage of the Chebyshev iterates (mixed precision)")
     ap.add_argument("--eps-tol", type=float, default=None)
     ap.add_argument("--cpu-sample-n", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -316,7 +327,8 @@ def main() -> int:
     dcsr = me.to_device(g)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    opts = dict(precision=args.precision, seed=0, cheb_degree=args.cheb_degree)
+    opts = dict(precision=args.precision, seed=0, cheb_degree=args.cheb_degree,
+                cheb_iterates=args.cheb_iterates)
     if args.eps_tol is not None:
         opts["eps_tol"] = args.eps_tol
 
@@ -366,7 +378,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "manifold": kind, "n": n, "knn": knn, "K": K,
                    "tol": tol, "precision": args.precision, "preconditioner": "chebyshev",
-                   "cheb_degree": args.cheb_degree, "seed": 0},
+                   "cheb_degree": args.cheb_degree, "cheb_iterates": args.cheb_iterates,
+                   "seed": 0},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                        "p99": float(np.percentile(lat, 99) * 1e3)},
         "iterations": int(np.median([i["iterations"] for i in infos])),
@@ -382,7 +395,7 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic() if args.time_kernel == "cheb" else None,
+            "traffic": measured_traffic(args) if args.time_kernel == "cheb" else None,
             "launches": kt["launches"],
             "avg_us": avg_ms * 1e3,
             "bytes_per_launch": kt["bytes"] / max(kt["launches"], 1),

@@ -73,16 +73,16 @@ enum { ME_CHEB_LAPLACIAN = 0, ME_CHEB_FULL = 1 };
  * same; the option exists to exercise the large-graph form on small graphs. */
 enum { ME_ADDR_AUTO = 0, ME_ADDR_GLOBAL = 1 };
 /* Storage of the Chebyshev iterates in ME_MIXED (arithmetic stays FP32).
- * ME_ITER_FP16 stores them in FP16, the residual block scaled per column to
- * unit norm first; it applies to one-graph embedding solves with one-hop
- * entries (ME_CHEB_LAPLACIAN), block width 8 or 16, packed entries and
- * buffer addressing, and falls back to FP32 elsewhere.  It halves the bytes
- * of the iterates but rounds the preconditioner more coarsely, so LOBPCG may
- * take more iterations; the converged pairs meet the same FP64 residual test.
- * ME_ITER_AUTO (default) takes FP16 where it applies and an FP32 iterate
- * block holds at least 2^22 values (graphs whose step is bound by HBM
- * bandwidth rather than by cache latency), FP32 otherwise. */
-enum { ME_ITER_AUTO = 0, ME_ITER_FP32 = 1, ME_ITER_FP16 = 2 };
+ * ME_ITER_FP32 is the default.  ME_ITER_FP16 stores them in FP16, the
+ * residual block scaled per column to unit norm first; it applies to
+ * one-graph embedding solves with one-hop entries (ME_CHEB_LAPLACIAN), block
+ * width 8 or 16, packed entries and buffer addressing, and falls back to FP32
+ * elsewhere.  It halves the bytes of the iterates but rounds the
+ * preconditioner more coarsely, so LOBPCG takes more iterations, how many
+ * more depending on the graph: on uniform spheres a few (net gain where the
+ * step is bound by HBM bandwidth), on Swiss rolls up to 40% (net loss).  The
+ * converged pairs meet the same FP64 residual test either way. */
+enum { ME_ITER_FP32 = 0, ME_ITER_FP16 = 1 };
 
 /* Input graph W (Section 3.1), CSR, device memory, owned by the caller and
  * only read during the call.  rowptr int64[n+1] (rowptr[0] = 0), col int32[nnz]
@@ -111,7 +111,7 @@ typedef struct {
   int cheb_op;        /* operator the Chebyshev preconditioner inverts in the
                          embedding solve: ME_CHEB_LAPLACIAN (default) or ME_CHEB_FULL */
   int addressing;     /* ME_ADDR_AUTO (default) or ME_ADDR_GLOBAL                     */
-  int cheb_iterates;  /* ME_ITER_AUTO (default), ME_ITER_FP32 or ME_ITER_FP16            */
+  int cheb_iterates;  /* ME_ITER_FP32 (default) or ME_ITER_FP16                        */
 } me_opts;
 
 /* Per-solve report.  Times are host wall-clock milliseconds of the phases. */

@@ -20,7 +20,7 @@ ME_FP64, ME_MIXED = 0, 1
 ME_PRECOND_NONE, ME_PRECOND_JACOBI, ME_PRECOND_CHEBYSHEV = 0, 1, 2
 ME_CHEB_LAPLACIAN, ME_CHEB_FULL = 0, 1
 ME_ADDR_AUTO, ME_ADDR_GLOBAL = 0, 1
-ME_ITER_AUTO, ME_ITER_FP32, ME_ITER_FP16 = 0, 1, 2
+ME_ITER_FP32, ME_ITER_FP16 = 0, 1
 
 STATUS_NAMES = {
     0: "ME_OK", 1: "ME_WARN_NOT_CONVERGED", 2: "ME_WARN_EPS_ZERO", -1: "ME_ERR_INVALID_ARG",

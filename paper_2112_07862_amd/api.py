@@ -40,7 +40,7 @@ _PRECOND = {"none": L.ME_PRECOND_NONE, "jacobi": L.ME_PRECOND_JACOBI,
 
 _CHEB_OP = {"laplacian": L.ME_CHEB_LAPLACIAN, "full": L.ME_CHEB_FULL}
 _ADDRESSING = {"auto": L.ME_ADDR_AUTO, "global": L.ME_ADDR_GLOBAL}
-_ITERATES = {"auto": L.ME_ITER_AUTO, "fp32": L.ME_ITER_FP32, "fp16": L.ME_ITER_FP16}
+_ITERATES = {"fp32": L.ME_ITER_FP32, "fp16": L.ME_ITER_FP16}
 
 
 def make_opts(precision="fp64", precond="chebyshev", max_iter=None, eps_max_iter=None,

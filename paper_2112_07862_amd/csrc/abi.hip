@@ -23,7 +23,7 @@ bool me::opts_valid(const me_opts& o) {
          o.precond <= 2 && (o.precision == ME_FP64 || o.precision == ME_MIXED) &&
          o.eps_tol > 0 && (o.cheb_op == ME_CHEB_LAPLACIAN || o.cheb_op == ME_CHEB_FULL) &&
          (o.addressing == ME_ADDR_AUTO || o.addressing == ME_ADDR_GLOBAL) &&
-         o.cheb_iterates >= ME_ITER_AUTO && o.cheb_iterates <= ME_ITER_FP16 &&
+         (o.cheb_iterates == ME_ITER_FP32 || o.cheb_iterates == ME_ITER_FP16) &&
          (o.precond != ME_PRECOND_CHEBYSHEV ||
           (o.cheb_degree >= 2 && o.cheb_degree <= kMaxChebDegree));
 }
@@ -42,7 +42,7 @@ void me_opts_default(me_opts* o) {
   o->cheb_degree = 128;
   o->cheb_op = ME_CHEB_LAPLACIAN;
   o->addressing = ME_ADDR_AUTO;
-  o->cheb_iterates = ME_ITER_AUTO;
+  o->cheb_iterates = ME_ITER_FP32;
 }
 
 const char* me_status_string(int st) {

@@ -335,9 +335,8 @@ void Engine::iteration(const TileSet& ts) {
   if (cheb_) {
     const int deg = o_.cheb_degree;
     double cb = 0.0;
-    bool h16 = cheb32_ && o_.cheb_iterates != ME_ITER_FP32 && sl_cheb_h_ok(hdev_.data(), ts);
-    if (h16 && o_.cheb_iterates == ME_ITER_AUTO)
-      h16 = (double)hdev_[ts.ids[0]].n * kb >= (double)(1 << 22);
+    const bool h16 =
+        cheb32_ && o_.cheb_iterates == ME_ITER_FP16 && sl_cheb_h_ok(hdev_.data(), ts);
     if (tm) {
       for (int id : ts.ids) {
         const GraphOps& g = *sh_[id].sp.g;

@@ -55,7 +55,7 @@ def test_invalid_options_rejected_before_device_work():
                        ("precision", 2), ("max_iter", 0), ("check_every", 0),
                        ("eps_tol", 0.0), ("cheb_op", 2), ("cheb_op", -1),
                        ("addressing", 2), ("addressing", -1),
-                       ("cheb_iterates", 3), ("cheb_iterates", -1)]:
+                       ("cheb_iterates", 2), ("cheb_iterates", -1)]:
         o = _lib.MeOpts()
         lib.me_opts_default(ctypes.byref(o))
         setattr(o, field, val)

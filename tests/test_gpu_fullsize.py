@@ -9,7 +9,8 @@
 * Sphere, N = 1e6, 12-NN, K = 16: too large for the whole oracle; sampled
   rows are checked against the definitions (T_i, Q_ii, degrees, r_i, and
   (A X - B X Lambda)_i from the row-wise operator), b against the whole r
-  vector, X^T B X = I in FP64 on the host."""
+  vector, X^T B X = I in FP64 on the host; the same for a second solve with
+  FP16 Chebyshev iterates."""
 import numpy as np
 import pytest
 import torch
@@ -98,9 +99,24 @@ def test_sphere_1m_sampled(me):
     assert np.all(np.diff(lam) >= 0)
     G = X.T @ (ex["b"][:, None] * X)
     assert np.abs(G - np.eye(K)).max() <= 1e-10
-    # sampled rows of A X - B X Lambda, bounded by the certified norm
-    AX = oracle.operator_a_rows(g.n, g.rowptr, g.col, g.val, rows, h.mu, h.eps, X)
-    R = AX - ex["b"][rows, None] * X[rows] * lam[None, :]
-    bound = tol * np.abs(lam) * np.linalg.norm(ex["b"][:, None] * X, axis=0)
-    assert np.all(np.abs(R) <= bound[None, :] * 1.001), np.abs(R).max(axis=0) / bound
+    _check_sampled_rows(g, h, ex["b"], rows, X, lam, tol)
+    # FP16 Chebyshev iterates at full size: the same bars
+    X16, lam16, info16 = me.embed(h, K, tol=tol, cheb_iterates="fp16", **BENCH_OPTS)
+    print(f"[gpu] sphere fp16 iterates: iters {info16['iterations']}", flush=True)
+    assert info16["status"] == 0 and info16["max_residual"] <= tol, info16
+    X16, lam16 = _np(X16), _np(lam16)
+    assert not np.array_equal(X16, X)
+    np.testing.assert_allclose(lam16, lam, rtol=1e-5)
+    G16 = X16.T @ (ex["b"][:, None] * X16)
+    assert np.abs(G16 - np.eye(K)).max() <= 1e-10
+    _check_sampled_rows(g, h, ex["b"], rows, X16, lam16, tol)
     h.close()
+
+
+def _check_sampled_rows(g, h, b, rows, X, lam, tol):
+    """Sampled rows of A X - B X Lambda (the oracle's row-wise operator),
+    bounded by the certified norm tol |lambda_j| |B x_j|."""
+    AX = oracle.operator_a_rows(g.n, g.rowptr, g.col, g.val, rows, h.mu, h.eps, X)
+    R = AX - b[rows, None] * X[rows] * lam[None, :]
+    bound = tol * np.abs(lam) * np.linalg.norm(b[:, None] * X, axis=0)
+    assert np.all(np.abs(R) <= bound[None, :] * 1.001), np.abs(R).max(axis=0) / bound

@@ -252,8 +252,7 @@ def test_embed_mixed_precision_matches_oracle(me, name, K):
 def test_embed_fp16_iterates_matches_oracle(me, name, K):
     """FP16 storage of the Chebyshev iterates (block widths 8 and 16): the
     same bar as the FP32 form.  The run differs from the FP32 one, so the FP16
-    kernels did the preconditioning; on graphs this small the automatic choice
-    is FP32, bit for bit."""
+    kernels did the preconditioning; the default is FP32, bit for bit."""
     g, ops = oracle_ops(name)
     lam_o, V_o = oracle.generalized_eigs(ops["A"], ops["b"], K)
     relgap = (lam_o[K] - lam_o[K - 1]) / lam_o[K - 1]

@@ -9,8 +9,8 @@ def test_candidates_build_time_constraints():
     assert "default" in tune.CANDIDATES
     for name, c in tune.CANDIDATES.items():
         lanes1, epl, unr1, unr = c
-        for size in (4, 8):          # FP32, FP64
-            for kb in (4, 8, 16):
+        for size, kbs in ((2, (8, 16)), (4, (4, 8, 16)), (8, (4, 8, 16))):  # FP16, FP32, FP64
+            for kb in kbs:
                 nch = kb * size // 16
                 g = lanes1 if nch == 1 else epl * nch
                 assert g >= nch and g <= 32 and g & (g - 1) == 0, (name, size, kb, g)
