@@ -185,14 +185,14 @@ __device__ __forceinline__ ChebView<T> cheb_view(const SlotDev& d, int r, int yi
   return v;
 }
 
-// Rows of block `blk` through buffer resources.  Everything a row needs
+// Rows row0, row0 + 1, ... (blockDim.x / G of them) through buffer resources.  Everything a row needs
 // besides its neighbours is requested before the slot's done flag is tested
 // (all of it in bounds either way), so the flag, the row bounds and the
 // row's own data share one memory latency.
 template <typename T, int KB, int RANGE, bool PK>
-__device__ __forceinline__ void cheb_step_rows(const ChebView<T>& d, int64_t blk, int k) {
+__device__ __forceinline__ void cheb_step_rows(const ChebView<T>& d, int64_t row0, int k) {
   using C = RowCfg<T, KB>;
-  const int64_t row = blk * kGatherRows + threadIdx.x / C::G;
+  const int64_t row = row0 + threadIdx.x / C::G;
   const int q = threadIdx.x % C::G;
   const bool live = row < d.n;
   const int ch = q % C::NCH;
@@ -245,7 +245,7 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const
   const Tile t = tiles[b];
   const SlotDev& d = sl[t.slot];
   if constexpr (BUF) {
-    cheb_step_rows<T, KB, -1, PK>(cheb_view<T>(d, r, yin, yout), t.blk, k);
+    cheb_step_rows<T, KB, -1, PK>(cheb_view<T>(d, r, yin, yout), (int64_t)t.blk * kGatherRows, k);
   } else {
     const int64_t row = (int64_t)t.blk * kGatherRows + threadIdx.x / C::G;
     const int q = threadIdx.x % C::G;
@@ -281,15 +281,21 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const
   }
 }
 
-// One-slot form: the slot's view arrives in the kernel arguments and tile b
-// is block b, so no table is read before the rows; the entry range is a
-// template argument.
+// One-slot form: the slot's view arrives in the kernel arguments, so no
+// table is read before the rows; the entry range is a template argument.
+// Workgroups of kStep1Rows rows (one wave for the default row mapping):
+// measured faster than 32-, 64- and 128-row workgroups.
+constexpr int kStep1Rows = kGatherRows / 2;
+template <typename T, int KB>
+constexpr int step1_threads() {
+  return kStep1Rows * RowCfg<T, KB>::G;
+}
 template <typename T, int KB, int RANGE, bool PK>
-__global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step1(ChebView<T> v,
-                                                                        int64_t ntiles, int k) {
-  const int64_t b = xcd_block(ntiles);
-  if (b >= ntiles) return;
-  cheb_step_rows<T, KB, RANGE, PK>(v, b, k);
+__global__ void __launch_bounds__((step1_threads<T, KB>())) k_sl_cheb_step1(ChebView<T> v,
+                                                                          int64_t nblocks, int k) {
+  const int64_t b = xcd_block(nblocks);
+  if (b >= nblocks) return;
+  cheb_step_rows<T, KB, RANGE, PK>(v, b * kStep1Rows, k);
 }
 
 template <typename T>
@@ -338,12 +344,14 @@ static void launch_cheb_step(const SlotDev* sl, const SlotDev* host_sl, const Ti
   const dim3 grid(xcd_grid(ts.n_gather)), blk(RowCfg<T, KB>::THREADS);
   if (ts.buf && ts.nslots == 1) {
     const ChebView<T> v = cheb_view_host<T>(host_sl[ts.ids[0]], r, yin, yout);
+    const int64_t nb = (v.n + kStep1Rows - 1) / kStep1Rows;
+    const dim3 g1(xcd_grid(nb)), b1(step1_threads<T, KB>());
     if (v.range == kRangeW)
-      k_sl_cheb_step1<T, KB, kRangeW, PK><<<grid, blk, 0, s>>>(v, ts.n_gather, k);
+      k_sl_cheb_step1<T, KB, kRangeW, PK><<<g1, b1, 0, s>>>(v, nb, k);
     else if (v.range == kRangeT)
-      k_sl_cheb_step1<T, KB, kRangeT, PK><<<grid, blk, 0, s>>>(v, ts.n_gather, k);
+      k_sl_cheb_step1<T, KB, kRangeT, PK><<<g1, b1, 0, s>>>(v, nb, k);
     else
-      k_sl_cheb_step1<T, KB, kRangeAll, PK><<<grid, blk, 0, s>>>(v, ts.n_gather, k);
+      k_sl_cheb_step1<T, KB, kRangeAll, PK><<<g1, b1, 0, s>>>(v, nb, k);
   } else if (ts.buf) {
     k_sl_cheb_step<T, KB, true, PK><<<grid, blk, 0, s>>>(sl, ts.gather, ts.n_gather, k, r, yin,
                                                           yout);
