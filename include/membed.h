@@ -74,10 +74,12 @@ enum { ME_CHEB_LAPLACIAN = 0, ME_CHEB_FULL = 1 };
 enum { ME_ADDR_AUTO = 0, ME_ADDR_GLOBAL = 1 };
 /* Storage of the Chebyshev iterates in ME_MIXED (arithmetic stays FP32).
  * ME_ITER_FP32 is the default.  ME_ITER_FP16 stores them in FP16, the
- * residual block scaled per column to unit norm first; it applies to
- * one-graph embedding solves with one-hop entries (ME_CHEB_LAPLACIAN), block
- * width 8 or 16, packed entries and buffer addressing, and falls back to FP32
- * elsewhere.  It halves the bytes of the iterates but rounds the
+ * residual block scaled per column to unit norm first.  It applies to
+ * embedding solves of one graph at a time (me_embed, a batch of one graph, a
+ * server with max_active = 1) with one-hop entries (ME_CHEB_LAPLACIAN),
+ * block width 8 or 16, packed entries and buffer addressing, and falls back
+ * to FP32 elsewhere, so that a graph's result never depends on the rest of
+ * its batch.  It halves the bytes of the iterates but rounds the
  * preconditioner more coarsely, so LOBPCG takes more iterations, how many
  * more depending on the graph: on uniform spheres a few (net gain where the
  * step is bound by HBM bandwidth), on Swiss rolls up to 40% (net loss).  The

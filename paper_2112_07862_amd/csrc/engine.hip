@@ -335,8 +335,10 @@ void Engine::iteration(const TileSet& ts) {
   if (cheb_) {
     const int deg = o_.cheb_degree;
     double cb = 0.0;
-    const bool h16 =
-        cheb32_ && o_.cheb_iterates == ME_ITER_FP16 && sl_cheb_h_ok(hdev_.data(), ts);
+    // only in an engine of one graph, so that a graph's result never depends
+    // on which other graphs share its batch
+    const bool h16 = cheb32_ && cap_ == 1 && o_.cheb_iterates == ME_ITER_FP16 &&
+                     sl_cheb_h_ok(hdev_.data(), ts);
     if (tm) {
       for (int id : ts.ids) {
         const GraphOps& g = *sh_[id].sp.g;

@@ -272,6 +272,33 @@ def test_embed_fp16_iterates_matches_oracle(me, name, K):
     assert torch.equal(Xa, torch.as_tensor(_np(X32)).to(Xa.device)) and ia["iterations"] == i32["iterations"]
 
 
+def test_fp16_iterates_fall_back_where_they_do_not_apply(me):
+    """FP16 iterates serve one-slot embedding solves with one-hop entries,
+    block width 8 or 16, buffer addressing and mixed precision; everywhere
+    else the request runs the FP32 (or FP64) path, bit for bit."""
+    g, _ = oracle_ops("swiss_3k")
+    cases = [dict(K=8, precision="mixed", addressing="global"),
+             dict(K=8, precision="mixed", cheb_op="full"),
+             dict(K=4, precision="mixed"),
+             dict(K=8, precision="fp64")]
+    for c in cases:
+        c = dict(c)
+        K = c.pop("K")
+        h = me.build_graph_ops(g, **{k: v for k, v in c.items() if k != "cheb_op"})
+        X1, l1, i1 = me.embed(h, K, tol=1e-8, seed=3, cheb_iterates="fp32", **c)
+        X2, l2, i2 = me.embed(h, K, tol=1e-8, seed=3, cheb_iterates="fp16", **c)
+        assert i1["status"] == 0 and i1["iterations"] == i2["iterations"], (c, i1, i2)
+        assert torch.equal(X1, X2) and torch.equal(l1, l2), c
+        h.close()
+    # a batch runs several slots per launch: FP32 iterates
+    gs = [GRAPHS["square_2k"](), GRAPHS["torus_2500"]()]
+    r1 = me.embed_batch(gs, [8, 8], tol=1e-8, precision="mixed", cheb_iterates="fp32")
+    r2 = me.embed_batch(gs, [8, 8], tol=1e-8, precision="mixed", cheb_iterates="fp16")
+    for (Xa, la, ia), (Xb, lb, ib) in zip(r1, r2):
+        assert ia["status"] == 0 and ia["iterations"] == ib["iterations"]
+        assert torch.equal(Xa, Xb) and torch.equal(la, lb)
+
+
 def cm_order_reference(g):
     """Cuthill-McKee order (pure Python, sequential): start at the lowest
     node on the last breadth-first level of a search from node 0; scan each
