@@ -390,6 +390,9 @@ __device__ __forceinline__ int32_t ld_coherent(const int32_t* p) {
 }
 
 constexpr int kBfsThreads = 1024;
+// Neighbours of one node whose loads and atomics are issued together in the
+// node-parallel levels of the plain search.
+constexpr int kNbrGrp = 8;
 
 // A frontier of at most kBfsThreads nodes staged in LDS: node ids, first
 // edges and the exclusive scan of their degrees, so that one thread per edge
@@ -446,10 +449,19 @@ __device__ __forceinline__ int32_t bfs_levels(const int64_t* __restrict__ rp,
     } else {
       for (int32_t i = tid; i < nin; i += kBfsThreads) {
         const int32_t u = fin[i];
-        for (int64_t t = rp[u]; t < rp[u + 1]; ++t) {
-          const int32_t v = col[t];
-          if (ld_coherent(&level[v]) < 0 && atomicCAS(&level[v], -1, lev + 1) == -1)
-            fout[atomicAdd(&s_cnt[1], 1)] = v;
+        const int64_t t0 = rp[u], t1 = rp[u + 1];
+        for (int64_t t = t0; t < t1; t += kNbrGrp) {
+          int32_t v[kNbrGrp], lv[kNbrGrp];
+#pragma unroll
+          for (int j = 0; j < kNbrGrp; ++j)
+            if (t + j < t1) v[j] = col[t + j];
+#pragma unroll
+          for (int j = 0; j < kNbrGrp; ++j)
+            if (t + j < t1) lv[j] = ld_coherent(&level[v[j]]);
+#pragma unroll
+          for (int j = 0; j < kNbrGrp; ++j)
+            if (t + j < t1 && lv[j] < 0 && atomicCAS(&level[v[j]], -1, lev + 1) == -1)
+              fout[atomicAdd(&s_cnt[1], 1)] = v[j];
         }
       }
     }

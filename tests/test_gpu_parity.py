@@ -33,6 +33,8 @@ def _graphs():
         "sphere_3k": lambda: sg.manifold_graph("sphere", 3000, 12, 2),
         "torus_2500": lambda: sg.manifold_graph("torus", 2500, 8, 3),
         "random_300": lambda: sg.random_graph(300, 0.05, 4),
+        # levels of 1411 and 2166 nodes: the order's node-parallel form
+        "random_4000": lambda: sg.random_graph(4000, 0.0015, 7),
         "ring_40": lambda: sg.ring(40, 2),
         "ring_203": lambda: sg.ring(203, 3),
         "tri_mesh": lambda: sg.tri_mesh(3),
@@ -345,7 +347,7 @@ def cm_order_reference(g):
 
 
 @pytest.mark.parametrize("name", ["square_2k", "sphere_3k", "two_squares", "grid_bipartite",
-                                  "star_1500", "tri_mesh", "random_300"])
+                                  "star_1500", "tri_mesh", "random_300", "random_4000"])
 def test_solver_order_bit_exact(me, name):
     g, _ = oracle_ops(name)
     h = me.build_graph_ops(g)
