@@ -116,6 +116,22 @@ def test_batch_single_graph_matches_embed(me):
     assert oracle.sin_principal_angle_b(_np(X1), _np(X2), ops["b"]) <= 1e-6
 
 
+def test_batch_of_one_takes_fp16_iterates(me):
+    """A batch of one graph is an engine of one graph, so FP16 iterates apply
+    there (the run differs from the FP32 one) and its pairs agree with the
+    single-graph entry point's FP16 solve to the solve tolerance."""
+    g = sg.manifold_graph("square", 2000, 8, 0)
+    X1, l1, i1 = me.embed(g, 8, tol=1e-8, seed=0, precision="mixed", cheb_iterates="fp16")
+    X2, l2, i2 = me.embed_batch([g], [8], tol=1e-8, seed=0, precision="mixed",
+                                cheb_iterates="fp16")[0]
+    X3, l3, i3 = me.embed_batch([g], [8], tol=1e-8, seed=0, precision="mixed")[0]
+    assert i1["status"] == 0 and i2["status"] == 0 and i3["status"] == 0
+    assert not np.array_equal(_np(X2), _np(X3))
+    np.testing.assert_allclose(_np(l1), _np(l2), rtol=1e-9)
+    ops = oracle.build_ops(g.n, g.rowptr, g.col, g.val)
+    assert oracle.sin_principal_angle_b(_np(X1), _np(X2), ops["b"]) <= 1e-6
+
+
 def test_batch_failing_graph_isolated(me):
     """A malformed graph reports its own error; the others are unaffected."""
     good = sg.manifold_graph("square", 800, 8, 21)
