@@ -74,12 +74,14 @@ enum { ME_CHEB_LAPLACIAN = 0, ME_CHEB_FULL = 1 };
 enum { ME_ADDR_AUTO = 0, ME_ADDR_GLOBAL = 1 };
 /* Storage of the Chebyshev iterates in ME_MIXED (arithmetic stays FP32).
  * ME_ITER_FP32 is the default.  ME_ITER_FP16 stores them in FP16, the
- * residual block scaled per column to unit norm first.  It applies to
- * embedding solves of one graph at a time (me_embed, a batch of one graph, a
- * server with max_active = 1) with one-hop entries (ME_CHEB_LAPLACIAN),
- * block width 8 or 16, packed entries and buffer addressing, and falls back
- * to FP32 elsewhere, so that a graph's result never depends on the rest of
- * its batch.  It halves the bytes of the iterates but rounds the
+ * residual block scaled per column to unit norm first.  It applies to the
+ * embedding solve of a call that is given exactly one input graph (me_embed,
+ * me_embed_batch with G = 1) with one-hop entries (ME_CHEB_LAPLACIAN), block
+ * width 8 or 16, packed entries and buffer addressing, and falls back to FP32
+ * everywhere else: in a batch of two or more graphs (whatever happens to the
+ * others: failed, solved densely) and in every server request.  The choice
+ * depends only on the call, so a graph's result never depends on the rest of
+ * its batch or on the server's load.  It halves the bytes of the iterates but rounds the
  * preconditioner more coarsely, so LOBPCG takes more iterations, how many
  * more depending on the graph: on uniform spheres a few (net gain where the
  * step is bound by HBM bandwidth), on Swiss rolls up to 40% (net loss).  The
@@ -245,8 +247,9 @@ int me_embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_
  * current round runs, solves eps = lambda_2(Q) and then its embedding as
  * engine slots beside all other admitted requests, and is retired when its
  * embedding is certified; its memory then admits the next request.  A
- * request's result does not depend on the other requests (its arithmetic is
- * that of a batch of one).  One host thread drives a server. */
+ * request's result does not depend on the other requests: it is bitwise that
+ * of a batch of one with the same options and ME_ITER_FP32 (a server always
+ * stores the Chebyshev iterates in FP32).  One host thread drives a server. */
 typedef struct me_server me_server;
 typedef struct {
   size_t mem_budget; /* device bytes for admitted requests; 0 = 60% of free memory at creation */

@@ -205,17 +205,27 @@ def two_hop_components(n, t_rowptr, t_col) -> int:
 
 
 def fiedler_value(Q: sp.csr_matrix, components: int | None = None,
-                  dense_max: int = 3000) -> float:
+                  dense_max: int = 3000, method: str = "shift_invert") -> float:
     """eps = lambda_2(Q), the second smallest eigenvalue (Section 4.2).
 
-    Dense symmetric eigenvalues for N <= dense_max; otherwise ARPACK
-    shift-invert about a small negative shift (Q is singular).  When the two-
-    hop graph has more than one component the value is exactly 0 (R4)."""
+    Dense symmetric eigenvalues for N <= dense_max; otherwise ARPACK, either
+    shift-invert about a small negative shift (Q is singular; needs a sparse
+    LU of Q) or, with ``method="smallest"``, plain Lanczos for the smallest
+    algebraic eigenvalues of Q itself (matrix-vector products only: slower to
+    converge, but no factorisation, so it reaches graphs whose LU does not
+    fit).  When the two-hop graph has more than one component the value is
+    exactly 0 (R4)."""
     n = Q.shape[0]
     if components is not None and components > 1:
         return 0.0
     if n <= dense_max:
         return float(np.linalg.eigvalsh(Q.toarray())[1]) if n > 1 else 0.0
+    if method == "smallest":
+        vals = spla.eigsh(Q.tocsr(), k=6, which="SA", return_eigenvectors=False,
+                          tol=1e-13, ncv=48)
+        return float(np.sort(vals)[1])
+    if method != "shift_invert":
+        raise ValueError(method)
     scale = float(abs(Q.diagonal()).max())
     vals = spla.eigsh(Q.tocsc(), k=3, sigma=-1e-3 * scale, which="LM",
                       return_eigenvectors=False, tol=1e-14)
@@ -260,15 +270,18 @@ def b_from_radii(r: np.ndarray) -> np.ndarray:
     return r * (b1 / r[0])
 
 
-def build_ops(n, rowptr, col, val, reading: str = "R1") -> dict:
-    """All operators of the problem for one graph."""
+def build_ops(n, rowptr, col, val, reading: str = "R1",
+              eps_method: str = "shift_invert") -> dict:
+    """All operators of the problem for one graph (``eps_method``: the
+    ARPACK route of ``fiedler_value`` for large graphs)."""
     W = validate(n, rowptr, col, val)
     d = degrees(W)
     L = laplacian(W)
     t_rowptr, t_col, t_cnt = two_hop(W)
     Q = theta_sum_q(n, t_rowptr, t_col, reading=reading)
     ncomp = two_hop_components(n, t_rowptr, t_col)
-    eps = fiedler_value(Q, components=ncomp if reading == "R1" else None)
+    eps = fiedler_value(Q, components=ncomp if reading == "R1" else None,
+                        method=eps_method)
     mu = mu_from_q(Q, eps)
     A = operator_a(L, Q, mu, eps)
     r = gershgorin_radii(A)

@@ -40,10 +40,22 @@ def dense_generalized_eigs(A, b, K: int):
     return lam[:m], s[:, None] * Y[:, :m]
 
 
-def sparse_generalized_eigs(A, b, K: int, tol: float = 1e-13):
-    """K + 1 smallest pairs via ARPACK shift-invert on (A, B)."""
+def sparse_generalized_eigs(A, b, K: int, tol: float = 1e-13, method: str = "shift_invert"):
+    """K + 1 smallest pairs by ARPACK: shift-invert on (A, B) about a shift
+    just below zero (needs a sparse LU of A), or with ``method="smallest"``
+    plain Lanczos for the smallest algebraic eigenvalues of the symmetric
+    C = B^-1/2 A B^-1/2 (products only), the pairs (lambda, B^-1/2 y)."""
     A = sp.csr_matrix(A)
     b = np.asarray(b, dtype=np.float64)
+    if method == "smallest":
+        s = 1.0 / np.sqrt(b)
+        C = sp.diags(s) @ A @ sp.diags(s)
+        C = ((C + C.T) * 0.5).tocsr()
+        lam, Y = spla.eigsh(C, k=K + 1, which="SA", tol=tol, ncv=max(4 * (K + 1), 64))
+        order = np.argsort(lam)
+        return lam[order], s[:, None] * Y[:, order]
+    if method != "shift_invert":
+        raise ValueError(method)
     shift = -1e-3 * float(np.mean(A.diagonal()))
     lam, V = spla.eigsh(A.tocsc(), k=K + 1, M=sp.diags(b).tocsc(), sigma=shift,
                         which="LM", tol=tol)
@@ -51,12 +63,12 @@ def sparse_generalized_eigs(A, b, K: int, tol: float = 1e-13):
     return lam[order], V[:, order]
 
 
-def generalized_eigs(A, b, K: int, dense_max: int = 4000):
+def generalized_eigs(A, b, K: int, dense_max: int = 4000, method: str = "shift_invert"):
     n = A.shape[0]
     if n <= dense_max:
         lam, V = dense_generalized_eigs(A, b, K)
     else:
-        lam, V = sparse_generalized_eigs(A, b, K)
+        lam, V = sparse_generalized_eigs(A, b, K, method=method)
     V = b_orthonormalize(V, b)
     return lam, V
 

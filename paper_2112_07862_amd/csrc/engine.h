@@ -186,7 +186,11 @@ struct SlotResult {
 
 class Engine {
  public:
-  Engine(hipStream_t s, const me_opts& o, int capacity, bool timed);
+  // solo: the caller solves one input graph (me_embed, a batch of one
+  // graph), which alone may take FP16 Chebyshev iterates; the engine's
+  // capacity is not used for that, so that a graph's arithmetic never
+  // depends on which other graphs share a batch or a server
+  Engine(hipStream_t s, const me_opts& o, int capacity, bool timed, bool solo = false);
   ~Engine();
   int init();
   // Workspace of one slot (device bytes).
@@ -236,6 +240,7 @@ class Engine {
   me_opts o_;
   int cap_;
   bool timed_;
+  bool solo_;
   bool cheb_, cheb32_;
   std::vector<SlotHost> sh_;
   std::vector<SlotResult> res_;

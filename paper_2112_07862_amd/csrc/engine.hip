@@ -60,8 +60,8 @@ size_t Engine::slot_bytes(int64_t n, int kb) {
   return b;
 }
 
-Engine::Engine(hipStream_t s, const me_opts& o, int capacity, bool timed)
-    : s_(s), o_(o), cap_(capacity), timed_(timed) {
+Engine::Engine(hipStream_t s, const me_opts& o, int capacity, bool timed, bool solo)
+    : s_(s), o_(o), cap_(capacity), timed_(timed), solo_(solo) {
   cheb_ = o.precond == ME_PRECOND_CHEBYSHEV;
   cheb32_ = cheb_ && o.precision == ME_MIXED;
 }
@@ -335,9 +335,9 @@ void Engine::iteration(const TileSet& ts) {
   if (cheb_) {
     const int deg = o_.cheb_degree;
     double cb = 0.0;
-    // only in an engine of one graph, so that a graph's result never depends
-    // on which other graphs share its batch
-    const bool h16 = cheb32_ && cap_ == 1 && o_.cheb_iterates == ME_ITER_FP16 &&
+    // only when the caller solves one input graph, so that a graph's result
+    // never depends on which other graphs share its batch
+    const bool h16 = cheb32_ && solo_ && o_.cheb_iterates == ME_ITER_FP16 &&
                      sl_cheb_h_ok(hdev_.data(), ts);
     if (tm) {
       for (int id : ts.ids) {

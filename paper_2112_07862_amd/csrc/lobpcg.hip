@@ -188,7 +188,7 @@ int embed(const GraphOps& g, int K, double tol, const me_opts* o, const double* 
     kb = (int)g.n;
   } else {
     kb = block_width(K);
-    Engine e(s, *o, 1, true);
+    Engine e(s, *o, 1, true, /*solo=*/true);
     ME_TRY_STATUS(e.init());
     int id = -1;
     ME_TRY_STATUS(e.add(embed_slot_spec(g, K, tol, o, x0, X, lambda), ws, ws_bytes, &id));
@@ -284,7 +284,9 @@ int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opt
   {
     int cnt = 0;
     for (int i = 0; i < G; ++i) cnt += st[i] >= 0 && gs[i].n > kDenseMaxN;
-    Engine e(s, *o, std::max(cnt, 1), false);
+    // FP16 iterates only for a batch of one input graph (decided by G, not by
+    // how many graphs reach the engine)
+    Engine e(s, *o, std::max(cnt, 1), false, /*solo=*/G == 1);
     ME_TRY_STATUS(e.init());
     std::vector<int> id(G, -1);
     for (int i = 0; i < G; ++i) {

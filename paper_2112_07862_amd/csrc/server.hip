@@ -192,11 +192,19 @@ int Server::admit() {
       if (r->g.needs_eps) st = dense_eps_solve(r->g, side_, &eps);
       if (st >= 0) st = build_post(&r->g, eps, 0, side_);
       if (st >= 0) {
+        // a HIP failure here is this request's error: finish() releases its
+        // budget and reports it through me_server_poll
         double* buf = nullptr;
-        ME_TRY(hipMallocAsync((void**)&buf, embed_workspace_bytes(r->g, r->K, &so_.opts), side_));
-        dense_embed_solve(r->g, r->K, buf, r->X, r->lambda, side_);
-        ME_TRY(hipFreeAsync(buf, side_));
-        ME_TRY(hipStreamSynchronize(side_));
+        hipError_t he =
+            hipMallocAsync((void**)&buf, embed_workspace_bytes(r->g, r->K, &so_.opts), side_);
+        if (he == hipSuccess) {
+          dense_embed_solve(r->g, r->K, buf, r->X, r->lambda, side_);
+          he = hipFreeAsync(buf, side_);
+        }
+        if (he == hipSuccess) he = hipStreamSynchronize(side_);
+        if (he != hipSuccess) st = ME_ERR_HIP;
+      }
+      if (st >= 0) {
         r->info.block = (int)r->g.n;
         r->info.eps = r->g.eps;
         r->info.mu = r->g.mu;

@@ -25,7 +25,7 @@ __all__ = [
     "CSR", "from_edges", "sample_points", "knn_graph", "manifold_graph",
     "ring", "line", "complete", "star", "tri_mesh", "grid", "complete_bipartite",
     "random_graph", "disjoint_union", "initial_block", "batch_specs",
-    "serve_arrivals", "CONFIGS",
+    "serve_arrivals", "CONFIGS", "periodic_lattice", "lattice_stencil",
 ]
 
 
@@ -225,6 +225,51 @@ def random_graph(n: int, p: float, seed: int, wlo: float = 0.25, whi: float = 2.
     hi = np.maximum(i, j)
     key, first = np.unique(lo * n + hi, return_index=True)
     return from_edges(n, key // n, key % n, w[first])
+
+
+def lattice_stencil(name: str, sigma2: float = 2.0):
+    """Offsets and weights of a symmetric lattice stencil.  Weights are
+    Gaussian in the Euclidean length of the offset, exp(-|s|^2 / sigma2),
+    in the lattice's own geometry.
+
+    cross       : (+-1, 0), (0, +-1)                       (square lattice)
+    king        : cross plus (+-1, +-1)                    (square lattice)
+    triangular  : (+-1, 0), (0, +-1), +-(1, -1), all of length 1
+                  (the triangular lattice in a 60-degree basis)
+    """
+    if name == "cross":
+        offs = [(1, 0), (-1, 0), (0, 1), (0, -1)]
+        lens2 = [1.0] * 4
+    elif name == "king":
+        offs = [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1), (1, -1), (-1, 1)]
+        lens2 = [1.0] * 4 + [2.0] * 4
+    elif name == "triangular":
+        offs = [(1, 0), (-1, 0), (0, 1), (0, -1), (1, -1), (-1, 1)]
+        lens2 = [1.0] * 6
+    else:
+        raise ValueError(f"unknown stencil {name!r}")
+    return offs, [math.exp(-l2 / sigma2) for l2 in lens2]
+
+
+def periodic_lattice(n1: int, n2: int, offsets, weights) -> CSR:
+    """Graph on Z_n1 x Z_n2 (node (x, y) has id x * n2 + y) joining (x, y) to
+    ((x + a) mod n1, (y + b) mod n2) with weight w for each offset (a, b)
+    and weight w of the stencil.  The stencil must be symmetric (each offset's
+    negation listed with the same weight) and small enough for the lattice
+    that no two offsets land on the same node."""
+    offs = np.asarray(offsets, dtype=np.int64)
+    w = np.asarray(weights, dtype=np.float64)
+    n = n1 * n2
+    x, y = np.divmod(np.arange(n, dtype=np.int64), n2)
+    nb = ((x[:, None] + offs[None, :, 0]) % n1) * n2 + (y[:, None] + offs[None, :, 1]) % n2
+    order = np.argsort(nb, axis=1, kind="stable")
+    col = np.take_along_axis(nb, order, axis=1)
+    val = np.broadcast_to(w, nb.shape)
+    val = np.take_along_axis(val, order, axis=1)
+    if np.any(np.diff(col, axis=1) == 0) or np.any(col == np.arange(n)[:, None]):
+        raise ValueError("lattice too small for the stencil")
+    rowptr = np.arange(n + 1, dtype=np.int64) * offs.shape[0]
+    return CSR(n, rowptr, col.ravel().astype(np.int32), np.ascontiguousarray(val.ravel()))
 
 
 def disjoint_union(graphs) -> CSR:

@@ -15,13 +15,28 @@ def _args(**kw):
     return argparse.Namespace(**a)
 
 
-def test_traffic_only_from_the_matching_summary():
-    """Each committed summary serves only its own workload and
-    configuration; any other run reports no traffic."""
+def _recorded_hash(name):
+    with open(os.path.join(bench.ROOT, "profiles", name)) as fh:
+        for line in fh:
+            if line.startswith("kernel_sources_sha256:"):
+                return line.split(":", 1)[1].strip()
+    return None
+
+
+def test_traffic_only_from_the_matching_summary(monkeypatch):
+    """Each committed summary serves only its own workload and configuration
+    while the kernel sources still hash to the value it records; any other
+    run reports no traffic."""
     for (wl, prec, it), name in bench.TRAFFIC_FILES.items():
         assert os.path.exists(os.path.join(bench.ROOT, "profiles", name)), name
+        rec = _recorded_hash(name)
+        assert rec
+        monkeypatch.setattr(bench, "kernel_source_hash", lambda texts=None, rec=rec: rec)
         t = bench.measured_traffic(_args(workload=wl, precision=prec, cheb_iterates=it))
         assert t is not None and t > 0, (wl, prec, it)
+        monkeypatch.setattr(bench, "kernel_source_hash", lambda texts=None: "0" * 64)
+        assert bench.measured_traffic(_args(workload=wl, precision=prec, cheb_iterates=it)) is None
+    monkeypatch.undo()
     assert bench.measured_traffic(_args(workload="sphere_1m")) is None
     assert bench.measured_traffic(_args(precision="fp64")) is None
     assert bench.measured_traffic(_args(cheb_degree=96)) is None

@@ -5,6 +5,8 @@ a single solve (eigenvalues relative 1e-6, sine of the largest B-principal
 angle 1e-5 with the tolerance set from the smallest relative gap, X^T B X = I
 to 1e-10); a graph's result in a batch is bitwise identical to the same graph
 solved as a batch of one; a failing graph does not disturb the others."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -167,3 +169,76 @@ def test_batch_mix_recipe_small(me):
         assert info["status"] == 0, (name, info)
         assert np.max(np.abs(_np(lam) - lam_o[:K]) / np.abs(lam_o[:K])) <= 1e-6, name
         assert oracle.sin_principal_angle_b(_np(X), V_o[:, :K], ops["b"]) <= 1e-5, name
+
+
+def test_fp16_iterates_never_depend_on_the_batch(me):
+    """FP16 iterates are chosen by the call (one input graph), not by how many
+    graphs reach the solver: a large graph beside a tiny one (solved densely)
+    or beside a malformed one gets bitwise the FP32-iterate result it gets
+    beside a second large graph."""
+    big = sg.manifold_graph("square", 2000, 8, 0)
+    big2 = sg.manifold_graph("torus", 1800, 8, 1)
+    tiny = sg.tri_mesh(3)
+    bad = sg.manifold_graph("square", 500, 8, 2)
+    val = bad.val.copy()
+    val[5] = -1.0
+    bad = sg.CSR(bad.n, bad.rowptr, bad.col, val)
+    kw = dict(tol=1e-8, seed=0, precision="mixed", cheb_iterates="fp16")
+    ref = me.embed_batch([big, big2], [8, 8], **kw)[0]
+    fp32 = me.embed_batch([big, big2], [8, 8], tol=1e-8, seed=0, precision="mixed")[0]
+    assert torch.equal(ref[0], fp32[0])
+    for other, K in ((tiny, 3), (bad, 4)):
+        got = me.embed_batch([big, other], [8, K], **kw)[0]
+        assert got[2]["status"] == 0 and got[2]["iterations"] == ref[2]["iterations"]
+        assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+    solo = me.embed_batch([big], [8], **kw)[0]
+    assert not torch.equal(solo[0], ref[0])
+
+
+def _gen(spec):
+    kind, n, k, K, seed = spec
+    return sg.manifold_graph(kind, n, k, seed)
+
+
+def _oracle_of_spec(spec):
+    kind, n, k, K, seed = spec
+    g = sg.manifold_graph(kind, n, k, seed)
+    ops = oracle.build_ops(g.n, g.rowptr, g.col, g.val)
+    lam, V = oracle.generalized_eigs(ops["A"], ops["b"], K)
+    return ops["eps"], ops["b"], lam, V[:, :K]
+
+
+@pytest.mark.timeout(900)
+def test_batch_full_recipe_512(me):
+    """The full batched recipe: 512 graphs (seeds 1000 + g), N log-uniform in
+    [500, 20000], square / Swiss roll / torus, 8-NN, K in {4, 8, 16}, mixed
+    precision, tol 1e-6, one batched call.  Every graph converges; every 16th
+    graph is compared with the oracle (eps relative 1e-9, eigenvalues relative
+    1e-6, B-principal angle 1e-5 where tol / relgap allows it) and is bitwise
+    equal to the same graph solved as a batch of one."""
+    from concurrent.futures import ProcessPoolExecutor
+    specs = sg.batch_specs(count=512)
+    workers = min(16, os.cpu_count() or 1)
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        graphs = list(ex.map(_gen, specs, chunksize=8))
+        sample = list(range(0, 512, 16))
+        ref = dict(zip(sample, ex.map(_oracle_of_spec, [specs[q] for q in sample])))
+    Ks = [s[3] for s in specs]
+    tol = 1e-6
+    print(f"[gpu] batch recipe 512 graphs, total N {sum(g.n for g in graphs)}", flush=True)
+    res = me.embed_batch(graphs, Ks, tol=tol, seed=0, precision="mixed")
+    for q, (X, lam, info) in enumerate(res):
+        assert info["status"] == 0 and info["max_residual"] <= tol, (q, specs[q], info)
+    for q in sample:
+        X, lam, info = res[q]
+        eps_o, b, lam_o, V_o = ref[q]
+        K = Ks[q]
+        assert abs(info["eps"] - eps_o) <= 1e-9 * eps_o, (q, info["eps"], eps_o)
+        lam = _np(lam)
+        assert np.max(np.abs(lam - lam_o[:K]) / lam_o[:K]) <= 1e-6, (q, specs[q])
+        relgap = (lam_o[K] - lam_o[K - 1]) / lam_o[K - 1]
+        if tol / relgap <= 2.5e-6:
+            assert oracle.sin_principal_angle_b(_np(X), V_o, b) <= 1e-5, (q, specs[q])
+        Xa, la, ia = me.embed_batch([graphs[q]], [K], tol=tol, seed=0, precision="mixed")[0]
+        assert ia["iterations"] == info["iterations"], q
+        assert torch.equal(Xa, X) and torch.equal(la, res[q][1]), q

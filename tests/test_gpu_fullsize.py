@@ -1,26 +1,40 @@
 """Parity at full workload sizes, in the configuration bench.py times
-(mixed precision, Chebyshev degree 128).
+(mixed precision, Chebyshev degree 128), and in FP64.  No expected value
+comes from the HIP path.
 
 * Swiss roll, N = 1e5, 10-NN, K = 8: the oracle handles the whole graph
   (sparse products and ARPACK shift-invert), so everything is compared:
   T bit-exact, per-node scalars, eps and mu, eigenvalues (relative 1e-6),
   residuals recomputed by the oracle in FP64, X^T B X = I, and the principal
-  angle at the tolerance the relative gap requires.
-* Sphere, N = 1e6, 12-NN, K = 16: too large for the whole oracle; sampled
-  rows are checked against the definitions (T_i, Q_ii, degrees, r_i, and
-  (A X - B X Lambda)_i from the row-wise operator), b against the whole r
-  vector, X^T B X = I in FP64 on the host; the same for a second solve with
-  FP16 Chebyshev iterates."""
+  angle at the tolerance the relative gap requires; for the mixed-precision
+  path and for plain FP64.
+* Periodic king lattice 1250 x 800 (N = 1e6), Gaussian stencil weights:
+  every operator and eigenpair has a closed form (oracle.lattice), so eps,
+  mu, T_i, b, the 15 smallest eigenvalues and their eigenspace are compared
+  with it at the full million nodes.
+* Sphere, N = 1e6, 12-NN, K = 16: the oracle's values for this graph were
+  computed once by tests/golden/make_sphere_1m_reference.py (ARPACK on the
+  whole graph) and stored: the full two-hop pattern (by hash), eps, mu, the
+  17 smallest eigenvalues, per-node scalars on 200 sampled rows.  Sampled
+  rows of A X - B X Lambda use the oracle's row-wise operator with the
+  stored eps and mu."""
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
 
 import oracle
+from oracle import lattice as LT
 import synthgraphs as sg
 
 pytestmark = pytest.mark.gpu
 
 BENCH_OPTS = dict(precision="mixed", cheb_degree=128, seed=0)
+SPHERE_REF = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                          "sphere_1m_reference.json")
 
 
 @pytest.fixture(scope="module")
@@ -36,12 +50,27 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def test_swiss_roll_100k_bench_config(me):
+_swiss = {}
+
+
+def _swiss_oracle():
+    if not _swiss:
+        kind, n, knn, K, tol = sg.CONFIGS["swiss_roll_100k"]
+        g = sg.manifold_graph(kind, n, knn, 0)
+        ops = oracle.build_ops(g.n, g.rowptr, g.col, g.val)
+        lam_o, V_o = oracle.generalized_eigs(ops["A"], ops["b"], K, dense_max=0)
+        _swiss.update(g=g, ops=ops, lam_o=lam_o, V_o=V_o)
+    return _swiss["g"], _swiss["ops"], _swiss["lam_o"], _swiss["V_o"]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_swiss_roll_100k_bench_config(me, precision):
     kind, n, knn, K, tol = sg.CONFIGS["swiss_roll_100k"]
-    print(f"[gpu] full size {kind} n={n} K={K}", flush=True)
-    g = sg.manifold_graph(kind, n, knn, 0)
-    ops = oracle.build_ops(g.n, g.rowptr, g.col, g.val)
-    h = me.build_graph_ops(g, **BENCH_OPTS)
+    print(f"[gpu] full size {kind} n={n} K={K} {precision}", flush=True)
+    g, ops, lam_o, V_o = _swiss_oracle()
+    opts = dict(BENCH_OPTS, precision=precision)
+    h = me.build_graph_ops(g, **opts)
     ex = h.export()
     assert np.array_equal(_np(ex["t_rowptr"]), ops["t_rowptr"])
     assert np.array_equal(_np(ex["t_col"]), ops["t_col"])
@@ -51,9 +80,8 @@ def test_swiss_roll_100k_bench_config(me):
     assert abs(h.eps - ops["eps"]) <= 1e-9 * ops["eps"], (h.eps, ops["eps"])
     assert abs(h.mu - ops["mu"]) <= 1e-9 * ops["mu"]
     np.testing.assert_allclose(_np(ex["b"]), ops["b"], rtol=1e-8)
-    lam_o, V_o = oracle.generalized_eigs(ops["A"], ops["b"], K, dense_max=0)
     # the bench tolerance
-    X, lam, info = me.embed(h, K, tol=tol, **BENCH_OPTS)
+    X, lam, info = me.embed(h, K, tol=tol, **opts)
     assert info["status"] == 0, info
     lam, X = _np(lam), _np(X)
     assert np.max(np.abs(lam - lam_o[:K]) / lam_o[:K]) <= 1e-6, (lam, lam_o[:K])
@@ -63,7 +91,7 @@ def test_swiss_roll_100k_bench_config(me):
     # the principal-angle bar needs rho <= 1e-5 relgap (sin theta <= rho / relgap)
     relgap = (lam_o[K] - lam_o[K - 1]) / lam_o[K - 1]
     tol2 = min(tol, 1e-5 * relgap / 4)
-    X2, lam2, info2 = me.embed(h, K, tol=tol2, **BENCH_OPTS)
+    X2, lam2, info2 = me.embed(h, K, tol=tol2, **opts)
     assert info2["status"] == 0, info2
     s = oracle.sin_principal_angle_b(_np(X2), V_o[:, :K], ops["b"])
     print(f"[gpu] relgap {relgap:.3e} tol {tol2:.2e} sin {s:.2e}", flush=True)
@@ -71,52 +99,96 @@ def test_swiss_roll_100k_bench_config(me):
     h.close()
 
 
-def test_sphere_1m_sampled(me):
+def _sha(rowptr, col):
+    hh = hashlib.sha256()
+    hh.update(np.ascontiguousarray(rowptr, dtype=np.int64).tobytes())
+    hh.update(np.ascontiguousarray(col, dtype=np.int32).tobytes())
+    return hh.hexdigest()
+
+
+@pytest.mark.timeout(600)
+def test_lattice_1m_closed_form(me):
+    """A million-node periodic lattice against its closed form: eps, mu to
+    1e-9, T_i = 16 everywhere, b = 1, the 15 smallest eigenvalues to 1e-6
+    (K = 15 closes a cluster, relative gap 0.30), the B-principal angle to
+    the exact eigenspace (cos/sin of the 15 lowest modes) to 1e-5, in mixed
+    precision (bench configuration) and in FP64."""
+    n1, n2, K = 1250, 800, 15
+    offs, w = sg.lattice_stencil("king")
+    g = sg.periodic_lattice(n1, n2, offs, w)
+    cf = LT.lattice_spectrum(n1, n2, offs, w)
+    lam_cf, modes = LT.smallest(cf, K + 1)
+    assert K in LT.cluster_ends(lam_cf)
+    relgap = (lam_cf[K] - lam_cf[K - 1]) / lam_cf[K - 1]
+    basis = LT.mode_basis(n1, n2, modes[:K])
+    print(f"[gpu] lattice {n1}x{n2} king K={K} eps={cf['eps']:.6e} relgap={relgap:.3f}",
+          flush=True)
+    for precision in ("mixed", "fp64"):
+        h = me.build_graph_ops(g, precision=precision, seed=0)
+        assert abs(h.eps - cf["eps"]) <= 1e-9 * cf["eps"], (h.eps, cf["eps"])
+        assert abs(h.mu - cf["mu"]) <= 1e-9 * cf["mu"], (h.mu, cf["mu"])
+        ex = {k: _np(v) for k, v in h.export().items()}
+        assert np.all(ex["t_count"] == cf["t"]) and h.nnz_t == cf["t"] * g.n
+        np.testing.assert_allclose(ex["qdiag"], cf["qdiag"], rtol=1e-13)
+        np.testing.assert_allclose(ex["d"], cf["d"], rtol=1e-13)
+        np.testing.assert_allclose(ex["b"], 1.0, rtol=1e-9)
+        tol = min(1e-6, 1e-5 * relgap / 4)
+        X, lam, info = me.embed(h, K, tol=tol, precision=precision, seed=0)
+        print(f"[gpu] lattice {precision}: iters {info['iterations']} eps iters "
+              f"{info['eps_iterations']} rho {info['max_residual']:.2e}", flush=True)
+        assert info["status"] == 0, info
+        lam, X = _np(lam), _np(X)
+        assert np.max(np.abs(lam - lam_cf[:K]) / lam_cf[:K]) <= 1e-6, (lam, lam_cf[:K])
+        s = oracle.sin_principal_angle_b(X, basis, np.ones(g.n))
+        print(f"[gpu] lattice {precision}: sin {s:.2e}", flush=True)
+        assert s <= 1e-5
+        G = X.T @ X
+        assert np.abs(G - np.eye(K)).max() <= 1e-10
+        h.close()
+
+
+@pytest.mark.timeout(600)
+def test_sphere_1m_against_stored_oracle(me):
+    if not os.path.exists(SPHERE_REF):
+        pytest.skip("tests/golden/sphere_1m_reference.json not written yet")
+    with open(SPHERE_REF) as f:
+        ref = json.load(f)
     kind, n, knn, K, tol = sg.CONFIGS["sphere_1m"]
+    assert (ref["graph"]["n"], ref["graph"]["knn"], ref["K"]) == (n, knn, K)
     print(f"[gpu] full size {kind} n={n} K={K}", flush=True)
     g = sg.manifold_graph(kind, n, knn, 0)
+    assert _sha(g.rowptr, g.col) == ref["graph"]["w_sha256"]
     h = me.build_graph_ops(g, **BENCH_OPTS)
     ex = {k: _np(v) for k, v in h.export().items()}
-    rows = np.sort(np.random.default_rng(5).choice(n, 200, replace=False)).tolist()
-    t_rows = oracle.two_hop_rows(g.n, g.rowptr, g.col, rows)
-    trp, tcol = ex["t_rowptr"], ex["t_col"]
-    for i, t in zip(rows, t_rows):
-        assert np.array_equal(tcol[trp[i]:trp[i + 1]], t), i
-        assert ex["t_count"][i] == t.size
-    d = np.add.reduceat(g.val, g.rowptr[:-1])
-    np.testing.assert_allclose(ex["d"][rows], d[rows], rtol=1e-13)
-    qd = oracle.q_diag_rows(g.n, g.rowptr, g.col, rows)
-    np.testing.assert_allclose(ex["qdiag"][rows], qd, rtol=1e-13)
-    # r_i = d_i + mu Q_ii; b = r / geometric mean of r (over every node)
-    np.testing.assert_allclose(ex["r"][rows], d[rows] + h.mu * qd, rtol=1e-12)
-    b = np.exp(np.log(ex["r"]) - np.mean(np.log(ex["r"])))
-    np.testing.assert_allclose(ex["b"], b, rtol=1e-9)
-    X, lam, info = me.embed(h, K, tol=tol, **BENCH_OPTS)
-    print(f"[gpu] sphere iters {info['iterations']} eps iters {info['eps_iterations']}",
-          flush=True)
-    assert info["status"] == 0 and info["max_residual"] <= tol, info
-    X, lam = _np(X), _np(lam)
-    assert np.all(np.diff(lam) >= 0)
-    G = X.T @ (ex["b"][:, None] * X)
-    assert np.abs(G - np.eye(K)).max() <= 1e-10
-    _check_sampled_rows(g, h, ex["b"], rows, X, lam, tol)
-    # FP16 Chebyshev iterates at full size: the same bars
-    X16, lam16, info16 = me.embed(h, K, tol=tol, cheb_iterates="fp16", **BENCH_OPTS)
-    print(f"[gpu] sphere fp16 iterates: iters {info16['iterations']}", flush=True)
-    assert info16["status"] == 0 and info16["max_residual"] <= tol, info16
-    X16, lam16 = _np(X16), _np(lam16)
-    assert not np.array_equal(X16, X)
-    np.testing.assert_allclose(lam16, lam, rtol=1e-5)
-    G16 = X16.T @ (ex["b"][:, None] * X16)
-    assert np.abs(G16 - np.eye(K)).max() <= 1e-10
-    _check_sampled_rows(g, h, ex["b"], rows, X16, lam16, tol)
+    # the whole two-hop pattern, bit-exact
+    assert h.nnz_t == ref["nnz_t"]
+    assert _sha(ex["t_rowptr"], ex["t_col"]) == ref["t_sha256"]
+    assert hashlib.sha256(ex["t_count"].astype(np.int32).tobytes()).hexdigest() == \
+        ref["t_count_sha256"]
+    rows = np.asarray(ref["sample_rows"])
+    np.testing.assert_allclose(ex["d"][rows], ref["d"], rtol=1e-13)
+    np.testing.assert_allclose(ex["qdiag"][rows], ref["qdiag"], rtol=1e-13)
+    assert abs(ex["qdiag"].max() - ref["max_qdiag"]) <= 1e-13 * ref["max_qdiag"]
+    assert abs(h.eps - ref["eps"]) <= 1e-9 * ref["eps"], (h.eps, ref["eps"])
+    assert abs(h.mu - ref["mu"]) <= 1e-9 * ref["mu"], (h.mu, ref["mu"])
+    np.testing.assert_allclose(ex["r"][rows], ref["r"], rtol=2e-9)
+    np.testing.assert_allclose(ex["b"][rows], ref["b"], rtol=2e-9)
+    lam_ref = np.asarray(ref["lam"])
+    for it in ("fp32", "fp16"):
+        X, lam, info = me.embed(h, K, tol=tol, cheb_iterates=it, **BENCH_OPTS)
+        print(f"[gpu] sphere {it} iterates: iters {info['iterations']} eps iters "
+              f"{info['eps_iterations']}", flush=True)
+        assert info["status"] == 0 and info["max_residual"] <= tol, info
+        X, lam = _np(X), _np(lam)
+        assert np.max(np.abs(lam - lam_ref[:K]) / lam_ref[:K]) <= 1e-6, (lam, lam_ref[:K])
+        G = X.T @ (ex["b"][:, None] * X)
+        assert np.abs(G - np.eye(K)).max() <= 1e-10
+        # sampled rows of A X - B X Lambda with the oracle's operator and the
+        # stored eps and mu; bounded by the certified tol |lambda_j| |B x_j|
+        AX = oracle.operator_a_rows(g.n, g.rowptr, g.col, g.val, rows.tolist(), ref["mu"],
+                                    ref["eps"], X)
+        b_rows = np.asarray(ref["b"])
+        R = AX - b_rows[:, None] * X[rows] * lam[None, :]
+        bound = tol * np.abs(lam) * np.linalg.norm(ex["b"][:, None] * X, axis=0)
+        assert np.all(np.abs(R) <= bound[None, :] * 1.01), np.abs(R).max(axis=0) / bound
     h.close()
-
-
-def _check_sampled_rows(g, h, b, rows, X, lam, tol):
-    """Sampled rows of A X - B X Lambda (the oracle's row-wise operator),
-    bounded by the certified norm tol |lambda_j| |B x_j|."""
-    AX = oracle.operator_a_rows(g.n, g.rowptr, g.col, g.val, rows, h.mu, h.eps, X)
-    R = AX - b[rows, None] * X[rows] * lam[None, :]
-    bound = tol * np.abs(lam) * np.linalg.norm(b[:, None] * X, axis=0)
-    assert np.all(np.abs(R) <= bound[None, :] * 1.001), np.abs(R).max(axis=0) / bound

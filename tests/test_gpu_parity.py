@@ -143,15 +143,42 @@ def test_embed_matches_oracle(me, name, K):
 
 def test_embed_eps_zero_graph(me):
     """A bipartite grid: two-hop graph disconnected, eps = mu = 0, A = L;
-    lambda_1 = 0 with a constant vector."""
+    lambda_1 = 0 with a constant vector; the K-subspace matches the oracle's
+    at the tolerance its relative gap requires."""
     g, ops = oracle_ops("grid_bipartite")
     K = 4
     lam_o, V_o = oracle.generalized_eigs(ops["A"], ops["b"], K)
-    X, lam, info = me.embed(g, K, tol=1e-8, seed=2)
+    relgap = (lam_o[K] - lam_o[K - 1]) / lam_o[K - 1]
+    tol = min(1e-8, 1e-5 * relgap / 4)
+    X, lam, info = me.embed(g, K, tol=tol, seed=2)
     assert info["status_name"] == "ME_WARN_EPS_ZERO"
-    lam = _np(lam)
+    lam, X = _np(lam), _np(X)
     assert abs(lam[0]) < 1e-10
     np.testing.assert_allclose(lam[1:], lam_o[1:K], rtol=1e-6)
+    assert oracle.sin_principal_angle_b(X, V_o[:, :K], ops["b"]) <= 1e-5
+    assert oracle.b_orthonormality_error(X, ops["b"]) <= 1e-10
+    # the first column is the B-normalised constant vector
+    c = np.ones(g.n) / np.sqrt(ops["b"].sum())
+    assert np.max(np.abs(X[:, 0] - c)) <= 1e-6
+
+
+def test_plain_fp64_square_2000_tol_1e8(me):
+    """The plain-method configuration: N = 2000 uniform in the unit square,
+    symmetrised 8-NN, K = 4, FP64 throughout, tol 1e-8, seed 0."""
+    kind, n, knn, K, tol = sg.CONFIGS["square_2k"]
+    assert (kind, n, knn, K, tol) == ("square", 2000, 8, 4, 1e-8)
+    g, ops = oracle_ops("square_2k")
+    lam_o, V_o = oracle.generalized_eigs(ops["A"], ops["b"], K)
+    relgap = (lam_o[K] - lam_o[K - 1]) / lam_o[K - 1]
+    X, lam, info = me.embed(g, K, tol=tol, seed=0, precision="fp64")
+    assert info["status"] == 0 and info["max_residual"] <= tol, info
+    X, lam = _np(X), _np(lam)
+    assert np.max(np.abs(lam - lam_o[:K]) / lam_o[:K]) <= 1e-6
+    rho = oracle.relative_residuals(ops["A"], ops["b"], X, lam)
+    assert np.all(rho <= tol * 1.01), rho
+    assert tol / relgap <= 1e-5
+    assert oracle.sin_principal_angle_b(X, V_o[:, :K], ops["b"]) <= 1e-5
+    assert oracle.b_orthonormality_error(X, ops["b"]) <= 1e-10
 
 
 def test_embed_with_explicit_start_block_and_determinism(me):

@@ -114,3 +114,32 @@ def test_serve_failing_request_isolated(me):
     a4 = me.embed_batch([good], [4], tol=1e-8, seed=1)[0]
     a8 = me.embed_batch([good], [8], tol=1e-8, seed=1)[0]
     assert torch.equal(out[tickets[0]][0], a4[0]) and torch.equal(out[tickets[2]][0], a8[0])
+
+
+@pytest.mark.timeout(600)
+def test_serve_recipe_mix_with_large_requests_equals_alone(me):
+    """Requests drawn from the serving recipe (Poisson stream seed 7: N
+    log-uniform in [1000, 200000], square / Swiss roll / sphere, 10-NN, K = 8,
+    tol 1e-6), among them requests of more than 1e5 nodes, submitted while
+    others run: each result is bitwise the same graph solved alone (a batch
+    of one), and each eigenvalue matches the oracle to 1e-6 for the graphs it
+    can factor within the test (N <= 30000)."""
+    specs = sg.serve_arrivals(40)
+    big = [q for q, s in enumerate(specs) if s[2] >= 100_000][:2]
+    small = [q for q, s in enumerate(specs) if s[2] < 30_000][:5]
+    assert len(big) == 2
+    pick = sorted(big + small)
+    reqs = [(sg.manifold_graph(specs[q][1], specs[q][2], specs[q][3], specs[q][5]), specs[q][4])
+            for q in pick]
+    print(f"[gpu] serve recipe: N = {[g.n for g, _ in reqs]}", flush=True)
+    tickets, out, _ = _drive(me, reqs, 1e-6, seed=0, precision="mixed")
+    for (g, K), t, q in zip(reqs, tickets, pick):
+        X, lam, info = out[t]
+        assert info["status"] == 0 and info["max_residual"] <= 1e-6, (q, info)
+        Xa, la, ia = me.embed_batch([g], [K], tol=1e-6, seed=0, precision="mixed")[0]
+        assert ia["iterations"] == info["iterations"], q
+        assert torch.equal(X, Xa) and torch.equal(lam, la), q
+        if g.n <= 30_000:
+            ops = oracle.build_ops(g.n, g.rowptr, g.col, g.val)
+            lam_o, _ = oracle.generalized_eigs(ops["A"], ops["b"], K)
+            assert np.max(np.abs(lam.cpu().numpy() - lam_o[:K]) / lam_o[:K]) <= 1e-6, q

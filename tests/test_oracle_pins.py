@@ -370,3 +370,153 @@ def test_generators_are_symmetric_and_seeded():
         h = sg.manifold_graph(kind, 400, 10, 5)
         assert np.array_equal(g.col, h.col) and np.array_equal(g.val, h.val)
         assert g.degrees_count().min() >= 10
+
+
+# ---------------------------------------------------------------------------
+# Closed forms for periodic lattices (oracle.lattice): every operator of the
+# method from the Fourier modes alone, checked against the assembled sparse
+# operators and LAPACK on lattices small enough for both.  The two share no
+# code: one is trigonometric sums, the other sparse assembly + dense eig.
+# ---------------------------------------------------------------------------
+
+from oracle import lattice as LT  # noqa: E402
+
+LATTICES = [("cross", 7, 9), ("king", 9, 11), ("triangular", 8, 10), ("king", 10, 13),
+            ("triangular", 11, 7)]
+
+
+@pytest.mark.parametrize("stencil,n1,n2", LATTICES)
+def test_lattice_closed_form_matches_assembled_operators(stencil, n1, n2):
+    offs, w = sg.lattice_stencil(stencil)
+    g = sg.periodic_lattice(n1, n2, offs, w)
+    ops = ops_of(g)
+    cf = LT.lattice_spectrum(n1, n2, offs, w)
+    assert np.all(ops["t_count"] == cf["t"])
+    np.testing.assert_allclose(ops["d"], cf["d"], rtol=1e-15)
+    np.testing.assert_allclose(ops["Q"].diagonal(), cf["qdiag"], rtol=1e-15)
+    assert abs(ops["eps"] - cf["eps"]) <= 1e-12 * cf["eps"]
+    assert abs(ops["mu"] - cf["mu"]) <= 1e-12 * cf["mu"]
+    np.testing.assert_allclose(ops["r"], cf["r"], rtol=1e-14)
+    np.testing.assert_allclose(ops["b"], 1.0, atol=1e-14)
+    # the whole spectrum of A, and of L and Q
+    for key, M in (("lam_a", ops["A"]), ("lam_l", ops["L"]), ("lam_q", ops["Q"])):
+        dense = np.sort(np.linalg.eigvalsh(M.toarray()))
+        np.testing.assert_allclose(dense, np.sort(cf[key]), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("stencil,n1,n2", [("king", 9, 11), ("triangular", 8, 10)])
+def test_lattice_mode_basis_spans_the_eigenvectors(stencil, n1, n2):
+    """For every closed cluster of the smallest eigenvalues, the cos/sin
+    basis of the modes spans the oracle's generalized eigenvectors."""
+    offs, w = sg.lattice_stencil(stencil)
+    g = sg.periodic_lattice(n1, n2, offs, w)
+    cf = LT.lattice_spectrum(n1, n2, offs, w)
+    lam, modes = LT.smallest(cf, 20)
+    ends = [k for k in LT.cluster_ends(lam) if k <= 12]
+    assert ends
+    X, lam_o, info = oracle.embed(g.n, g.rowptr, g.col, g.val, max(ends))
+    np.testing.assert_allclose(lam_o, lam[:max(ends)], rtol=1e-11)
+    for k in ends:
+        Vb = LT.mode_basis(n1, n2, modes[:k])
+        assert Vb.shape[1] == k
+        assert oracle.sin_principal_angle_b(X[:, :k], Vb, info["b"]) < 1e-9
+
+
+def test_lattice_one_dimensional_is_the_ring_closed_form():
+    """n2 = 1 with offsets (+-s, 0), s = 1..k is the circulant ring C_n(1..k)."""
+    for n, k in [(17, 3), (40, 2), (101, 4)]:
+        offs = [(s, 0) for s in range(1, k + 1)] + [(-s, 0) for s in range(1, k + 1)]
+        cf = LT.lattice_spectrum(n, 1, offs, [1.0] * (2 * k))
+        eps, mu, lam_a = ring_closed_form(n, k)
+        assert abs(cf["eps"] - eps) <= 1e-13 * eps and abs(cf["mu"] - mu) <= 1e-13 * mu
+        np.testing.assert_allclose(np.sort(cf["lam_a"]), lam_a, rtol=0, atol=1e-12)
+        assert cf["t"] == 2 * k
+
+
+def test_lattice_bipartite_two_hop_graph_gives_eps_zero():
+    """The cross stencil on an even x even torus is bipartite: the two-hop
+    graph splits into two parity classes, lambda_2(Q) = 0 exactly (reading
+    R4), and the closed form says so without rounding."""
+    offs, w = sg.lattice_stencil("cross")
+    cf = LT.lattice_spectrum(8, 10, offs, w)
+    assert cf["eps"] == 0.0 and cf["mu"] == 0.0
+    g = sg.periodic_lattice(8, 10, offs, w)
+    assert ops_of(g)["eps"] == 0.0
+
+
+def test_lattice_rejects_wraparound():
+    offs, w = sg.lattice_stencil("king")
+    with pytest.raises(ValueError):
+        LT.lattice_spectrum(4, 9, offs, w)
+
+
+def test_lattice_headline_size_clusters():
+    """The 1250 x 800 king lattice used for the million-node GPU test: the 15
+    smallest eigenvalues close a cluster with a relative gap near 0.3, and
+    the closed form's eigenvalues are the min-max values (each is a Rayleigh
+    quotient of its own mode vector, A applied row-wise by the oracle)."""
+    offs, w = sg.lattice_stencil("king")
+    cf = LT.lattice_spectrum(1250, 800, offs, w)
+    lam, modes = LT.smallest(cf, 17)
+    assert 15 in LT.cluster_ends(lam)
+    assert (lam[15] - lam[14]) / lam[14] > 0.25
+    g = sg.periodic_lattice(1250, 800, offs, w)
+    V = LT.mode_basis(1250, 800, modes[:3])
+    rows = [0, 1, 799, 800, 123456, 999999]
+    AV = oracle.operator_a_rows(g.n, g.rowptr, g.col, g.val, rows, cf["mu"], cf["eps"], V)
+    for j in range(3):
+        np.testing.assert_allclose(AV[:, j], lam[1] * V[rows, j] if j else lam[0] * V[rows, j],
+                                   rtol=1e-9, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# relative_residuals: values worked out by hand for vectors that are NOT
+# eigenvectors, so that a wrong denominator (|x| for |Bx|, a dropped |lambda|,
+# lambda with its sign, |B^1/2 x|) fails.
+# ---------------------------------------------------------------------------
+
+def test_relative_residuals_hand_values():
+    import scipy.sparse as sp_
+    A = sp_.csr_matrix(np.array([[2.0, -1.0], [-1.0, 2.0]]))
+    b = np.array([1.0, 2.0])
+    # x = (0, 1), lambda = 3: A x - 3 B x = (-1, 2) - (0, 6) = (-1, -4),
+    # |.| = sqrt(17); |lambda| |B x| = 3 * 2 = 6
+    # x = (1, 1), lambda = -1: A x + B x = (1, 1) + (1, 2) = (2, 3), |.| = sqrt(13);
+    # |lambda| |B x| = 1 * sqrt(5)
+    X = np.array([[0.0, 1.0], [1.0, 1.0]])
+    rho = oracle.relative_residuals(A, b, X, np.array([3.0, -1.0]))
+    np.testing.assert_allclose(rho, [math.sqrt(17) / 6, math.sqrt(13) / math.sqrt(5)],
+                               rtol=1e-15)
+
+
+def test_relative_residuals_line5_hand_value():
+    """Line of 5 (Fig. 2a): eps = mu = 0, so A = L; b = (1,2,2,2,1) / 8^(1/5).
+    x = e_0, lambda = 1: A x - B x = (1 - b_0, -1, 0, 0, 0),
+    rho = sqrt((1 - b_0)^2 + 1) / b_0."""
+    g = sg.line(5)
+    ops = ops_of(g)
+    b0 = 8 ** -0.2
+    x = np.zeros((5, 1))
+    x[0, 0] = 1.0
+    rho = oracle.relative_residuals(ops["A"], ops["b"], x, np.array([1.0]))
+    assert abs(rho[0] - math.sqrt((1 - b0) ** 2 + 1) / b0) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# The products-only ARPACK route (used where an LU does not fit) against the
+# shift-invert route and dense LAPACK.
+# ---------------------------------------------------------------------------
+
+def test_smallest_route_matches_shift_invert_and_dense():
+    g = sg.manifold_graph("sphere", 1500, 12, 3)
+    ops = ops_of(g)  # eps by dense eigvalsh at this size
+    eps_s = oracle.fiedler_value(ops["Q"], dense_max=0, method="smallest")
+    assert abs(eps_s - ops["eps"]) <= 1e-10 * ops["eps"]
+    eps_i = oracle.fiedler_value(ops["Q"], dense_max=0)
+    assert abs(eps_i - ops["eps"]) <= 1e-10 * ops["eps"]
+    l1, V1 = oracle.sparse_generalized_eigs(ops["A"], ops["b"], 8, method="smallest")
+    l2, V2 = oracle.sparse_generalized_eigs(ops["A"], ops["b"], 8)
+    l3, V3 = oracle.dense_generalized_eigs(ops["A"], ops["b"], 8)
+    np.testing.assert_allclose(l1, l3, rtol=1e-10)
+    np.testing.assert_allclose(l2, l3, rtol=1e-10)
+    assert oracle.sin_principal_angle_b(V1[:, :8], V3[:, :8], ops["b"]) < 1e-7
