@@ -7,13 +7,18 @@ eps = lambda_2(Q) (its own LOBPCG), mu, b, and the LOBPCG solve of (A, B) to
 relative residual <= tol, certified in FP64.  The input CSR is resident in
 HBM before the timed region starts.
 
-Default workload: N = 100,000 points uniform on a Swiss roll
-(t ~ U[1.5 pi, 4.5 pi], h ~ U[0, 20]), symmetrised 10-NN graph with Gaussian
-weights, sigma = median 10-NN distance, K = 8, tol = 1e-6, seed 0.
+Default workload: N = 1,000,000 points uniform on the unit 2-sphere plus
+isotropic noise of standard deviation 1e-3, symmetrised 12-NN graph with
+Gaussian weights, sigma = median 12-NN distance, K = 16, tol = 1e-6, seed 0,
+mixed precision.
 
-Prints one JSON line (rank 0): metric, value (nodes/s), latency, roofline of
-the timed kernel (HIP events on its stream, algorithmic bytes), and the CPU
-oracle's throughput on a bounded sample of the same workload family.
+Prints one JSON line (rank 0): metric, value (nodes/s of the 1M sphere),
+latency, roofline of the timed kernel (HIP events on its stream, algorithmic
+bytes), and, as extra keys, the batched mix (512 graphs, one batched call,
+beside the plain FP64 single-graph path), the serving stream at several
+offered Poisson rates (p50/p99 latency below saturation and the saturation
+throughput), and the CPU oracle's throughput on a bounded sample of the same
+workload family.
 """
 from __future__ import annotations
 
@@ -31,6 +36,7 @@ if ROOT not in sys.path:
 
 METRIC = "graph nodes embedded/sec at rel. residual ≤1e-6; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
+SERVE_BASE_RATE = 200.0  # Poisson arrivals per second of the serving recipe
 KERNELS = {"spmm": 1, "gram": 2, "combine": 3, "cheb": 4}
 KERNEL_NAMES = {"spmm": "k_spmm (difference-form SpMM of A on the LOBPCG block)",
                 "gram": "k_gram (Rayleigh-Ritz Gram S^T B S, S^T A S on MFMA)",
@@ -125,103 +131,98 @@ def _gen(spec):
     return sg.manifold_graph(kind, n, k, seed)
 
 
-def generate_batch(count: int, workers: int = 16):
-    """The batched mix (seeds 1000 + g), generated on host worker processes
-    before the GPU is touched."""
-    import synthgraphs as sg
-    from concurrent.futures import ProcessPoolExecutor
-    specs = sg.batch_specs(count=count)
-    with ProcessPoolExecutor(max_workers=min(workers, os.cpu_count() or 1)) as ex:
-        graphs = list(ex.map(_gen, specs, chunksize=4))
-    return specs, graphs
-
-
-def bench_batch(args) -> int:
-    """Batched mix: `count` graphs (N log-uniform in [500, 20000], square /
-    Swiss roll / torus, 8-NN, K in {4, 8, 16}) embedded by one batched call
-    per step; beside it, the plain FP64 single-graph path on every 8th graph."""
-    count = args.batch_count
-    print(f"[bench] generating batch of {count}", file=sys.stderr, flush=True)
-    specs, graphs = generate_batch(count)
-    import torch
-    import paper_2112_07862_amd as me
-    Ks = [s[3] for s in specs]
-    dev = [me.to_device(g) for g in graphs]
-    torch.cuda.synchronize()
-    total_n = sum(g.n for g in graphs)
-    opts = dict(precision=args.precision, seed=0, cheb_degree=args.cheb_degree)
-    tol = 1e-6
-    for w in range(args.warmup):
-        t = time.perf_counter()
-        me.embed_batch(dev, Ks, tol=tol, **opts)
-        print(f"[bench] warmup {w}: {time.perf_counter() - t:.2f} s", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    lat, bad = [], 0
-    t0 = time.perf_counter()
-    for s_ in range(args.steps):
-        ts = time.perf_counter()
-        res = me.embed_batch(dev, Ks, tol=tol, **opts)
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - ts)
-        bad = sum(1 for _, _, i in res if i["status"] not in (0, 2) or i["max_residual"] > tol)
-        its = [i["iterations"] for _, _, i in res]
-        print(f"[bench] step {s_}: {lat[-1]:.2f} s, not converged {bad}, iterations "
-              f"median {int(np.median(its))} max {max(its)}", file=sys.stderr, flush=True)
-    elapsed = time.perf_counter() - t0
-    value = total_n * args.steps / elapsed if bad == 0 else 0.0
-    # plain FP64 single-graph solves on a sample of the same graphs
-    sample = list(range(0, count, 8))
-    ts = time.perf_counter()
-    sn = 0
-    for q in sample:
-        X, lam, info = me.embed(dev[q], Ks[q], tol=tol, precision="fp64", seed=0,
-                                cheb_degree=args.cheb_degree)
-        sn += graphs[q].n
-    torch.cuda.synchronize()
-    single = sn / (time.perf_counter() - ts)
-    out = {
-        "metric": METRIC, "value": value, "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
-        "config": {"workload": f"batch_{count}", "graphs": count, "total_nodes": total_n,
-                   "n_range": [500, 20000], "knn": 8, "K": [4, 8, 16], "tol": tol,
-                   "precision": args.precision, "cheb_degree": args.cheb_degree},
-        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
-                       "p99": float(np.percentile(lat, 99) * 1e3)},
-        "single_graph_fp64": {"nodes_per_s": single, "graphs": len(sample),
-                              "note": "me.embed one graph at a time, FP64, every 8th graph"},
-    }
-    print(json.dumps(out), flush=True)
-    return 0
-
-
 def _gen_serve(spec):
     import synthgraphs as sg
     t, kind, n, k, K, seed = spec
     return sg.manifold_graph(kind, n, k, seed)
 
 
-def bench_serve(args) -> int:
-    """Serving mix: Poisson arrivals (200 graphs/s), N log-uniform in
-    [1000, 200000] on square / Swiss roll / sphere, 10-NN, K = 8, tol 1e-6,
-    driven through the continuous-batching server against the wall clock."""
+def _gen_main(spec):
+    import synthgraphs as sg
+    kind, n, knn = spec
+    return sg.manifold_graph(kind, n, knn, 0)
+
+
+def generate(main_spec, batch_count: int, serve_count: int, workers: int = 16):
+    """Every input graph of the run (the main workload, the batched mix with
+    seeds 1000 + g, the serving stream with seed 7), generated on host worker
+    processes before the GPU is touched."""
     import synthgraphs as sg
     from concurrent.futures import ProcessPoolExecutor
-    count = args.serve_count
-    specs = sg.serve_arrivals(count, rate=args.serve_rate)
-    print(f"[bench] generating {count} requests", file=sys.stderr, flush=True)
-    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
-        graphs = list(ex.map(_gen_serve, specs, chunksize=2))
+    bspecs = sg.batch_specs(count=batch_count) if batch_count else []
+    sspecs = sg.serve_arrivals(serve_count, rate=SERVE_BASE_RATE) if serve_count else []
+    with ProcessPoolExecutor(max_workers=min(workers, os.cpu_count() or 1)) as ex:
+        fmain = ex.submit(_gen_main, main_spec) if main_spec else None
+        bgraphs = list(ex.map(_gen, bspecs, chunksize=4))
+        sgraphs = list(ex.map(_gen_serve, sspecs, chunksize=2))
+        gmain = fmain.result() if fmain else None
+    return gmain, (bspecs, bgraphs), (sspecs, sgraphs)
+
+
+def batch_leg(me, specs, graphs, precision: str, cheb_degree: int, steps: int,
+              warmup: int) -> dict:
+    """Batched mix: every graph embedded by one batched call per step
+    (mixed precision); beside it the plain FP64 single-graph path (one me.embed
+    per graph, FP64) on every 8th graph of the same mix."""
     import torch
-    import paper_2112_07862_amd as me
+    Ks = [s[3] for s in specs]
     dev = [me.to_device(g) for g in graphs]
     torch.cuda.synchronize()
+    total_n = sum(g.n for g in graphs)
+    opts = dict(precision=precision, seed=0, cheb_degree=cheb_degree)
     tol = 1e-6
-    opts = dict(precision=args.precision, seed=0, cheb_degree=args.cheb_degree)
-    srv = me.Server(**opts)
-    # warm-up: two requests through the server
-    for q in range(2):
+    for w in range(warmup):
+        t = time.perf_counter()
+        me.embed_batch(dev, Ks, tol=tol, **opts)
+        print(f"[bench] batch warmup {w}: {time.perf_counter() - t:.2f} s", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    lat, bad = [], 0
+    t0 = time.perf_counter()
+    for s_ in range(steps):
+        ts = time.perf_counter()
+        res = me.embed_batch(dev, Ks, tol=tol, **opts)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        bad += sum(1 for _, _, i in res if i["status"] not in (0, 2) or i["max_residual"] > tol)
+        its = [i["iterations"] for _, _, i in res]
+        print(f"[bench] batch step {s_}: {lat[-1]:.2f} s, not converged {bad}, iterations "
+              f"median {int(np.median(its))} max {max(its)}", file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    value = total_n * steps / elapsed if bad == 0 else 0.0
+    sample = list(range(0, len(graphs), 8))
+    ts = time.perf_counter()
+    sn, sbad = 0, 0
+    for q in sample:
+        X, lam, info = me.embed(dev[q], Ks[q], tol=tol, precision="fp64", seed=0,
+                                cheb_degree=cheb_degree)
+        sn += graphs[q].n
+        sbad += info["status"] not in (0, 2) or info["max_residual"] > tol
+    torch.cuda.synchronize()
+    single = sn / (time.perf_counter() - ts) if sbad == 0 else 0.0
+    print(f"[bench] batch {value:.0f} nodes/s, FP64 one graph at a time {single:.0f} nodes/s",
+          file=sys.stderr, flush=True)
+    return {
+        "workload": f"batch_{len(graphs)}", "graphs": len(graphs), "total_nodes": total_n,
+        "n_range": [500, 20000], "manifolds": ["square", "swiss_roll", "torus"], "knn": 8,
+        "K": [4, 8, 16], "tol": tol, "precision": precision, "steps": steps,
+        "nodes_per_s": value, "s_per_batch": elapsed / max(steps, 1), "failed": bad,
+        "single_graph_fp64": {"nodes_per_s": single, "graphs": len(sample),
+                              "note": "me.embed one graph at a time, FP64, every 8th graph "
+                                      "of the same mix"},
+        "speedup_vs_single_fp64": value / single if single > 0 else None,
+    }
+
+
+def serve_run(me, specs, dev, ns, rate: float, precision: str, cheb_degree: int) -> dict:
+    """Drives the continuous-batching server with the stream's requests at
+    Poisson rate `rate` (the stream's arrival gaps rescaled) against the wall
+    clock; latency = completion - arrival."""
+    times = [s[0] * SERVE_BASE_RATE / rate for s in specs]
+    count = len(specs)
+    tol = 1e-6
+    srv = me.Server(precision=precision, seed=0, cheb_degree=cheb_degree)
+    for q in range(2):  # warm-up: two requests through the server
         srv.submit(dev[q], 8, tol)
     while srv.step() > 0:
         pass
@@ -232,12 +233,12 @@ def bench_serve(args) -> int:
     t_last = t0
     while done < count:
         now = time.perf_counter() - t0
-        while nxt < count and specs[nxt][0] <= now:
+        while nxt < count and times[nxt] <= now:
             t = srv.submit(dev[nxt], specs[nxt][4], tol)
-            arrive[t] = (specs[nxt][0], graphs[nxt].n)
+            arrive[t] = (times[nxt], ns[nxt])
             nxt += 1
         if done == nxt and nxt < count:  # idle until the next arrival
-            time.sleep(max(0.0, specs[nxt][0] - (time.perf_counter() - t0)))
+            time.sleep(max(0.0, times[nxt] - (time.perf_counter() - t0)))
             continue
         srv.step()
         steps += 1
@@ -251,26 +252,89 @@ def bench_serve(args) -> int:
             if info["status"] not in (0, 2) or info["max_residual"] > tol:
                 bad += 1
             t_last = tf
-        if fin:
-            print(f"[bench] t={tf - t0:.2f}s done {done}/{count} submitted {nxt}",
-                  file=sys.stderr, flush=True)
     srv.close()
     span = t_last - t0
-    offered = sum(g.n for g in graphs) / max(specs[-1][0], 1e-9)
-    out = {
-        "metric": METRIC, "value": nodes / span if bad == 0 else 0.0, "unit": "nodes/s",
-        "n_gpus": 1, "steps": steps, "warmup": 2, "ms_per_step": span * 1e3 / max(steps, 1),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
-        "config": {"workload": f"serve_{count}", "requests": count, "rate_per_s": args.serve_rate,
-                   "n_range": [1000, 200000], "knn": 10, "K": 8, "tol": tol,
-                   "precision": args.precision, "cheb_degree": args.cheb_degree},
-        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
-                       "p99": float(np.percentile(lat, 99) * 1e3)},
-        "offered_nodes_per_s": offered, "span_s": span, "failed": bad,
+    offered = sum(ns) / max(times[-1], 1e-9)
+    out = {"rate_per_s": rate, "offered_nodes_per_s": offered,
+           "nodes_per_s": nodes / span if bad == 0 else 0.0,
+           "p50_ms": float(np.percentile(lat, 50) * 1e3),
+           "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "span_s": span, "rounds": steps, "failed": bad}
+    print(f"[bench] serve rate {rate:g}/s: offered {offered:.3g} nodes/s, served "
+          f"{out['nodes_per_s']:.3g} nodes/s, p50 {out['p50_ms']:.0f} ms, p99 "
+          f"{out['p99_ms']:.0f} ms", file=sys.stderr, flush=True)
+    return out
+
+
+def serve_leg(me, specs, graphs, rates, precision: str, cheb_degree: int) -> dict:
+    """Serving: the same request stream (N log-uniform in [1000, 200000] on
+    square / Swiss roll / sphere, 10-NN, K = 8, tol 1e-6) offered at several
+    Poisson rates.  The recipe's 200/s overloads one GPU; the lower rates give
+    the latency below saturation.  The saturation point is the throughput
+    sustained under overload."""
+    import torch
+    dev = [me.to_device(g) for g in graphs]
+    torch.cuda.synchronize()
+    ns = [g.n for g in graphs]
+    runs = [serve_run(me, specs, dev, ns, r, precision, cheb_degree) for r in rates]
+    top = max(runs, key=lambda r: r["rate_per_s"])
+    mean_n = float(np.mean(ns))
+    sat = top["nodes_per_s"]
+    below = [r for r in runs if r["offered_nodes_per_s"] < 0.9 * sat]
+    return {
+        "workload": f"serve_{len(graphs)}", "requests": len(graphs),
+        "n_range": [1000, 200000], "manifolds": ["square", "swiss_roll", "sphere"], "knn": 10,
+        "K": 8, "tol": 1e-6, "precision": precision, "mean_n": mean_n, "runs": runs,
+        "saturation": {"nodes_per_s": sat, "requests_per_s": sat / mean_n,
+                       "note": f"throughput sustained at the highest offered rate "
+                               f"({top['rate_per_s']:g}/s, "
+                               f"{top['offered_nodes_per_s']:.3g} nodes/s offered)"},
+        "below_saturation": [{"rate_per_s": r["rate_per_s"],
+                              "load": r["offered_nodes_per_s"] / sat if sat > 0 else None,
+                              "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"]} for r in below],
     }
+
+
+def envelope(args, value, ms_per_step, steps, warmup, dtype, config) -> dict:
+    return {"metric": METRIC, "value": value, "unit": "nodes/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": config}
+
+
+def bench_batch(args) -> int:
+    """A line for the batched mix alone (--workload batch)."""
+    print(f"[bench] generating batch of {args.batch_count}", file=sys.stderr, flush=True)
+    _, (specs, graphs), _ = generate(None, args.batch_count, 0)
+    import paper_2112_07862_amd as me
+    b = batch_leg(me, specs, graphs, args.precision, args.cheb_degree, args.steps, args.warmup)
+    out = envelope(args, b["nodes_per_s"], b["s_per_batch"] * 1e3, args.steps, args.warmup,
+                   "f64" if args.precision == "fp64" else "f32+f64",
+                   {k: b[k] for k in ("workload", "graphs", "total_nodes", "n_range", "knn",
+                                      "K", "tol", "precision")})
+    out["batch"] = b
     print(json.dumps(out), flush=True)
     return 0
+
+
+def bench_serve(args) -> int:
+    """A line for the serving stream alone (--workload serve)."""
+    print(f"[bench] generating {args.serve_count} requests", file=sys.stderr, flush=True)
+    _, _, (specs, graphs) = generate(None, 0, args.serve_count)
+    import paper_2112_07862_amd as me
+    sv = serve_leg(me, specs, graphs, args.serve_rates, args.precision, args.cheb_degree)
+    top = max(sv["runs"], key=lambda r: r["rate_per_s"])
+    out = envelope(args, sv["saturation"]["nodes_per_s"], top["span_s"] * 1e3 / top["rounds"],
+                   top["rounds"], 2, "f64" if args.precision == "fp64" else "f32+f64",
+                   {k: sv[k] for k in ("workload", "requests", "n_range", "knn", "K", "tol",
+                                       "precision")})
+    out["latency_ms"] = {"p50": top["p50_ms"], "p99": top["p99_ms"]}
+    out["serving"] = sv
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+CPU_SAMPLE_N = {"sphere_1m": 50_000, "swiss_roll_100k": 100_000, "square_2k": 2000}
 
 
 def main() -> int:
@@ -278,18 +342,24 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="swiss_roll_100k")
+    ap.add_argument("--workload", default="sphere_1m",
+                    help="sphere_1m (default), swiss_roll_100k, square_2k, batch or serve")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--time-kernel", default="cheb", choices=list(KERNELS))
     ap.add_argument("--cheb-degree", type=int, default=128)
     ap.add_argument("--cheb-iterates", default="fp32", choices=["fp32", "fp16"],
                     help="storage of the Chebyshev iterates (mixed precision)")
     ap.add_argument("--eps-tol", type=float, default=None)
-    ap.add_argument("--cpu-sample-n", type=int, default=100_000)
+    ap.add_argument("--cpu-sample-n", type=int, default=None,
+                    help="nodes of the CPU oracle's sample graph (default per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-mix and serving legs of the default line")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--serve-count", type=int, default=120)
-    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[10.0, 25.0, 40.0, 200.0],
+                    help="Poisson arrival rates (requests/s) the serving stream is offered at")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device-to-device copies of MIB MiB (the known-size "
                          "reference for the HBM byte counters) and exit")
@@ -306,8 +376,8 @@ def main() -> int:
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
-    import torch
     if args.copy_calibration:
+        import torch
         nbytes = args.copy_calibration << 20
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
         b = torch.empty_like(a)
@@ -317,13 +387,17 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}), flush=True)
         return 0
-    import paper_2112_07862_amd as me
     import synthgraphs as sg
 
     kind, n, knn, K, tol = sg.CONFIGS[args.workload]
-    print(f"[bench] generating {args.workload}: {kind} N={n} {knn}-NN K={K} tol={tol}",
-          file=sys.stderr, flush=True)
-    g = sg.manifold_graph(kind, n, knn, 0)
+    extras = not args.no_extras
+    print(f"[bench] generating {args.workload}: {kind} N={n} {knn}-NN K={K} tol={tol}"
+          + (f"; batch of {args.batch_count}; {args.serve_count} serving requests"
+             if extras else ""), file=sys.stderr, flush=True)
+    g, (bspecs, bgraphs), (sspecs, sgraphs) = generate(
+        (kind, n, knn), args.batch_count if extras else 0, args.serve_count if extras else 0)
+    import torch
+    import paper_2112_07862_amd as me
     dcsr = me.to_device(g)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -363,25 +437,17 @@ def main() -> int:
     value = n * args.steps / elapsed if ok else 0.0
     avg_ms = kt["total_ms"] / max(kt["launches"], 1)
     achieved = (kt["bytes"] / max(kt["launches"], 1)) / (avg_ms * 1e-3) / 1e9 if kt["launches"] else 0.0
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "nodes/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "manifold": kind, "n": n, "knn": knn, "K": K,
-                   "tol": tol, "precision": args.precision, "preconditioner": "chebyshev",
-                   "cheb_degree": args.cheb_degree, "cheb_iterates": args.cheb_iterates,
-                   "seed": 0},
+    out = envelope(args, value, elapsed * 1e3 / args.steps, args.steps, args.warmup,
+                   "f64" if args.precision == "fp64" else "f32+f64",
+                   {"workload": args.workload, "manifold": kind, "n": n, "knn": knn, "K": K,
+                    "tol": tol, "precision": args.precision, "preconditioner": "chebyshev",
+                    "cheb_degree": args.cheb_degree, "cheb_iterates": args.cheb_iterates,
+                    "seed": 0})
+    out.update({
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
-                       "p99": float(np.percentile(lat, 99) * 1e3)},
+                       "p99": float(np.percentile(lat, 99) * 1e3),
+                       "note": "one graph's solve, repeated; serving latencies are under "
+                               "'serving'"},
         "iterations": int(np.median([i["iterations"] for i in infos])),
         "eps_iterations": int(np.median([i["eps_iterations"] for i in infos])),
         "max_residual": max(i["max_residual"] for i in infos),
@@ -400,7 +466,7 @@ def main() -> int:
             "avg_us": avg_ms * 1e3,
             "bytes_per_launch": kt["bytes"] / max(kt["launches"], 1),
         },
-    }
+    })
     # context for the roofline, outside the timed region: a plain device copy
     # moving the same bytes as one launch (and a large one), and the other
     # row-streaming kernels of the solve measured the same way
@@ -425,9 +491,18 @@ def main() -> int:
                              "launches": k2["launches"],
                              "bytes_per_launch": k2["bytes"] / k2["launches"]}
     out["other_kernels"] = others
+    del dcsr
+    if extras:
+        print("[bench] batched mix ...", file=sys.stderr, flush=True)
+        out["batch"] = batch_leg(me, bspecs, bgraphs, "mixed", args.cheb_degree,
+                                 args.batch_steps, 1)
+        print("[bench] serving ...", file=sys.stderr, flush=True)
+        out["serving"] = serve_leg(me, sspecs, sgraphs, args.serve_rates, "mixed",
+                                   args.cheb_degree)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(kind, args.cpu_sample_n, knn, K, 0)
+        cn = args.cpu_sample_n or CPU_SAMPLE_N.get(args.workload, 50_000)
+        out["cpu_baseline"] = cpu_baseline(kind, min(cn, n), knn, K, 0)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -204,8 +204,14 @@ def _oracle_of_spec(spec):
     kind, n, k, K, seed = spec
     g = sg.manifold_graph(kind, n, k, seed)
     ops = oracle.build_ops(g.n, g.rowptr, g.col, g.val)
-    lam, V = oracle.generalized_eigs(ops["A"], ops["b"], K)
+    lam, V = oracle.generalized_eigs(ops["A"], ops["b"], K, dense_max=1500)
     return ops["eps"], ops["b"], lam, V[:, :K]
+
+
+def _one_blas_thread():
+    # the pool's processes share the host's cores: one BLAS thread each
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
 
 
 @pytest.mark.timeout(900)
@@ -219,7 +225,8 @@ def test_batch_full_recipe_512(me):
     from concurrent.futures import ProcessPoolExecutor
     specs = sg.batch_specs(count=512)
     workers = min(16, os.cpu_count() or 1)
-    with ProcessPoolExecutor(max_workers=workers) as ex:
+    print("[gpu] batch recipe: generating 512 graphs and 32 oracle solves", flush=True)
+    with ProcessPoolExecutor(max_workers=workers, initializer=_one_blas_thread) as ex:
         graphs = list(ex.map(_gen, specs, chunksize=8))
         sample = list(range(0, 512, 16))
         ref = dict(zip(sample, ex.map(_oracle_of_spec, [specs[q] for q in sample])))
