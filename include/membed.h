@@ -22,6 +22,12 @@
  *     (outputs untouched).  No entry point prints or aborts.
  *   - Dense N x K blocks are row-major (row i holds node i's K coordinates).
  *   - Threading: a handle may be used by one host thread at a time.
+ *   - Device memory: every entry point that computes takes a caller-owned
+ *     workspace (device memory, e.g. a uint8 tensor) with a query of its
+ *     size; given one, the call carves every device array it needs from it
+ *     and makes no device allocation (no hipMalloc, no pinned host memory).
+ *     Passing NULL instead lets the library allocate stream-ordered device
+ *     memory itself.  me_apply (a diagnostic hook) always allocates.
  */
 #ifndef MEMBED_H
 #define MEMBED_H
@@ -141,6 +147,20 @@ void me_opts_default(me_opts* opts);
 /* Text of a status code (static storage). */
 const char* me_status_string(int status);
 
+/* Upper bound of the device workspace me_build_graph_ops needs for W
+ * (Sections 3.1, 4.1.1, 4.2): W's copy and per-node arrays, the two-hop
+ * pattern T and the packed operator, the locality order's scratch and the
+ * eps = lambda_2(Q) solve.  nnz(T) is only known after the build, so T is
+ * sized by the bound W's degrees give: T_i lies in the union of the
+ * neighbourhoods of i's neighbours, so nnz(T) <= sum_k d_k (d_k - 1).
+ *   W      host struct of device pointers (see me_csr); only its row
+ *          pointers are read (copied to the host).
+ *   opts   host, may be NULL.
+ *   bytes  host output.
+ * Errors: ME_ERR_INVALID_ARG (null arguments, row pointers not starting at 0,
+ * not ending at nnz or decreasing).  Synchronises `stream`. */
+int me_build_workspace_bytes(const me_csr* W, const me_opts* opts, void* stream, size_t* bytes);
+
 /* Validates W and builds every operator of the generalized problem
  * (Sections 3.1, 4.1.1, 4.2, 4.3): degrees, the two-hop pattern T with
  * counts T_i, Q (with the (i,i) entry of Theta_i equal to 1 so that Q is the
@@ -148,14 +168,21 @@ const char* me_status_string(int status);
  * eps = lambda_2(Q) by LOBPCG on Q with the constant vector deflated (exactly
  * 0 when the two-hop graph is disconnected: ME_WARN_EPS_ZERO), mu, b and the
  * packed difference-form operator A.
- *   W      host struct holding device pointers (see me_csr).
- *   opts   host, may be NULL (defaults).
- *   out    host; receives a new handle on success (ME_OK or a warning).
- *   info   host, may be NULL; receives eps, mu, eps_iterations, ms_build.
- * The handle owns device memory allocated by the library; release it with
- * me_graph_ops_destroy.  The call synchronises `stream`. */
-int me_build_graph_ops(const me_csr* W, const me_opts* opts, void* stream,
-                       me_graph_ops** out, me_info* info);
+ *   W         host struct holding device pointers (see me_csr); read only
+ *             during the call (the handle keeps a copy of W).
+ *   opts      host, may be NULL (defaults).
+ *   ws        device workspace of at least me_build_workspace_bytes bytes, or
+ *             NULL.  Given one, the handle's arrays live in it (it must
+ *             outlive the handle, and me_graph_ops_destroy frees only the
+ *             host part) and the call allocates no device memory; NULL: the
+ *             handle owns device memory the library allocates.
+ *   ws_bytes  size of ws.
+ *   out       host; receives a new handle on success (ME_OK or a warning).
+ *   info      host, may be NULL; receives eps, mu, eps_iterations, ms_build.
+ * Errors: the validation codes above, ME_ERR_WORKSPACE (ws smaller than the
+ * query).  The call synchronises `stream`. */
+int me_build_graph_ops(const me_csr* W, const me_opts* opts, void* ws, size_t ws_bytes,
+                       void* stream, me_graph_ops** out, me_info* info);
 
 /* Scalars of a built handle (host outputs, any may be NULL). */
 int me_graph_ops_query(const me_graph_ops* ops, int64_t* n, int64_t* nnz_T,
@@ -189,7 +216,8 @@ int me_graph_ops_order(const me_graph_ops* ops, int32_t* perm, void* stream);
 int me_apply(const me_graph_ops* ops, int which, int k, const double* X, double* Y,
              void* stream);
 
-/* Device workspace needed by me_embed for this graph and K. */
+/* Device workspace me_embed needs for this graph and K: the solver's blocks,
+ * its tables and work lists (0 for a null handle or K outside 1..16). */
 size_t me_embed_workspace_bytes(const me_graph_ops* ops, int K, const me_opts* opts);
 
 /* The first K generalized eigenpairs of (A, B) (Section 4.3) by LOBPCG until
@@ -205,6 +233,7 @@ size_t me_embed_workspace_bytes(const me_graph_ops* ops, int K, const me_opts* o
  *            library's seeded counter-based generator (opts->seed).
  *   ws       device workspace of at least me_embed_workspace_bytes bytes, or
  *            NULL to let the library allocate (and free) it on `stream`.
+ *            Given one, the call makes no allocation of any kind.
  *   X        device n x K float64 output, row-major, X^T B X = I, columns in
  *            ascending lambda order, each column's largest-magnitude entry
  *            positive (lowest row on ties).
@@ -214,6 +243,14 @@ size_t me_embed_workspace_bytes(const me_graph_ops* ops, int K, const me_opts* o
 int me_embed(const me_graph_ops* ops, int K, double tol, const me_opts* opts,
              const double* X0, void* ws, size_t ws_bytes, double* X, double* lambda,
              me_info* info, void* stream);
+
+/* Upper bound of the device workspace me_embed_batch needs for these
+ * graphs: the sum over graphs of the build (as me_build_workspace_bytes)
+ * and of the solver state of both solves, plus the batch's tables and work
+ * lists.  Reads every graph's row pointers (copied to the host).
+ * Synchronises `stream`. */
+int me_embed_batch_workspace_bytes(int G, const me_csr* Ws, const int* Ks, const me_opts* opts,
+                                   void* stream, size_t* bytes);
 
 /* Embeds G independent graphs in one solve (the method of Section 4 applied
  * to each graph; a batch is a way to run many of them at once, not a change
@@ -227,22 +264,33 @@ int me_embed(const me_graph_ops* ops, int K, double tol, const me_opts* opts,
  *   Ks       host int[G], 1..16 each (with the block rule of me_embed).
  *   tol      > 0, the rho target of every graph.
  *   opts     host, may be NULL.
+ *   ws       device workspace of at least me_embed_batch_workspace_bytes
+ *            bytes (no device allocation is made), or NULL (the library
+ *            allocates on `stream` and frees before returning).
+ *   ws_bytes size of ws.
  *   Xs       host array of G device pointers, graph g's n_g x K_g output.
  *   lambdas  host array of G device pointers, K_g values each.
  *   infos    host me_info[G], may be NULL; per-graph status and report
  *            (ms_build: time until that graph's operators were ready,
  *            ms_solve: the embedding phase of the whole batch).
- * Returns the first negative per-graph status if any graph failed (the other
- * graphs' outputs are still valid, see infos), else the largest warning, else
- * ME_OK.  Synchronises `stream`. */
+ * Returns ME_ERR_WORKSPACE if ws is smaller than the query, else the first
+ * negative per-graph status if any graph failed (the other graphs' outputs
+ * are still valid, see infos), else the largest warning, else ME_OK.
+ * Synchronises `stream`. */
 int me_embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opts* opts,
-                   double* const* Xs, double* const* lambdas, me_info* infos, void* stream);
+                   void* ws, size_t ws_bytes, double* const* Xs, double* const* lambdas,
+                   me_info* infos, void* stream);
 
 /* ---- Serving: continuous batching of independent requests ---------------
  * A server owns one LOBPCG engine on `stream`.  Each request is a graph and
- * K; requests wait in a FIFO queue until their estimated device footprint
- * (operators plus solver state) fits `mem_budget` next to the admitted ones
- * and fewer than `max_active` are admitted.  An admitted request is built on
+ * K; requests wait in a FIFO queue until their device footprint (an upper
+ * bound of operators plus solver state, from W's degrees as in
+ * me_build_workspace_bytes) fits `mem_budget` next to the admitted ones and
+ * fewer than `max_active` are admitted.  With a caller workspace the
+ * footprint is reserved in it as one range when the request is admitted and
+ * returned when it retires, and the server allocates no device memory; a
+ * request that cannot fit even in an idle server completes with
+ * ME_ERR_WORKSPACE.  An admitted request is built on
  * a second stream of the server (default priority) while the engine's
  * current round runs, solves eps = lambda_2(Q) and then its embedding as
  * engine slots beside all other admitted requests, and is retired when its
@@ -252,14 +300,25 @@ int me_embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_
  * stores the Chebyshev iterates in FP32).  One host thread drives a server. */
 typedef struct me_server me_server;
 typedef struct {
-  size_t mem_budget; /* device bytes for admitted requests; 0 = 60% of free memory at creation */
+  size_t mem_budget; /* device bytes for admitted requests; 0 = 60% of free memory at creation
+                        (with a workspace: its size, > 0)                               */
   int max_active;    /* requests admitted at once, >= 1 (default 256)                  */
   me_opts opts;      /* solver options of every request                               */
+  void* workspace;   /* NULL (default) or a caller-owned device region of mem_budget
+                        bytes that holds everything the server puts on the device
+                        (a 128th of it, at least 256 KiB, for the solver's work lists);
+                        it must outlive the server                                     */
 } me_server_opts;
 
 void me_server_opts_default(me_server_opts* so);
 /* Creates a server; `so` host, may be NULL (defaults). */
 int me_server_create(const me_server_opts* so, void* stream, me_server** out);
+/* Device footprint the server charges a request of graph W and K (the range
+ * it reserves in a caller region): the build as me_build_workspace_bytes
+ * bounds it and both solver slots.  Reads W's row pointers; synchronises
+ * `stream`.  A region needs, besides its requests, the server's tables and
+ * work-list areas (about a 64th of the region). */
+int me_server_request_bytes(const me_csr* W, int K, void* stream, size_t* bytes);
 /* Queues a request (no GPU work).  W: host struct of device pointers that
  * must stay valid until the request completes; X (n x K) and lambda (K):
  * device outputs, written when the request completes; K 1..16, tol > 0.

@@ -4,6 +4,7 @@ first K generalized eigenvectors of (A = L - mu Q + eps I, B) by LOBPCG, all
 in hand-written HIP kernels behind the C ABI of include/membed.h."""
 from ._lib import LIB_PATH, load  # noqa: F401
 from .api import (  # noqa: F401
-    DeviceCSR, GraphOps, MembedError, build_graph_ops, embed, embed_batch, kernel_timing,
-    kernel_timing_read, make_opts, Server, to_device,
+    DeviceCSR, GraphOps, MembedError, build_graph_ops, build_workspace_bytes, embed,
+    embed_batch, embed_batch_workspace_bytes, kernel_timing, kernel_timing_read, make_opts,
+    Server, server_request_bytes, to_device,
 )

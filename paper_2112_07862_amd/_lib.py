@@ -53,15 +53,19 @@ class MeInfo(ctypes.Structure):
 
 
 class MeServerOpts(ctypes.Structure):
-    _fields_ = [("mem_budget", c_size_t), ("max_active", c_int), ("opts", MeOpts)]
+    _fields_ = [("mem_budget", c_size_t), ("max_active", c_int), ("opts", MeOpts),
+                ("workspace", c_void_p)]
 
 
 # name -> (restype, argtypes)
 SIGNATURES = {
     "me_opts_default": (None, [ctypes.POINTER(MeOpts)]),
     "me_status_string": (ctypes.c_char_p, [c_int]),
+    "me_build_workspace_bytes": (c_int, [ctypes.POINTER(MeCsr), ctypes.POINTER(MeOpts),
+                                         c_void_p, ctypes.POINTER(c_size_t)]),
     "me_build_graph_ops": (c_int, [ctypes.POINTER(MeCsr), ctypes.POINTER(MeOpts), c_void_p,
-                                   ctypes.POINTER(c_void_p), ctypes.POINTER(MeInfo)]),
+                                   c_size_t, c_void_p, ctypes.POINTER(c_void_p),
+                                   ctypes.POINTER(MeInfo)]),
     "me_graph_ops_query": (c_int, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64),
                                    ctypes.POINTER(c_double), ctypes.POINTER(c_double),
                                    ctypes.POINTER(c_int)]),
@@ -73,13 +77,19 @@ SIGNATURES = {
     "me_embed_workspace_bytes": (c_size_t, [c_void_p, c_int, ctypes.POINTER(MeOpts)]),
     "me_embed": (c_int, [c_void_p, c_int, c_double, ctypes.POINTER(MeOpts), c_void_p, c_void_p,
                          c_size_t, c_void_p, c_void_p, ctypes.POINTER(MeInfo), c_void_p]),
+    "me_embed_batch_workspace_bytes": (c_int, [c_int, ctypes.POINTER(MeCsr),
+                                               ctypes.POINTER(c_int), ctypes.POINTER(MeOpts),
+                                               c_void_p, ctypes.POINTER(c_size_t)]),
     "me_embed_batch": (c_int, [c_int, ctypes.POINTER(MeCsr), ctypes.POINTER(c_int), c_double,
-                               ctypes.POINTER(MeOpts), ctypes.POINTER(c_void_p),
-                               ctypes.POINTER(c_void_p), ctypes.POINTER(MeInfo), c_void_p]),
+                               ctypes.POINTER(MeOpts), c_void_p, c_size_t,
+                               ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                               ctypes.POINTER(MeInfo), c_void_p]),
     "me_graph_ops_destroy": (None, [c_void_p]),
     "me_server_opts_default": (None, [ctypes.POINTER(MeServerOpts)]),
     "me_server_create": (c_int, [ctypes.POINTER(MeServerOpts), c_void_p,
                                  ctypes.POINTER(c_void_p)]),
+    "me_server_request_bytes": (c_int, [ctypes.POINTER(MeCsr), c_int, c_void_p,
+                                        ctypes.POINTER(c_size_t)]),
     "me_server_submit": (c_int, [c_void_p, ctypes.POINTER(MeCsr), c_int, c_double, c_void_p,
                                  c_void_p, ctypes.POINTER(c_int64)]),
     "me_server_step": (c_int, [c_void_p, ctypes.POINTER(c_int)]),

@@ -174,15 +174,35 @@ def c_int64_():
     return ctypes.c_int64()
 
 
-def build_graph_ops(csr, stream=None, **opts) -> GraphOps:
+def build_workspace_bytes(csr, stream=None, **opts) -> int:
+    """Device bytes build_graph_ops needs when given a workspace (an upper
+    bound: the two-hop pattern is sized by W's degrees)."""
+    dcsr = to_device(csr)
+    o = make_opts(**opts)
+    b = ctypes.c_size_t()
+    _check(L.load().me_build_workspace_bytes(ctypes.byref(dcsr.as_struct()), ctypes.byref(o),
+                                             _stream_ptr(stream), ctypes.byref(b)),
+           "build_workspace_bytes")
+    return int(b.value)
+
+
+def build_graph_ops(csr, stream=None, workspace: torch.Tensor | None = None, **opts) -> GraphOps:
+    """Builds the operators of one graph.  With `workspace` (a uint8 device
+    tensor of at least build_workspace_bytes) every device array of the
+    handle lives in it and the library allocates nothing; the tensor must
+    outlive the handle (the handle keeps a reference)."""
     dcsr = to_device(csr)
     o = make_opts(**opts)
     h = ctypes.c_void_p()
     info = L.MeInfo()
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     st = L.load().me_build_graph_ops(ctypes.byref(dcsr.as_struct()), ctypes.byref(o),
-                                     _stream_ptr(stream), ctypes.byref(h), ctypes.byref(info))
+                                     _ptr(workspace), nbytes, _stream_ptr(stream),
+                                     ctypes.byref(h), ctypes.byref(info))
     _check(st, "build_graph_ops")
-    return GraphOps(h, dcsr.n, info, st, dcsr)
+    ops = GraphOps(h, dcsr.n, info, st, dcsr)
+    ops._workspace = workspace
+    return ops
 
 
 def embed(graph, K: int, tol: float = 1e-6, X0: torch.Tensor | None = None,
@@ -222,11 +242,30 @@ def embed(graph, K: int, tol: float = 1e-6, X0: torch.Tensor | None = None,
             ops.close()
 
 
-def embed_batch(graphs, Ks, tol: float = 1e-6, stream=None, **opts):
+def embed_batch_workspace_bytes(graphs, Ks, stream=None, **opts) -> int:
+    """Device bytes embed_batch needs when given a workspace (an upper bound)."""
+    G = len(graphs)
+    if isinstance(Ks, int):
+        Ks = [Ks] * G
+    dcsrs = [to_device(g) for g in graphs]
+    o = make_opts(**opts)
+    Ws = (L.MeCsr * max(G, 1))(*[d.as_struct() for d in dcsrs])
+    Kc = (ctypes.c_int * max(G, 1))(*[int(k) for k in Ks])
+    b = ctypes.c_size_t()
+    _check(L.load().me_embed_batch_workspace_bytes(G, Ws, Kc, ctypes.byref(o),
+                                                   _stream_ptr(stream), ctypes.byref(b)),
+           "embed_batch_workspace_bytes")
+    return int(b.value)
+
+
+def embed_batch(graphs, Ks, tol: float = 1e-6, stream=None,
+                workspace: torch.Tensor | None = None, **opts):
     """Embeds many graphs in one batched solve.  `graphs`: CSRs (host or
-    DeviceCSR); `Ks`: one K per graph (or a single int).  Returns a list of
-    (X, lambda, info) per graph; graphs that failed carry info["status"] < 0
-    and X, lambda None.  Raises only if the call as a whole is invalid."""
+    DeviceCSR); `Ks`: one K per graph (or a single int).  With `workspace` (a
+    uint8 device tensor of at least embed_batch_workspace_bytes) the library
+    allocates no device memory.  Returns a list of (X, lambda, info) per
+    graph; graphs that failed carry info["status"] < 0 and X, lambda None.
+    Raises only if the call as a whole is invalid."""
     lib = L.load()
     G = len(graphs)
     if isinstance(Ks, int):
@@ -235,6 +274,7 @@ def embed_batch(graphs, Ks, tol: float = 1e-6, stream=None, **opts):
         raise ValueError("one K per graph")
     dcsrs = [to_device(g) for g in graphs]
     o = make_opts(**opts)
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     Xs = [torch.empty((d.n, int(k)), dtype=torch.float64, device=d.rowptr.device)
           for d, k in zip(dcsrs, Ks)]
     lams = [torch.empty(max(int(k), 1), dtype=torch.float64, device=d.rowptr.device)
@@ -244,9 +284,9 @@ def embed_batch(graphs, Ks, tol: float = 1e-6, stream=None, **opts):
     Xp = (ctypes.c_void_p * max(G, 1))(*[x.data_ptr() for x in Xs])
     Lp = (ctypes.c_void_p * max(G, 1))(*[l.data_ptr() for l in lams])
     infos = (L.MeInfo * max(G, 1))()
-    st = lib.me_embed_batch(G, Ws, Kc, float(tol), ctypes.byref(o), Xp, Lp, infos,
-                            _stream_ptr(stream))
-    if st == -1 and all(infos[i].status == 0 for i in range(G)):
+    st = lib.me_embed_batch(G, Ws, Kc, float(tol), ctypes.byref(o), _ptr(workspace), nbytes,
+                            Xp, Lp, infos, _stream_ptr(stream))
+    if st in (-1, -7) and all(infos[i].status == 0 for i in range(G)):
         _check(st, "embed_batch")
     out = []
     for i in range(G):
@@ -259,18 +299,37 @@ def embed_batch(graphs, Ks, tol: float = 1e-6, stream=None, **opts):
     return out
 
 
+def server_request_bytes(csr, K: int, stream=None) -> int:
+    """Device footprint a Server charges a request (its reservation in a
+    caller region)."""
+    d = to_device(csr)
+    b = ctypes.c_size_t()
+    _check(L.load().me_server_request_bytes(ctypes.byref(d.as_struct()), int(K),
+                                            _stream_ptr(stream), ctypes.byref(b)),
+           "server_request_bytes")
+    return int(b.value)
+
+
 class Server:
     """Continuous-batching request loop (me_server_*): submit graphs at any
     time, call step() to advance every admitted solve by one round (and admit,
     retire and backfill), poll() for finished requests."""
 
-    def __init__(self, mem_budget: int = 0, max_active: int = 256, stream=None, **opts):
+    def __init__(self, mem_budget: int = 0, max_active: int = 256, stream=None,
+                 workspace: torch.Tensor | None = None, **opts):
+        """With `workspace` (a uint8 device tensor) every request's device
+        memory is carved from it (mem_budget = its size) and the server
+        allocates none; requests wait until their footprint fits."""
         lib = L.load()
         so = L.MeServerOpts()
         lib.me_server_opts_default(ctypes.byref(so))
         so.mem_budget = int(mem_budget)
         so.max_active = int(max_active)
         so.opts = make_opts(**opts)
+        if workspace is not None:
+            so.workspace = workspace.data_ptr()
+            so.mem_budget = workspace.numel() * workspace.element_size()
+        self._workspace = workspace
         self._stream = stream
         h = ctypes.c_void_p()
         _check(lib.me_server_create(ctypes.byref(so), _stream_ptr(stream), ctypes.byref(h)),

@@ -9,9 +9,11 @@ using namespace me;
 
 namespace me {
 void free_graph_ops(GraphOps& g) {
-  if (g.mem) (void)hipFree(g.mem);
-  if (g.mem2) (void)hipFree(g.mem2);
-  if (g.ord_mem) (void)hipFree(g.ord_mem);
+  if (!g.in_region) {  // region memory belongs to the caller's workspace
+    if (g.mem) (void)hipFree(g.mem);
+    if (g.mem2) (void)hipFree(g.mem2);
+    if (g.ord_mem) (void)hipFree(g.ord_mem);
+  }
   g.mem = g.mem2 = g.ord_mem = nullptr;
 }
 }  // namespace me
@@ -65,18 +67,40 @@ const char* me_status_string(int st) {
 }
 
 
-int me_build_graph_ops(const me_csr* W, const me_opts* opts, void* stream, me_graph_ops** out,
-                       me_info* info) {
+int me_build_workspace_bytes(const me_csr* W, const me_opts* opts, void* stream,
+                             size_t* bytes) {
+  if (!W || !bytes) return ME_ERR_INVALID_ARG;
+  *bytes = 0;
+  me_opts o;
+  if (opts) o = *opts; else me_opts_default(&o);
+  if (!opts_valid(o)) return ME_ERR_INVALID_ARG;
+  int64_t tb = 0;
+  ME_TRY_STATUS(two_hop_bound(W, (hipStream_t)stream, &tb));
+  *bytes = kHeapAlign + build_bytes_bound(W->n, W->nnz, tb) + eps_solve_bytes(W->n);
+  return ME_OK;
+}
+
+int me_build_graph_ops(const me_csr* W, const me_opts* opts, void* ws, size_t ws_bytes,
+                       void* stream, me_graph_ops** out, me_info* info) {
   if (!W || !out) return ME_ERR_INVALID_ARG;
   *out = nullptr;
   me_opts o;
   if (opts) o = *opts; else me_opts_default(&o);
   if (!opts_valid(o)) return ME_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (ws && ws_bytes < 2 * kHeapAlign) return ME_ERR_WORKSPACE;  // before any device call
+  if (ws) {
+    size_t need = 0;
+    ME_TRY_STATUS(me_build_workspace_bytes(W, &o, stream, &need));
+    if (ws_bytes < need) return ME_ERR_WORKSPACE;
+  }
   const auto t0 = std::chrono::steady_clock::now();
   auto* h = new (std::nothrow) me_graph_ops();
   if (!h) return ME_ERR_HIP;
-  hipStream_t s = (hipStream_t)stream;
-  int st = build_graph_ops(W, &o, s, &h->g, info);
+  // with a workspace the handle's arrays live in it and nothing is allocated
+  DevHeap region(ws, ws_bytes);
+  DevHeap hip;
+  int st = build_graph_ops(W, &o, ws ? region : hip, s, &h->g, info);
   if (st < 0) {
     (void)hipStreamSynchronize(s);
     free_ops(h->g);
@@ -168,7 +192,7 @@ size_t me_embed_workspace_bytes(const me_graph_ops* ops, int K, const me_opts* o
   if (!ops || K < 1 || K > kMaxBlockCols) return 0;
   me_opts o;
   if (opts) o = *opts; else me_opts_default(&o);
-  return embed_workspace_bytes(ops->g, K, &o);
+  return embed_workspace_bytes(ops->g.n, K, &o);
 }
 
 int me_embed(const me_graph_ops* ops, int K, double tol, const me_opts* opts, const double* X0,
@@ -180,16 +204,29 @@ int me_embed(const me_graph_ops* ops, int K, double tol, const me_opts* opts, co
   return embed(ops->g, K, tol, &o, X0, ws, ws_bytes, X, lambda, info, (hipStream_t)stream);
 }
 
+int me_embed_batch_workspace_bytes(int G, const me_csr* Ws, const int* Ks, const me_opts* opts,
+                                   void* stream, size_t* bytes) {
+  if (!bytes || G < 0 || (G > 0 && (!Ws || !Ks))) return ME_ERR_INVALID_ARG;
+  *bytes = 0;
+  if (G == 0) return ME_OK;
+  me_opts o;
+  if (opts) o = *opts; else me_opts_default(&o);
+  if (!opts_valid(o)) return ME_ERR_INVALID_ARG;
+  return batch_workspace_bytes(G, Ws, Ks, &o, (hipStream_t)stream, bytes);
+}
+
 int me_embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opts* opts,
-                   double* const* Xs, double* const* lambdas, me_info* infos, void* stream) {
+                   void* ws, size_t ws_bytes, double* const* Xs, double* const* lambdas,
+                   me_info* infos, void* stream) {
   if (G < 0 || (G > 0 && (!Ws || !Ks || !Xs || !lambdas)) || !(tol > 0.0))
     return ME_ERR_INVALID_ARG;
   if (G == 0) return ME_OK;
   me_opts o;
   if (opts) o = *opts; else me_opts_default(&o);
   if (!opts_valid(o)) return ME_ERR_INVALID_ARG;
+  if (ws && ws_bytes < 2 * kHeapAlign) return ME_ERR_WORKSPACE;  // before any device call
   if (infos) std::memset(infos, 0, sizeof(me_info) * (size_t)G);
-  return embed_batch(G, Ws, Ks, tol, &o, Xs, lambdas, infos, (hipStream_t)stream);
+  return embed_batch(G, Ws, Ks, tol, &o, ws, ws_bytes, Xs, lambdas, infos, (hipStream_t)stream);
 }
 
 void me_graph_ops_destroy(me_graph_ops* ops) {

@@ -713,15 +713,21 @@ __global__ void __launch_bounds__(kBfsThreads) k_cm_order(const OrderArgs* args)
   __shared__ FrontierLds f;
   __shared__ EdgeLds el;
   const int tid = threadIdx.x;
-  for (int64_t i = tid; i < n; i += kBfsThreads) {
-    level[i] = -1;
-    key[i] = INT32_MAX;
-  }
-  __syncthreads();
   int32_t last = 0;
-  int64_t off =
-      cm_component(rp, col, level, key, eoff, ev, ei, ef, perm, 0, *start, 0, s_wave, &f, &el,
-                   &last);
+  int64_t off = 0;
+  if (ga.resume_off > 0) {
+    // the first component is placed (by the per-level kernels)
+    off = ga.resume_off;
+    last = ga.resume_last;
+  } else {
+    for (int64_t i = tid; i < n; i += kBfsThreads) {
+      level[i] = -1;
+      key[i] = INT32_MAX;
+    }
+    __syncthreads();
+    off = cm_component(rp, col, level, key, eoff, ev, ei, ef, perm, 0, *start, 0, s_wave, &f, &el,
+                       &last);
+  }
   // further components: the lowest unvisited node only grows
   int64_t ptr = 0;
   for (;;) {
@@ -746,6 +752,259 @@ __global__ void __launch_bounds__(kBfsThreads) k_cm_order(const OrderArgs* args)
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// The same two searches for large graphs, one launch per level over many
+// workgroups (a single workgroup is bound by one CU's memory throughput on
+// the wide levels of a large graph).  The host enqueues rounds of levels
+// from a thread of its own and reads the frontier size between rounds;
+// levels past the end of a search exit at once.  The results are those of
+// the one-workgroup kernels (and of the sequential algorithm): levels are
+// claimed with the same compare-and-swap, a child's parent is the lowest
+// frontier position that reaches it, and children are placed by a scan over
+// the frontier in position order, each parent's in row order.
+// ---------------------------------------------------------------------------
+constexpr int64_t kWideOrderMin = 32768;  // graphs of at least this many nodes
+constexpr int kLvlGrid = 256;             // workgroups of a per-level launch
+constexpr int kLvlThreads = 256;
+constexpr int kNodeLanes = 16;            // lanes per frontier node
+constexpr int kLvlChunk = kLvlThreads / kNodeLanes;  // frontier nodes per workgroup pass
+constexpr int kLevelsPerRound = 32;       // levels enqueued between host reads
+
+// Frontier state of one level (device).  The plain search keeps three (level
+// t reads [t % 3], appends to [(t + 1) % 3] and clears [(t + 2) % 3]); the
+// ordering keeps two (level t reads [t % 2], its last chunk writes
+// [(t + 1) % 2]).
+struct LevelCtl {
+  int32_t nin;     // frontier size
+  int32_t lev;     // level of the frontier
+  int64_t placed;  // ordering: nodes placed so far (the frontier is the last nin)
+};
+
+__device__ __forceinline__ int32_t ld_ctl(const int32_t* p) { return ld_coherent(p); }
+
+// Level t of the plain search: the frontier fin (level t) claims level t + 1
+// into fout.  res[0] = last level with a non-empty frontier.
+__global__ void __launch_bounds__(kLvlThreads) k_bfs_level(const int64_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ col,
+                                                           int32_t* level, const int32_t* fin,
+                                                           int32_t* fout, LevelCtl* ctl, int t,
+                                                           int32_t* res) {
+  // res[1] = 1 once a level came out empty: every later level exits (a
+  // buffer that cycles back still holds an old frontier)
+  if (ld_coherent(&res[1])) return;
+  LevelCtl* cur = ctl + t % 3;
+  LevelCtl* nxt = ctl + (t + 1) % 3;
+  const int32_t nin = ld_ctl(&cur->nin);
+  if (nin == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) res[1] = 1;
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    LevelCtl* clr = ctl + (t + 2) % 3;
+    clr->nin = 0;
+    res[0] = t;
+  }
+  const int sub = threadIdx.x % kNodeLanes;
+  const int64_t stride = (int64_t)gridDim.x * (kLvlThreads / kNodeLanes);
+  for (int64_t i = ((int64_t)blockIdx.x * kLvlThreads + threadIdx.x) / kNodeLanes; i < nin;
+       i += stride) {
+    const int32_t u = fin[i];
+    const int64_t e1 = rp[u + 1];
+    for (int64_t e = rp[u] + sub; e < e1; e += kNodeLanes) {
+      const int32_t v = col[e];
+      if (ld_coherent(&level[v]) < 0 && atomicCAS(&level[v], -1, t + 1) == -1)
+        fout[atomicAdd(&nxt->nin, 1)] = v;
+    }
+  }
+}
+
+// Lowest node id on the last level (one workgroup): the pseudo-peripheral
+// start.  Level t's frontier is in fa for even t, fb for odd t.
+__global__ void __launch_bounds__(kLvlThreads) k_frontier_min(const int32_t* fa, const int32_t* fb,
+                                                              const LevelCtl* ctl,
+                                                              const int32_t* res, int32_t* out) {
+  __shared__ int32_t s_min;
+  if (threadIdx.x == 0) s_min = INT32_MAX;
+  __syncthreads();
+  const int32_t t = res[0];
+  const int32_t nin = ctl[t % 3].nin;
+  const int32_t* f = (t & 1) ? fb : fa;
+  int32_t m = INT32_MAX;
+  for (int32_t i = threadIdx.x; i < nin; i += kLvlThreads) m = min(m, f[i]);
+  atomicMin(&s_min, m);
+  __syncthreads();
+  if (threadIdx.x == 0) *out = s_min;
+}
+
+__global__ void k_fill_i32(int64_t n, int32_t* a, int32_t v) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// Search starts: plain search from node 0, ordering from the
+// pseudo-peripheral node.
+__global__ void k_bfs_start(int32_t* level, int32_t* fa, LevelCtl* ctl, int32_t* res) {
+  level[0] = 0;
+  fa[0] = 0;
+  ctl[0] = LevelCtl{1, 0, 1};
+  ctl[1] = LevelCtl{0, 0, 0};
+  ctl[2] = LevelCtl{0, 0, 0};
+  res[0] = 0;
+  res[1] = 0;
+}
+
+__global__ void k_store_i32(int32_t* p, int32_t v) { *p = v; }
+
+__global__ void k_cm_start(int32_t* level, int32_t* perm, const int32_t* start, LevelCtl* ctl) {
+  const int32_t v = *start;
+  level[v] = 0;
+  perm[0] = v;
+  ctl[0] = LevelCtl{1, 0, 1};
+  ctl[1] = LevelCtl{0, 0, 0};
+}
+
+// Ordering, level t, step 1: every frontier node claims its unvisited
+// neighbours for the next level and lowers their key to its position.
+__global__ void __launch_bounds__(kLvlThreads) k_cm_claim(const int64_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ col,
+                                                          int32_t* level, int32_t* key,
+                                                          const int32_t* perm, const LevelCtl* ctl,
+                                                          int t) {
+  const LevelCtl* cur = ctl + (t & 1);
+  const int32_t nin = ld_ctl(&cur->nin);
+  if (nin == 0) return;
+  const int32_t lev = cur->lev;
+  const int32_t* fin = perm + (cur->placed - nin);
+  const int sub = threadIdx.x % kNodeLanes;
+  const int64_t stride = (int64_t)gridDim.x * (kLvlThreads / kNodeLanes);
+  for (int64_t i = ((int64_t)blockIdx.x * kLvlThreads + threadIdx.x) / kNodeLanes; i < nin;
+       i += stride) {
+    const int32_t u = fin[i];
+    const int64_t e1 = rp[u + 1];
+    for (int64_t e = rp[u] + sub; e < e1; e += kNodeLanes) {
+      const int32_t v = col[e];
+      int32_t lv = ld_coherent(&level[v]);
+      if (lv < 0) {
+        const int32_t old = atomicCAS(&level[v], -1, lev + 1);
+        lv = old < 0 ? lev + 1 : old;
+      }
+      if (lv == lev + 1) atomicMin(&key[v], (int32_t)i);
+    }
+  }
+}
+
+// Children of frontier position i among its row's edges, e in row order:
+// flag = the neighbour is on the next level and i is its parent.
+__device__ __forceinline__ bool cm_child(const int32_t* level, const int32_t* key, int32_t v,
+                                         int32_t lev, int32_t i) {
+  return ld_coherent(&level[v]) == lev + 1 && ld_coherent(&key[v]) == i;
+}
+
+// Step 2: children per frontier node, and per chunk of kLvlChunk positions
+// (one chunk per workgroup pass, kNodeLanes lanes per node).
+__global__ void __launch_bounds__(kLvlThreads) k_cm_count(const int64_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ col,
+                                                          const int32_t* level, const int32_t* key,
+                                                          const int32_t* perm, int32_t* cnt,
+                                                          int32_t* partial, const LevelCtl* ctl,
+                                                          int t) {
+  const LevelCtl* cur = ctl + (t & 1);
+  const int32_t nin = ld_ctl(&cur->nin);
+  if (nin == 0) return;
+  const int32_t lev = cur->lev;
+  const int32_t* fin = perm + (cur->placed - nin);
+  __shared__ int32_t s_k[kLvlChunk];
+  const int sub = threadIdx.x % kNodeLanes, slot = threadIdx.x / kNodeLanes;
+  const int32_t nchunks = (nin + kLvlChunk - 1) / kLvlChunk;
+  for (int32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const int32_t i = c * kLvlChunk + slot;
+    int32_t k = 0;
+    if (i < nin) {
+      const int32_t u = fin[i];
+      const int64_t e1 = rp[u + 1];
+      for (int64_t e = rp[u] + sub; e < e1; e += kNodeLanes) k += cm_child(level, key, col[e], lev, i);
+    }
+    for (int o = kNodeLanes / 2; o > 0; o >>= 1) k += __shfl_xor(k, o, kNodeLanes);
+    if (sub == 0) {
+      if (i < nin) cnt[i] = k;
+      s_k[slot] = k;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int32_t x = 0;
+      for (int q = 0; q < kLvlChunk; ++q) x += s_k[q];
+      partial[c] = x;
+    }
+    __syncthreads();
+  }
+}
+
+// Step 3 (one workgroup): exclusive scan of the chunk counts in place, and
+// the next level's state (its frontier is the children just counted).
+__global__ void __launch_bounds__(kBfsThreads) k_cm_scan(int32_t* partial, LevelCtl* ctl, int t) {
+  const LevelCtl* cur = ctl + (t & 1);
+  LevelCtl* nxt = ctl + ((t + 1) & 1);
+  const int32_t nin = ld_ctl(&cur->nin);
+  if (nin == 0) {
+    if (threadIdx.x == 0) *nxt = *cur;
+    return;
+  }
+  __shared__ int32_t s_wave[kBfsThreads / kWave];
+  const int32_t nchunks = (nin + kLvlChunk - 1) / kLvlChunk;
+  const int32_t total = block_exclusive_scan(partial, nchunks, s_wave);
+  if (threadIdx.x == 0) *nxt = LevelCtl{total, cur->lev + 1, cur->placed + total};
+}
+
+// Step 4: place every child: a chunk starts at its scanned offset, a node at
+// the counts of the chunk's nodes before it, and a node's children keep row
+// order.
+__global__ void __launch_bounds__(kLvlThreads) k_cm_place(const int64_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ col,
+                                                          const int32_t* level, const int32_t* key,
+                                                          int32_t* perm, const int32_t* cnt,
+                                                          const int32_t* partial,
+                                                          const LevelCtl* ctl, int t) {
+  const LevelCtl* cur = ctl + (t & 1);
+  const int32_t nin = ld_ctl(&cur->nin);
+  if (nin == 0) return;
+  const int32_t lev = cur->lev;
+  const int64_t placed = cur->placed;
+  const int32_t* fin = perm + (placed - nin);
+  int32_t* fout = perm + placed;
+  __shared__ int32_t s_k[kLvlChunk];
+  const int tid = threadIdx.x, lane = tid % kWave;
+  const int sub = tid % kNodeLanes, slot = tid / kNodeLanes, grp = lane / kNodeLanes;
+  const int32_t nchunks = (nin + kLvlChunk - 1) / kLvlChunk;
+  for (int32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const int32_t i = c * kLvlChunk + slot;
+    const bool live = i < nin;
+    if (sub == 0) s_k[slot] = live ? cnt[i] : 0;
+    __syncthreads();
+    int32_t pos = partial[c];
+    for (int q = 0; q < slot; ++q) pos += s_k[q];
+    int64_t e0 = 0, e1 = 0;
+    if (live) {
+      const int32_t u = fin[i];
+      e0 = rp[u];
+      e1 = rp[u + 1];
+    }
+    for (int64_t e = e0; e < e1; e += kNodeLanes) {
+      const int64_t my = e + sub;
+      int32_t v = 0;
+      bool f = false;
+      if (my < e1) {
+        v = col[my];
+        f = cm_child(level, key, v, lev, i);
+      }
+      const uint64_t m = (__ballot(f) >> (grp * kNodeLanes)) & ((1ull << kNodeLanes) - 1);
+      if (f) fout[pos + __popcll(m & ((1ull << sub) - 1))] = v;
+      pos += __popcll(m);
+    }
+    __syncthreads();
+  }
+}
+
 // lev_s[i'] = breadth-first level of solver row i'
 __global__ void k_gather_level(int64_t n, const int32_t* perm, const int32_t* level,
                                int32_t* lev_s) {
@@ -766,16 +1025,24 @@ __global__ void k_invert_perm(int64_t n, const int32_t* perm, int32_t* iperm) {
 // perm (solver index -> user index), iperm (user -> solver).
 // Scratch and arguments of a graph's searches (graphs of at most kDenseMaxN
 // nodes take the identity order and need none).
-static int order_alloc(GraphOps* g, hipStream_t s) {
+size_t order_scratch_bytes(int64_t n, int64_t nnz) {
+  if (n <= kDenseMaxN) return 0;
+  return Arena::round((n + 2) * 4) * 3 + Arena::round((nnz + 2) * 4) * 3 + Arena::round(64);
+}
+
+size_t order_args_bytes(int G) {
+  return Arena::round(sizeof(OrderArgs) * (G > 0 ? G : 1)) + Arena::round(4 * (size_t)G + 4);
+}
+
+static int order_alloc(GraphOps* g, DevHeap& heap, hipStream_t s) {
   const int64_t n = g->n;
   g->ord = OrderArgs{};
   g->ord.n = n;
   g->ord.perm = g->perm;
   if (n <= kDenseMaxN) return ME_OK;
   const int64_t nnz = g->nnz_w;
-  const size_t bytes =
-      Arena::round((n + 2) * 4) * 3 + Arena::round((nnz + 2) * 4) * 3 + Arena::round(64);
-  ME_TRY(hipMallocAsync(&g->ord_mem, bytes, s));
+  const size_t bytes = order_scratch_bytes(n, nnz);
+  ME_TRY_STATUS(heap.alloc(&g->ord_mem, bytes, s));
   Arena a{(char*)g->ord_mem, bytes, 0};
   g->ord.rp = g->w_rp;
   g->ord.col = g->w_col;
@@ -789,23 +1056,99 @@ static int order_alloc(GraphOps* g, hipStream_t s) {
   return ME_OK;
 }
 
+static bool wide_graph(const GraphOps* g) { return g->ord_mem && g->n >= kWideOrderMin; }
+
+// Both searches of one large graph by per-level launches on s (see the
+// per-level kernels); dargs: the graph's arguments on the device.
+static int wide_order(GraphOps* g, OrderArgs* dargs, hipStream_t s) {
+  const int64_t n = g->n;
+  const OrderArgs& a = g->ord;
+  LevelCtl* ctl = reinterpret_cast<LevelCtl*>(a.ei);  // 3 plain-search + 2 ordering states
+  int32_t* res = reinterpret_cast<int32_t*>(ctl + 5);
+  int32_t* partial = a.ev;  // one count per frontier chunk
+  int32_t* key = a.fa;
+  int32_t* cnt = a.fb;
+  const int64_t nb = ceil_div(n, kBlock);
+  // plain search from node 0: its last level gives the start
+  k_fill_i32<<<nb, kBlock, 0, s>>>(n, a.level, -1);
+  k_bfs_start<<<1, 1, 0, s>>>(a.level, a.fa, ctl, res);
+  int64_t t = 0;
+  for (;;) {
+    for (int q = 0; q < kLevelsPerRound; ++q, ++t) {
+      const bool odd = t & 1;
+      k_bfs_level<<<kLvlGrid, kLvlThreads, 0, s>>>(a.rp, a.col, a.level, odd ? a.fb : a.fa,
+                                                  odd ? a.fa : a.fb, ctl, (int)t, res);
+    }
+    int32_t h[2] = {0, 0};
+    ME_TRY(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, s));
+    ME_TRY(hipStreamSynchronize(s));
+    if (h[1]) break;
+    if (t > n + kLevelsPerRound) return ME_ERR_HIP;  // a search has at most n levels
+  }
+  k_frontier_min<<<1, kLvlThreads, 0, s>>>(a.fa, a.fb, ctl, res, a.start);
+  // Cuthill-McKee order of the start's component
+  LevelCtl* cc = ctl + 3;
+  k_fill_i32<<<nb, kBlock, 0, s>>>(n, a.level, -1);
+  k_fill_i32<<<nb, kBlock, 0, s>>>(n, key, INT32_MAX);
+  k_cm_start<<<1, 1, 0, s>>>(a.level, a.perm, a.start, cc);
+  LevelCtl h{};
+  t = 0;
+  for (;;) {
+    for (int q = 0; q < kLevelsPerRound; ++q, ++t) {
+      k_cm_claim<<<kLvlGrid, kLvlThreads, 0, s>>>(a.rp, a.col, a.level, key, a.perm, cc, (int)t);
+      k_cm_count<<<kLvlGrid, kLvlThreads, 0, s>>>(a.rp, a.col, a.level, key, a.perm, cnt, partial,
+                                                 cc, (int)t);
+      k_cm_scan<<<1, kBfsThreads, 0, s>>>(partial, cc, (int)t);
+      k_cm_place<<<kLvlGrid, kLvlThreads, 0, s>>>(a.rp, a.col, a.level, key, a.perm, cnt, partial,
+                                                 cc, (int)t);
+    }
+    ME_TRY(hipMemcpyAsync(&h, cc + (t & 1), sizeof(h), hipMemcpyDeviceToHost, s));
+    ME_TRY(hipStreamSynchronize(s));
+    if (h.nin == 0) break;
+    if (t > n + kLevelsPerRound) return ME_ERR_HIP;
+  }
+  if (h.placed < n) {
+    // further components: the one-workgroup kernel continues from here
+    OrderArgs r = a;
+    r.resume_off = h.placed;
+    r.resume_last = h.lev - 1;
+    ME_TRY(hipMemcpyAsync(dargs, &r, sizeof(OrderArgs), hipMemcpyHostToDevice, s));
+    k_cm_order<<<1, kBfsThreads, 0, s>>>(dargs);
+    ME_TRY(hipStreamSynchronize(s));  // r is read by the copy
+  } else {
+    k_store_i32<<<1, 1, 0, s>>>(a.maxlev, h.lev - 1);
+  }
+  return ME_OK;
+}
+
 // The pseudo-peripheral starts and the Cuthill-McKee orders of G graphs
-// (one workgroup per graph in each launch), then iperm and the solver-order
-// levels of each.  *args_mem receives the argument array (device) that
-// order_finish releases.
-int order_launch(GraphOps* const* gs, int G, hipStream_t s, void** args_mem) {
-  *args_mem = nullptr;
+// (one workgroup per graph in each launch; graphs of kWideOrderMin nodes or
+// more by per-level launches driven from a host thread of the job), then
+// iperm and the solver-order levels of each.  job->args receives the
+// argument array (device) that order_finish releases.
+int order_launch(GraphOps* const* gs, int G, DevHeap& heap, hipStream_t s, OrderJob* job) {
+  job->args = nullptr;
+  job->status = ME_OK;
   std::vector<OrderArgs> host;
+  std::vector<GraphOps*> wide;
   for (int i = 0; i < G; ++i)
-    if (gs[i]->ord_mem) host.push_back(gs[i]->ord);
+    if (gs[i]->ord_mem && !wide_graph(gs[i])) host.push_back(gs[i]->ord);
   const int m = (int)host.size();
-  const size_t bytes = Arena::round(sizeof(OrderArgs) * (m > 0 ? m : 1)) + Arena::round(4 * G + 4);
-  ME_TRY(hipMallocAsync(args_mem, bytes, s));
-  OrderArgs* dargs = (OrderArgs*)*args_mem;
-  int32_t* maxlev = (int32_t*)((char*)*args_mem + Arena::round(sizeof(OrderArgs) * (m > 0 ? m : 1)));
-  for (int q = 0; q < m; ++q) host[q].maxlev = maxlev + q;
+  for (int i = 0; i < G; ++i)
+    if (wide_graph(gs[i])) {
+      host.push_back(gs[i]->ord);
+      wide.push_back(gs[i]);
+    }
+  const int mt = (int)host.size();
+  ME_TRY_STATUS(heap.alloc(&job->args, order_args_bytes(G), s));
+  OrderArgs* dargs = (OrderArgs*)job->args;
+  int32_t* maxlev =
+      (int32_t*)((char*)job->args + Arena::round(sizeof(OrderArgs) * (G > 0 ? G : 1)));
+  for (int q = 0; q < mt; ++q) host[q].maxlev = maxlev + q;
+  for (size_t w = 0; w < wide.size(); ++w) wide[w]->ord.maxlev = maxlev + m + w;
+  if (mt > 0)
+    ME_TRY(hipMemcpyAsync(dargs, host.data(), sizeof(OrderArgs) * mt, hipMemcpyHostToDevice, s));
   if (m > 0) {
-    ME_TRY(hipMemcpyAsync(dargs, host.data(), sizeof(OrderArgs) * m, hipMemcpyHostToDevice, s));
     k_pseudo_peripheral<<<m, kBfsThreads, 0, s>>>(dargs);
     k_cm_order<<<m, kBfsThreads, 0, s>>>(dargs);
   }
@@ -817,29 +1160,66 @@ int order_launch(GraphOps* const* gs, int G, hipStream_t s, void** args_mem) {
       k_iota<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->iperm);
       continue;
     }
+    if (wide_graph(g)) continue;
     k_invert_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->iperm);
     k_gather_level<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->ord.level, g->lev_s);
+  }
+  if (!wide.empty()) {
+    // the wide searches wait on the host between rounds of levels: a thread
+    // of their own keeps the caller free to enqueue other work meanwhile
+    int dev = 0;
+    ME_TRY(hipGetDevice(&dev));
+    const hipError_t ready = hipStreamSynchronize(s);  // the argument copy has landed
+    if (ready != hipSuccess) return ME_ERR_HIP;
+    job->th = std::thread([job, wide, dargs, m, s, dev]() {
+      if (hipSetDevice(dev) != hipSuccess) {
+        job->status = ME_ERR_HIP;
+        return;
+      }
+      for (size_t w = 0; w < wide.size(); ++w) {
+        GraphOps* g = wide[w];
+        const int st = wide_order(g, dargs + m + w, s);
+        if (st < 0) {
+          job->status = st;
+          return;
+        }
+        const int64_t n = g->n;
+        k_invert_perm<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->iperm);
+        k_gather_level<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->ord.level,
+                                                              g->lev_s);
+      }
+    });
   }
   return ME_OK;
 }
 
 // Waits for the searches, reads the deepest levels, frees their scratch.
-int order_finish(GraphOps* const* gs, int G, hipStream_t s, void* args_mem) {
-  int m = 0;
-  for (int i = 0; i < G; ++i) m += gs[i]->ord_mem ? 1 : 0;
-  std::vector<int32_t> lev(m > 0 ? m : 1, 0);
-  const size_t off = Arena::round(sizeof(OrderArgs) * (m > 0 ? m : 1));
-  if (m > 0 && args_mem)
-    ME_TRY(hipMemcpyAsync(lev.data(), (char*)args_mem + off, 4 * m, hipMemcpyDeviceToHost, s));
+int order_finish(GraphOps* const* gs, int G, DevHeap& heap, hipStream_t s, OrderJob* job) {
+  if (job->th.joinable()) job->th.join();
+  std::vector<int32_t> lev(G > 0 ? G : 1, 0);
+  int narrow = 0, nwide = 0;
+  for (int i = 0; i < G; ++i) {
+    if (!gs[i]->ord_mem) continue;
+    if (wide_graph(gs[i])) ++nwide; else ++narrow;
+  }
+  const size_t off = Arena::round(sizeof(OrderArgs) * (G > 0 ? G : 1));
+  if (narrow + nwide > 0 && job->args)
+    ME_TRY(hipMemcpyAsync(lev.data(), (char*)job->args + off, 4 * (narrow + nwide),
+                          hipMemcpyDeviceToHost, s));
   ME_TRY(hipStreamSynchronize(s));
-  int q = 0;
+  if (job->status < 0) return job->status;
+  int qn = 0, qw = narrow;
   for (int i = 0; i < G; ++i) {
     GraphOps* g = gs[i];
-    g->max_level = g->ord_mem ? lev[q++] : 0;
-    if (g->ord_mem) ME_TRY(hipFreeAsync(g->ord_mem, s));
-    g->ord_mem = nullptr;
+    if (g->ord_mem) g->max_level = wide_graph(g) ? lev[qw++] : lev[qn++];
+    else g->max_level = 0;
   }
-  if (args_mem) ME_TRY(hipFreeAsync(args_mem, s));
+  for (int i = 0; i < G; ++i) {
+    heap.release(gs[i]->ord_mem, s);  // the searches are complete (synchronised above)
+    gs[i]->ord_mem = nullptr;
+  }
+  heap.release(job->args, s);
+  job->args = nullptr;
   return ME_OK;
 }
 
@@ -1056,45 +1436,34 @@ static int read_scalar(const T* dev, T* host, hipStream_t s) {
 // Everything up to eps: validation, degrees, T, Q, the locality order and
 // the packed operator.  g->needs_eps tells whether eps = lambda_2(Q) must be
 // computed (connected two-hop graph); otherwise eps = 0 (ME_WARN_EPS_ZERO).
-static int build_pre_a_impl(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g,
-                            SideStream* side, void** args);
+static int build_pre_a_impl(const me_csr* W, const me_opts* o, DevHeap& heap, hipStream_t s,
+                            GraphOps* g, SideStream* side, OrderJob* job);
 
-int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
+int build_pre(const me_csr* W, const me_opts* o, DevHeap& heap, hipStream_t s, GraphOps* g) {
   SideStream side;
-  void* args = nullptr;
-  struct Pending {  // releases the search arguments if a step fails
-    void** args;
+  OrderJob job;
+  struct Pending {  // waits for the searches and releases their arguments if a step fails
+    OrderJob& job;
+    DevHeap& heap;
     ~Pending() {
-      if (*args) {
+      if (job.th.joinable()) job.th.join();
+      if (job.args) {
         (void)hipDeviceSynchronize();
-        (void)hipFree(*args);
+        heap.release(job.args, nullptr);
       }
     }
-  } pending{&args};
-  ME_TRY_STATUS(build_pre_a_impl(W, o, s, g, &side, &args));
-  const int st = order_finish(&g, 1, side.s, args);
-  args = nullptr;  // released by order_finish
+  } pending{job, heap};
+  ME_TRY_STATUS(build_pre_a_impl(W, o, heap, s, g, &side, &job));
+  const int st = order_finish(&g, 1, heap, side.s, &job);
   if (st < 0) return st;
   return build_pre_b(g, s);
 }
 
-int build_pre_a(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g) {
-  return build_pre_a_impl(W, o, s, g, nullptr, nullptr);
+int build_pre_a(const me_csr* W, const me_opts* o, DevHeap& heap, hipStream_t s, GraphOps* g) {
+  return build_pre_a_impl(W, o, heap, s, g, nullptr, nullptr);
 }
 
-// side != null: the graph's searches start on a side stream right after
-// validation and run beside the two-hop construction.
-static int build_pre_a_impl(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g,
-                            SideStream* side, void** args) {
-  const int64_t n = W->n, nnz = W->nnz;
-  if (n < 1 || nnz < 0 || !W->rowptr || (nnz > 0 && (!W->col || !W->val)))
-    return ME_ERR_INVALID_ARG;
-  if (n >= (int64_t)INT32_MAX) return ME_ERR_TOO_LARGE;
-  ME_TRY(hipGetDevice(&g->device));
-  g->n = n;
-  g->nnz_w = nnz;
-
-  // ---- allocation 1: W copy, per-node arrays, scratch of the count phase
+size_t build_mem1_bytes(int64_t n, int64_t nnz) {
   size_t b1 = 0;
   b1 += Arena::round((n + 1) * 8) + Arena::round(nnz * 4) + Arena::round(nnz * 8);  // W
   b1 += Arena::round((n + 1) * 8) + Arena::round(n * 4);                            // t_rp, t_cnt
@@ -1103,8 +1472,67 @@ static int build_pre_a_impl(const me_csr* W, const me_opts* o, hipStream_t s, Gr
   b1 += 3 * Arena::round(n * 4) + 4 * Arena::round(n * 8) + 4 * Arena::round(n * 4);  // solver order
   b1 += 2 * Arena::round((n + 1) * 8);                                              // offsets
   b1 += Arena::round(sizeof(int) * 64);
+  return b1;
+}
+
+size_t build_mem2_bytes(int64_t nnz, int64_t nnz_t) {
+  return Arena::round(nnz_t * 4 + 4) + Arena::round((nnz + nnz_t) * 4 + 4) +
+         Arena::round((nnz + nnz_t) * 8 + 8) + 2 * Arena::round((nnz + nnz_t) * 4 + 4);
+}
+
+// Bitmaps of the two-hop rows with more than the LDS hash's candidates.
+static int64_t twohop_big_grid(int64_t nbig) { return std::min<int64_t>(nbig, 128); }
+size_t twohop_bitmap_bytes(int64_t n) {
+  return (size_t)twohop_big_grid(n) * ((n + 31) / 32) * 4;
+}
+
+size_t build_bytes_bound(int64_t n, int64_t nnz, int64_t nnz_t_max) {
+  return DevHeap::round(build_mem1_bytes(n, nnz)) + DevHeap::round(build_mem2_bytes(nnz, nnz_t_max)) +
+         DevHeap::round(order_scratch_bytes(n, nnz)) + DevHeap::round(order_args_bytes(1)) +
+         DevHeap::round(twohop_bitmap_bytes(n));
+}
+
+// Largest two-hop pattern W's degrees allow: T_i lies in the union over
+// k in N(i) of N(k) minus i, so nnz(T) <= sum_k d_k (d_k - 1), and
+// nnz(T) <= n (n - 1) - nnz(W).  Reads the row pointers (device) to the host.
+int two_hop_bound(const me_csr* W, hipStream_t s, int64_t* bound) {
+  *bound = 0;
+  const int64_t n = W->n, nnz = W->nnz;
+  if (n < 1 || nnz < 0 || !W->rowptr) return ME_ERR_INVALID_ARG;
+  std::vector<int64_t> rp((size_t)n + 1);
+  ME_TRY(hipMemcpyAsync(rp.data(), W->rowptr, (n + 1) * 8, hipMemcpyDeviceToHost, s));
+  ME_TRY(hipStreamSynchronize(s));
+  if (rp[0] != 0 || rp[n] != nnz) return ME_ERR_INVALID_ARG;
+  __int128 sum = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t d = rp[i + 1] - rp[i];
+    if (d < 0) return ME_ERR_INVALID_ARG;
+    if (d > 0) sum += (__int128)d * (d - 1);
+  }
+  const __int128 full = (__int128)n * (n - 1) - nnz;
+  __int128 b = sum < full ? sum : full;
+  if (b < 0) b = 0;
+  *bound = b > (__int128)INT64_MAX ? INT64_MAX : (int64_t)b;
+  return ME_OK;
+}
+
+// side != null: the graph's searches start on a side stream right after
+// validation and run beside the two-hop construction.
+static int build_pre_a_impl(const me_csr* W, const me_opts* o, DevHeap& heap, hipStream_t s,
+                            GraphOps* g, SideStream* side, OrderJob* job) {
+  const int64_t n = W->n, nnz = W->nnz;
+  if (n < 1 || nnz < 0 || !W->rowptr || (nnz > 0 && (!W->col || !W->val)))
+    return ME_ERR_INVALID_ARG;
+  if (n >= (int64_t)INT32_MAX) return ME_ERR_TOO_LARGE;
+  ME_TRY(hipGetDevice(&g->device));
+  g->n = n;
+  g->nnz_w = nnz;
+
+  g->in_region = heap.region();
+  // ---- allocation 1: W copy, per-node arrays, scratch of the count phase
+  const size_t b1 = build_mem1_bytes(n, nnz);
   void* mem1 = nullptr;
-  ME_TRY(hipMallocAsync(&mem1, b1, s));
+  ME_TRY_STATUS(heap.alloc(&mem1, b1, s));
   g->mem = mem1;
   g->mem_bytes = b1;
   Arena ar{(char*)mem1, b1, 0};
@@ -1164,10 +1592,10 @@ static int build_pre_a_impl(const me_csr* W, const me_opts* o, hipStream_t s, Gr
   ME_TRY_STATUS(read_scalar(dflags, &hflags, s));
   if (hflags) return flags_to_status(hflags);
 
-  ME_TRY_STATUS(order_alloc(g, s));
+  ME_TRY_STATUS(order_alloc(g, heap, s));
   if (side) {
     ME_TRY_STATUS(side->fork(s));
-    ME_TRY_STATUS(order_launch(&g, 1, side->s, args));
+    ME_TRY_STATUS(order_launch(&g, 1, heap, side->s, job));
   }
 
   // ---- two-hop pattern: count
@@ -1180,9 +1608,9 @@ static int build_pre_a_impl(const me_csr* W, const me_opts* o, hipStream_t s, Gr
   ME_TRY_STATUS(read_scalar(big_count, &nbig, s));
   uint32_t* bitmaps = nullptr;
   const int64_t nwords = (n + 31) / 32;
-  const int grid_big = nbig > 0 ? std::min(nbig, 128) : 0;
+  const int grid_big = nbig > 0 ? (int)twohop_big_grid(nbig) : 0;
   if (nbig > 0) {
-    ME_TRY(hipMallocAsync((void**)&bitmaps, (size_t)grid_big * nwords * 4, s));
+    ME_TRY_STATUS(heap.alloc((void**)&bitmaps, (size_t)grid_big * nwords * 4, s));
     ME_TRY(hipMemsetAsync(bitmaps, 0, (size_t)grid_big * nwords * 4, s));
     k_twohop_big<<<grid_big, 256, 0, s>>>(n, g->w_rp, g->w_col, 0, big_list, nbig, bitmaps,
                                           g->t_cnt, nullptr, nullptr);
@@ -1193,15 +1621,20 @@ static int build_pre_a_impl(const me_csr* W, const me_opts* o, hipStream_t s, Gr
   ME_TRY_STATUS(read_scalar(g->t_rp + n, &nnz_t, s));
   g->nnz_t = nnz_t;
   if (nnz + nnz_t >= (int64_t)INT32_MAX) {
-    if (bitmaps) (void)hipFreeAsync(bitmaps, s);
+    heap.release_later(bitmaps, s);
     return ME_ERR_TOO_LARGE;
   }
 
   // ---- allocation 2: T columns and the merged operator
-  size_t b2 = Arena::round(nnz_t * 4 + 4) + Arena::round((nnz + nnz_t) * 4 + 4) +
-              Arena::round((nnz + nnz_t) * 8 + 8) + 2 * Arena::round((nnz + nnz_t) * 4 + 4);
+  const size_t b2 = build_mem2_bytes(nnz, nnz_t);
   void* mem2 = nullptr;
-  ME_TRY(hipMallocAsync(&mem2, b2, s));
+  {
+    const int st2 = heap.alloc(&mem2, b2, s);
+    if (st2 < 0) {
+      heap.release_later(bitmaps, s);
+      return st2;
+    }
+  }
   g->mem2 = mem2;
   Arena ar2{(char*)mem2, b2, 0};
   g->t_col = ar2.take<int32_t>(nnz_t + 1);
@@ -1216,7 +1649,7 @@ static int build_pre_a_impl(const me_csr* W, const me_opts* o, hipStream_t s, Gr
   if (nbig > 0) {
     k_twohop_big<<<grid_big, 256, 0, s>>>(n, g->w_rp, g->w_col, 1, big_list, nbig, bitmaps,
                                           g->t_cnt, g->t_rp, g->t_col);
-    ME_TRY(hipFreeAsync(bitmaps, s));
+    heap.release_later(bitmaps, s);  // free at the call's next quiesce
   }
 
   // ---- connectivity of the two-hop graph
@@ -1312,12 +1745,12 @@ int build_post(GraphOps* g, double eps, int eps_iters, hipStream_t s) {
   return st;
 }
 
-int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g,
+int build_graph_ops(const me_csr* W, const me_opts* o, DevHeap& heap, hipStream_t s, GraphOps* g,
                     me_info* info) {
-  ME_TRY_STATUS(build_pre(W, o, s, g));
+  ME_TRY_STATUS(build_pre(W, o, heap, s, g));
   double eps = 0.0;
   int eps_iters = 0;
-  if (g->needs_eps) ME_TRY_STATUS(solve_eps(*g, o, s, &eps, &eps_iters));
+  if (g->needs_eps) ME_TRY_STATUS(solve_eps(*g, o, heap, s, &eps, &eps_iters));
   const int st = build_post(g, eps, eps_iters, s);
   if (info && st >= 0) {
     info->eps = g->eps;

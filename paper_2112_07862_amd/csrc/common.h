@@ -5,6 +5,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "membed.h"
@@ -65,6 +68,53 @@ struct Arena {
   static size_t round(size_t bytes) { return (bytes + 255) & ~size_t(255); }
 };
 
+constexpr size_t kHeapAlign = 256;
+
+// Device memory of one call (or of one server).  Without a region every
+// request is a stream-ordered hipMallocAsync / hipFreeAsync.  Over a
+// caller-owned region (the workspace arguments of the C ABI) requests are
+// carved first-fit in kHeapAlign units and no HIP allocation is made; a
+// released range is reused at once, so `release` is only for memory whose
+// work is complete (its stream synchronised), and `release_later` defers the
+// range to the next `quiesce`, which the owner calls once every stream that
+// used the heap is idle.  If the region holds at least the sum of every
+// request of a call (each rounded to kHeapAlign), first fit never fails,
+// whatever the order of releases: each request lands either in a hole below
+// the highest byte in use or right above it.  Thread-safe.
+class DevHeap {
+ public:
+  DevHeap() = default;
+  DevHeap(void* base, size_t bytes);
+  DevHeap(const DevHeap&) = delete;
+  DevHeap& operator=(const DevHeap&) = delete;
+  // ME_ERR_WORKSPACE when the region has no free range of `bytes`.
+  int alloc(void** p, size_t bytes, hipStream_t s);
+  template <typename T>
+  int alloc_n(T** p, size_t count, hipStream_t s) {
+    return alloc(reinterpret_cast<void**>(p), count * sizeof(T), s);
+  }
+  void release(void* p, hipStream_t s);
+  void release_later(void* p, hipStream_t s);
+  void quiesce();
+  bool region() const { return region_; }
+  bool owns(const void* p) const;
+  size_t high_water() const { return hw_; }
+  size_t capacity() const { return cap_; }
+  size_t largest_free();
+  static size_t round(size_t bytes) { return (bytes + kHeapAlign - 1) & ~(kHeapAlign - 1); }
+
+ private:
+  void put_back(size_t off, size_t len);
+  std::mutex mu_;
+  char* base_ = nullptr;
+  size_t cap_ = 0;
+  bool region_ = false;
+  std::map<size_t, size_t> free_;  // offset -> bytes
+  std::map<size_t, size_t> live_;  // offset -> bytes
+  std::vector<void*> later_;
+  size_t hw_ = 0;
+};
+
 // Device-side control block of one LOBPCG solve.  Written by the per-slot
 // finalize kernels, read by every iteration kernel (early exit once `done`)
 // and copied to the host at each convergence check.
@@ -106,6 +156,21 @@ struct OrderArgs {
   const int32_t* col;
   int32_t *level, *fa, *fb, *ev, *ei, *ef, *start, *perm;
   int32_t* maxlev;  // receives the deepest level
+  // > 0: the first component is already placed in perm[0, resume_off),
+  // its last level resume_last; the one-workgroup ordering continues with
+  // the further components
+  int64_t resume_off;
+  int32_t resume_last;
+};
+
+// Searches in flight between order_launch and order_finish.
+struct OrderJob {
+  void* args = nullptr;  // device argument array
+  std::thread th;        // drives the per-level launches of large graphs
+  int status = 0;
+  ~OrderJob() {
+    if (th.joinable()) th.join();
+  }
 };
 
 // Packed graph operators (device pointers into one allocation).
@@ -168,20 +233,33 @@ struct GraphOps {
   void* mem = nullptr;   // per-node arrays, W copy
   void* mem2 = nullptr;  // T columns and the merged operator
   size_t mem_bytes = 0;
+  bool in_region = false;  // memory carved from a caller's workspace (not freed here)
   int device = 0;
 };
 
 // ---- launchers: build.hip -------------------------------------------------
-int build_graph_ops(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g, me_info* info);
+int build_graph_ops(const me_csr* W, const me_opts* o, DevHeap& heap, hipStream_t s, GraphOps* g,
+                    me_info* info);
+// Device bytes of the build's allocations (see build_bytes_bound).
+size_t build_mem1_bytes(int64_t n, int64_t nnz);
+size_t build_mem2_bytes(int64_t nnz, int64_t nnz_t);
+size_t order_scratch_bytes(int64_t n, int64_t nnz);
+size_t order_args_bytes(int G);
+size_t twohop_bitmap_bytes(int64_t n);
+// Every allocation of build_pre for a graph of n nodes, nnz entries and at
+// most nnz_t_max two-hop entries (each rounded to the heap's unit).
+size_t build_bytes_bound(int64_t n, int64_t nnz, int64_t nnz_t_max);
+// Upper bound of nnz(T) from W's degrees (reads W's row pointers).
+int two_hop_bound(const me_csr* W, hipStream_t s, int64_t* bound);
 // option ranges of me_opts (shared by every entry point that takes them)
 bool opts_valid(const me_opts& o);
 // build_pre = build_pre_a (validation, T, Q_ii, connectivity; the order's
 // scratch) + the locality order + build_pre_b (operator packed in that
 // order).  Batches run the searches of all graphs in one launch.
-int build_pre(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g);
-int build_pre_a(const me_csr* W, const me_opts* o, hipStream_t s, GraphOps* g);
-int order_launch(GraphOps* const* gs, int G, hipStream_t s, void** args_mem);
-int order_finish(GraphOps* const* gs, int G, hipStream_t s, void* args_mem);
+int build_pre(const me_csr* W, const me_opts* o, DevHeap& heap, hipStream_t s, GraphOps* g);
+int build_pre_a(const me_csr* W, const me_opts* o, DevHeap& heap, hipStream_t s, GraphOps* g);
+int order_launch(GraphOps* const* gs, int G, DevHeap& heap, hipStream_t s, OrderJob* job);
+int order_finish(GraphOps* const* gs, int G, DevHeap& heap, hipStream_t s, OrderJob* job);
 int build_pre_b(GraphOps* g, hipStream_t s);
 int build_post(GraphOps* g, double eps, int eps_iters, hipStream_t s);
 
@@ -228,13 +306,23 @@ void ktimer_drop_after(int phase, int last_real);
 void ktimer_collect();
 
 // ---- lobpcg.hip -------------------------------------------------------------
-int solve_eps(GraphOps& g, const me_opts* o, hipStream_t s, double* eps, int* iters);
+int solve_eps(GraphOps& g, const me_opts* o, DevHeap& heap, hipStream_t s, double* eps,
+              int* iters);
+// Device bytes the eps solve of a graph with n nodes allocates.
+size_t eps_solve_bytes(int64_t n);
 int block_width(int K);
-size_t embed_workspace_bytes(const GraphOps& g, int K, const me_opts* o);
+size_t embed_workspace_bytes(int64_t n, int K, const me_opts* o);
 int embed(const GraphOps& g, int K, double tol, const me_opts* o, const double* x0, void* ws,
           size_t ws_bytes, double* X, double* lambda, me_info* info, hipStream_t s);
-int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opts* o,
-                double* const* Xs, double* const* lams, me_info* infos, hipStream_t s);
+// Footprint of one server request (build bound and both solver slots).
+size_t request_bytes(int64_t n, int64_t nnz, int64_t nnz_t_max, int K);
+size_t dense_request_bytes(int64_t n);
+// Workspace bound of embed_batch (reads every graph's row pointers).
+int batch_workspace_bytes(int G, const me_csr* Ws, const int* Ks, const me_opts* o,
+                          hipStream_t s, size_t* bytes);
+int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opts* o, void* ws,
+                size_t ws_bytes, double* const* Xs, double* const* lams, me_info* infos,
+                hipStream_t s);
 // Releases the device memory of a GraphOps (partially built ones too).
 void free_graph_ops(GraphOps& g);
 

@@ -190,11 +190,26 @@ class Engine {
   // graph), which alone may take FP16 Chebyshev iterates; the engine's
   // capacity is not used for that, so that a graph's arithmetic never
   // depends on which other graphs share a batch or a server
-  Engine(hipStream_t s, const me_opts& o, int capacity, bool timed, bool solo = false);
+  // heap: device memory of the engine (null: stream-ordered HIP
+  // allocations).  Over a caller region the engine also needs tile_area
+  // bytes twice (work lists of the active slots and of the slots being
+  // started or certified): at least tile_area_bytes of the summed
+  // tile_bytes of the slots that can be active at once.
+  Engine(hipStream_t s, const me_opts& o, int capacity, bool timed, bool solo = false,
+         DevHeap* heap = nullptr, size_t tile_area = 0);
   ~Engine();
   int init();
   // Workspace of one slot (device bytes).
   static size_t slot_bytes(int64_t n, int kb);
+  // Slot table, control blocks and Chebyshev coefficients of `capacity` slots.
+  static size_t table_bytes(int capacity);
+  // Work-list entries of one slot (device bytes, before rounding).
+  static size_t tile_bytes(int64_t n, int kb);
+  // One work-list area for slots whose tile_bytes sum to `sum`.
+  static size_t tile_area_bytes(size_t sum);
+  // Every allocation of an engine of these slots that runs to completion
+  // (tables, slots, both work-list areas), each rounded to the heap's unit.
+  static size_t run_bytes(const std::vector<std::pair<int64_t, int>>& slots);
   // Registers a problem (ws: caller memory of slot_bytes, or null to let the
   // engine allocate); it starts at the next run()/step().  id >= 0 on success.
   int add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id);
@@ -225,14 +240,15 @@ class Engine {
     SlotSpec sp;
     int reentries = 0;
   };
-  int build_set(const std::vector<int>& ids, int kb, TileSet* ts);
+  // area: 0 for the active slots' lists, 1 for start and certificate passes
+  int build_set(const std::vector<int>& ids, int kb, TileSet* ts, int area);
   void free_set(TileSet* ts);
   int upload_slot(int id);
   void start_pass(const TileSet& ts);
   void rr_x(const TileSet& ts, int final_pass);
   void iteration(const TileSet& ts);
   int read_ctrl();
-  int sets_for(const std::vector<int>& ids, std::vector<TileSet>* sets);
+  int sets_for(const std::vector<int>& ids, std::vector<TileSet>* sets, int area);
   void free_sets(std::vector<TileSet>* sets);
   int certify(const std::vector<int>& ids, std::vector<int>* finished);
 
@@ -245,10 +261,20 @@ class Engine {
   std::vector<SlotHost> sh_;
   std::vector<SlotResult> res_;
   std::vector<SlotDev> hdev_;
+  DevHeap own_heap_;   // stream-ordered HIP allocations when no heap is given
+  DevHeap* heap_;
+  size_t tile_area_ = 0;
+  void* tables_ = nullptr;
+  void* tile_mem_ = nullptr;
+  struct Area {
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+  } areas_[2];
   SlotDev* d_slots_ = nullptr;
   Ctrl* d_ctrl_ = nullptr;
   ChebCoef* d_cheb_ = nullptr;
-  Ctrl* h_ctrl_ = nullptr;  // pinned mirror
+  Ctrl* h_ctrl_ = nullptr;  // host mirror (pinned in HIP mode, pageable over a region)
+  std::vector<Ctrl> h_ctrl_pageable_;
   std::vector<int> active_;
   std::vector<TileSet> sets_;  // work lists of active_, one per block width
   // convergence history per slot (largest required rho at the last check)

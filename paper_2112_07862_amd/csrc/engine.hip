@@ -60,8 +60,37 @@ size_t Engine::slot_bytes(int64_t n, int kb) {
   return b;
 }
 
-Engine::Engine(hipStream_t s, const me_opts& o, int capacity, bool timed, bool solo)
-    : s_(s), o_(o), cap_(capacity), timed_(timed), solo_(solo) {
+size_t Engine::table_bytes(int capacity) {
+  const size_t c = (size_t)std::max(capacity, 1);
+  return Arena::round(sizeof(SlotDev) * c) + Arena::round(sizeof(Ctrl) * c) +
+         Arena::round(sizeof(ChebCoef) * c);
+}
+
+size_t Engine::tile_bytes(int64_t n, int kb) {
+  const int64_t rb64 = kBlock / lpr64(kb), rb32 = kBlock / lpr32(kb);
+  return 4 + sizeof(Tile) * (size_t)(ceil_div(n, kGatherRows) + ceil_div(n, rb64) +
+                                     ceil_div(n, rb32) + partial_tiles(n));
+}
+
+size_t Engine::tile_area_bytes(size_t sum) {
+  // each of at most three lists (one per block width) rounds five sections
+  // and its start to the heap's unit
+  return DevHeap::round(sum + 3 * 6 * kHeapAlign);
+}
+
+size_t Engine::run_bytes(const std::vector<std::pair<int64_t, int>>& slots) {
+  size_t tiles = 0, b = DevHeap::round(table_bytes((int)slots.size()));
+  for (const auto& s : slots) {
+    b += DevHeap::round(slot_bytes(s.first, s.second));
+    tiles += tile_bytes(s.first, s.second);
+  }
+  return b + DevHeap::round(2 * tile_area_bytes(tiles));
+}
+
+Engine::Engine(hipStream_t s, const me_opts& o, int capacity, bool timed, bool solo,
+               DevHeap* heap, size_t tile_area)
+    : s_(s), o_(o), cap_(capacity), timed_(timed), solo_(solo),
+      heap_(heap ? heap : &own_heap_), tile_area_(tile_area) {
   cheb_ = o.precond == ME_PRECOND_CHEBYSHEV;
   cheb32_ = cheb_ && o.precision == ME_MIXED;
 }
@@ -70,10 +99,27 @@ int Engine::init() {
   sh_.assign(cap_, SlotHost());
   res_.assign(cap_, SlotResult());
   hdev_.assign(cap_, SlotDev());
-  ME_TRY(hipMallocAsync((void**)&d_slots_, sizeof(SlotDev) * cap_, s_));
-  ME_TRY(hipMallocAsync((void**)&d_ctrl_, sizeof(Ctrl) * cap_, s_));
-  ME_TRY(hipMallocAsync((void**)&d_cheb_, sizeof(ChebCoef) * cap_, s_));
-  ME_TRY(hipHostMalloc((void**)&h_ctrl_, sizeof(Ctrl) * cap_, hipHostMallocDefault));
+  const size_t tb = table_bytes(cap_);
+  ME_TRY_STATUS(heap_->alloc(&tables_, tb, s_));
+  Arena a{(char*)tables_, tb, 0};
+  d_slots_ = a.take<SlotDev>(cap_);
+  d_ctrl_ = a.take<Ctrl>(cap_);
+  d_cheb_ = a.take<ChebCoef>(cap_);
+  if (heap_->region()) {
+    // no allocation of any kind over a caller region: a pageable mirror and
+    // both work-list areas carved from the region
+    h_ctrl_pageable_.assign(cap_, Ctrl{});
+    h_ctrl_ = h_ctrl_pageable_.data();
+    if (tile_area_ == 0) return ME_ERR_WORKSPACE;
+    ME_TRY_STATUS(heap_->alloc(&tile_mem_, 2 * tile_area_, s_));
+    for (int q = 0; q < 2; ++q) {
+      areas_[q].base = (char*)tile_mem_ + q * tile_area_;
+      areas_[q].cap = tile_area_;
+      areas_[q].used = 0;
+    }
+  } else {
+    ME_TRY(hipHostMalloc((void**)&h_ctrl_, sizeof(Ctrl) * cap_, hipHostMallocDefault));
+  }
   std::memset(h_ctrl_, 0, sizeof(Ctrl) * cap_);
   return ME_OK;
 }
@@ -82,12 +128,11 @@ Engine::~Engine() {
   (void)hipStreamSynchronize(s_);
   free_sets(&sets_);
   for (auto& h : sh_)
-    if (h.used && h.own_ws && h.ws) (void)hipFreeAsync(h.ws, s_);
-  if (d_slots_) (void)hipFreeAsync(d_slots_, s_);
-  if (d_ctrl_) (void)hipFreeAsync(d_ctrl_, s_);
-  if (d_cheb_) (void)hipFreeAsync(d_cheb_, s_);
+    if (h.used && h.own_ws && h.ws) heap_->release(h.ws, s_);
+  heap_->release(tables_, s_);
+  heap_->release(tile_mem_, s_);
   (void)hipStreamSynchronize(s_);
-  if (h_ctrl_) (void)hipHostFree(h_ctrl_);
+  if (h_ctrl_ && !heap_->region()) (void)hipHostFree(h_ctrl_);
 }
 
 bool Engine::idle() const {
@@ -116,7 +161,7 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
   const size_t need = slot_bytes(n, kb);
   bool own = false;
   if (!ws) {
-    ME_TRY(hipMallocAsync(&ws, need, s_));
+    ME_TRY_STATUS(heap_->alloc(&ws, need, s_));
     own = true;
   } else if (ws_bytes < need) {
     return ME_ERR_WORKSPACE;
@@ -222,13 +267,13 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
 void Engine::release(int id) {
   if (id < 0 || id >= cap_ || !sh_[id].used) return;
   SlotHost& h = sh_[id];
-  if (h.own_ws && h.ws) (void)hipFreeAsync(h.ws, s_);
+  if (h.own_ws && h.ws) heap_->release(h.ws, s_);  // the slot's work is complete
   bytes_in_use_ -= h.ws_bytes;
   h = SlotHost();
 }
 
 // Work lists of the slots `ids` (all of block width kb).
-int Engine::build_set(const std::vector<int>& ids, int kb, TileSet* ts) {
+int Engine::build_set(const std::vector<int>& ids, int kb, TileSet* ts, int area) {
   ts->kb = kb;
   ts->nslots = (int)ids.size();
   ts->ids = ids;
@@ -264,7 +309,15 @@ int Engine::build_set(const std::vector<int>& ids, int kb, TileSet* ts) {
   const size_t o_e64 = put(e64.data(), e64.size() * sizeof(Tile));
   const size_t o_e32 = put(e32.data(), e32.size() * sizeof(Tile));
   const size_t o_r = put(red.data(), red.size() * sizeof(Tile));
-  ME_TRY(hipMallocAsync(&ts->mem, off > 0 ? off : 256, s_));
+  const size_t dev_bytes = DevHeap::round(off > 0 ? off : 1);
+  if (heap_->region()) {
+    Area& ar = areas_[area];
+    if (ar.used + dev_bytes > ar.cap) return ME_ERR_WORKSPACE;
+    ts->mem = ar.base + ar.used;
+    ar.used += dev_bytes;
+  } else {
+    ME_TRY_STATUS(heap_->alloc(&ts->mem, dev_bytes, s_));
+  }
   ME_TRY(hipMemcpyAsync(ts->mem, ts->host.data(), off, hipMemcpyHostToDevice, s_));
   char* base = (char*)ts->mem;
   ts->slots = (const int32_t*)(base + o_sl);
@@ -275,19 +328,21 @@ int Engine::build_set(const std::vector<int>& ids, int kb, TileSet* ts) {
   return ME_OK;
 }
 
+// Callers free a set only once the stream has finished the work that used it.
 void Engine::free_set(TileSet* ts) {
-  if (ts->mem) (void)hipFreeAsync(ts->mem, s_);
+  if (ts->mem && !heap_->region()) heap_->release(ts->mem, s_);
   *ts = TileSet();
 }
 
-int Engine::sets_for(const std::vector<int>& ids, std::vector<TileSet>* sets) {
+int Engine::sets_for(const std::vector<int>& ids, std::vector<TileSet>* sets, int area) {
+  areas_[area].used = 0;  // the area's previous lists are freed
   for (int kb : {4, 8, 16}) {
     std::vector<int> sub;
     for (int id : ids)
       if (sh_[id].sp.kb == kb) sub.push_back(id);
     if (sub.empty()) continue;
     sets->emplace_back();
-    ME_TRY_STATUS(build_set(sub, kb, &sets->back()));
+    ME_TRY_STATUS(build_set(sub, kb, &sets->back(), area));
   }
   return ME_OK;
 }
@@ -423,7 +478,7 @@ void Engine::iteration(const TileSet& ts) {
 
 int Engine::certify(const std::vector<int>& ids, std::vector<int>* finished) {
   std::vector<TileSet> cs;
-  ME_TRY_STATUS(sets_for(ids, &cs));
+  ME_TRY_STATUS(sets_for(ids, &cs, 1));
   for (auto& ts : cs) {
     rr_x(ts, 1);
     sl_resid(d_slots_, ts, -1, 0, 1, s_);
@@ -457,7 +512,7 @@ int Engine::certify(const std::vector<int>& ids, std::vector<int>* finished) {
     }
   }
   if (!fin.empty()) {
-    ME_TRY_STATUS(sets_for(fin, &cs));
+    ME_TRY_STATUS(sets_for(fin, &cs, 1));
     for (auto& ts : cs) {
       const int u[1] = {BX};
       sl_gram(d_slots_, ts, 1, u, 1, u, 0, nullptr, 1, 1, s_);
@@ -474,7 +529,7 @@ int Engine::certify(const std::vector<int>& ids, std::vector<int>* finished) {
     }
   }
   if (!again.empty()) {
-    ME_TRY_STATUS(sets_for(again, &cs));
+    ME_TRY_STATUS(sets_for(again, &cs, 1));
     for (auto& ts : cs) {
       sl_reenter(d_slots_, ts, s_);
       sl_zero(d_slots_, ts, BP, s_);
@@ -528,7 +583,7 @@ int Engine::begin_round() {
     if (sh_[id].used && !sh_[id].started) fresh.push_back(id);
   if (!fresh.empty()) {
     std::vector<TileSet> cs;
-    ME_TRY_STATUS(sets_for(fresh, &cs));
+    ME_TRY_STATUS(sets_for(fresh, &cs, 1));
     for (auto& ts : cs) start_pass(ts);
     ME_TRY(hipStreamSynchronize(s_));
     free_sets(&cs);
@@ -543,7 +598,7 @@ int Engine::begin_round() {
     ME_TRY(hipStreamSynchronize(s_));
     free_sets(&sets_);
     std::sort(active_.begin(), active_.end());
-    ME_TRY_STATUS(sets_for(active_, &sets_));
+    ME_TRY_STATUS(sets_for(active_, &sets_, 0));
     sets_dirty_ = false;
   }
   iter0_.resize(active_.size());

@@ -94,25 +94,34 @@ SlotSpec embed_slot_spec(const GraphOps& g, int K, double tol, const me_opts* o,
   return sp;
 }
 
-int dense_eps_solve(const GraphOps& g, hipStream_t s, double* eps) {
+static size_t dense_eps_bytes(int64_t n) { return (3 * (size_t)n * n + n) * 8; }
+
+int dense_eps_solve(const GraphOps& g, DevHeap& heap, hipStream_t s, double* eps) {
   const int64_t n = g.n;
   double* buf = nullptr;
   const size_t nn = (size_t)n * n;
-  ME_TRY(hipMallocAsync((void**)&buf, (3 * nn + n) * 8, s));
+  ME_TRY_STATUS(heap.alloc((void**)&buf, dense_eps_bytes(n), s));
   launch_dense_ops(g, 1, buf, buf + nn, s);
   launch_dense_geneig((int)n, buf, buf + nn, buf + 2 * nn, buf + 3 * nn, s);
   double lam2 = 0.0;
-  ME_TRY(hipMemcpyAsync(&lam2, buf + 3 * nn + 1, 8, hipMemcpyDeviceToHost, s));
-  ME_TRY(hipStreamSynchronize(s));
-  ME_TRY(hipFreeAsync(buf, s));
+  const hipError_t e1 = hipMemcpyAsync(&lam2, buf + 3 * nn + 1, 8, hipMemcpyDeviceToHost, s);
+  const hipError_t e2 = hipStreamSynchronize(s);
+  heap.release(buf, s);  // synchronised
+  if (e1 != hipSuccess || e2 != hipSuccess) return ME_ERR_HIP;
   *eps = lam2;
   return ME_OK;
 }
 
-int solve_eps(GraphOps& g, const me_opts* o, hipStream_t s, double* eps, int* iters) {
+size_t eps_solve_bytes(int64_t n) {
+  if (n <= kDenseMaxN) return DevHeap::round(dense_eps_bytes(n));
+  return Engine::run_bytes({{n, 4}});
+}
+
+int solve_eps(GraphOps& g, const me_opts* o, DevHeap& heap, hipStream_t s, double* eps,
+              int* iters) {
   *iters = 0;
-  if (g.n <= kDenseMaxN) return dense_eps_solve(g, s, eps);
-  Engine e(s, *o, 1, false);
+  if (g.n <= kDenseMaxN) return dense_eps_solve(g, heap, s, eps);
+  Engine e(s, *o, 1, false, false, &heap, Engine::tile_area_bytes(Engine::tile_bytes(g.n, 4)));
   ME_TRY_STATUS(e.init());
   int id = -1;
   ME_TRY_STATUS(e.add(eps_slot_spec(g, o), nullptr, 0, &id));
@@ -128,10 +137,18 @@ int solve_eps(GraphOps& g, const me_opts* o, hipStream_t s, double* eps, int* it
 // Embedding
 // ---------------------------------------------------------------------------
 
-size_t embed_workspace_bytes(const GraphOps& g, int K, const me_opts* o) {
+static size_t dense_embed_bytes(int64_t n) {
+  return Arena::round((3 * (size_t)n * n + n + 64 * 16 * 2) * 8);
+}
+
+size_t dense_request_bytes(int64_t n) { return dense_embed_bytes(n); }
+
+// Everything one embedding solve allocates: its slot, the engine's tables
+// and work-list areas (or the dense solve's buffer).
+size_t embed_workspace_bytes(int64_t n, int K, const me_opts* o) {
   (void)o;
-  if (g.n <= kDenseMaxN) return Arena::round((3 * (size_t)g.n * g.n + g.n + 64 * 16 * 2) * 8);
-  return Engine::slot_bytes(g.n, block_width(K));
+  if (n <= kDenseMaxN) return DevHeap::round(dense_embed_bytes(n)) + kHeapAlign;
+  return Engine::run_bytes({{n, block_width(K)}}) + kHeapAlign;
 }
 
 int check_k_range(const GraphOps& g, int K) {
@@ -172,26 +189,28 @@ int embed(const GraphOps& g, int K, double tol, const me_opts* o, const double* 
   const auto t0 = std::chrono::steady_clock::now();
   ME_TRY_STATUS(check_k_range(g, K));
   if (!X || !lambda || !(tol > 0.0)) return ME_ERR_INVALID_ARG;
-  const size_t need_bytes = embed_workspace_bytes(g, K, o);
-  if (ws && ws_bytes < need_bytes) return ME_ERR_WORKSPACE;
+  if (ws && ws_bytes < embed_workspace_bytes(g.n, K, o)) return ME_ERR_WORKSPACE;
+  // with a workspace every device allocation of the solve is carved from it
+  DevHeap region(ws, ws_bytes);
+  DevHeap hip;
+  DevHeap& heap = ws ? region : hip;
   int st = ME_OK, iters = 0, kb = K;
   double worst = 0.0, orth = 0.0;
   if (g.n <= kDenseMaxN) {
-    bool own = false;
-    if (!ws) {
-      ME_TRY(hipMallocAsync(&ws, need_bytes, s));
-      own = true;
-    }
-    dense_embed_solve(g, K, (double*)ws, X, lambda, s);
-    if (own) ME_TRY(hipFreeAsync(ws, s));
+    double* buf = nullptr;
+    ME_TRY_STATUS(heap.alloc((void**)&buf, dense_embed_bytes(g.n), s));
+    dense_embed_solve(g, K, buf, X, lambda, s);
+    heap.release_later(buf, s);
     ME_TRY(hipStreamSynchronize(s));
+    heap.quiesce();
     kb = (int)g.n;
   } else {
     kb = block_width(K);
-    Engine e(s, *o, 1, true, /*solo=*/true);
+    Engine e(s, *o, 1, true, /*solo=*/true, &heap,
+             Engine::tile_area_bytes(Engine::tile_bytes(g.n, kb)));
     ME_TRY_STATUS(e.init());
     int id = -1;
-    ME_TRY_STATUS(e.add(embed_slot_spec(g, K, tol, o, x0, X, lambda), ws, ws_bytes, &id));
+    ME_TRY_STATUS(e.add(embed_slot_spec(g, K, tol, o, x0, X, lambda), nullptr, 0, &id));
     ME_TRY_STATUS(e.run());
     const SlotResult& r = e.result(id);
     st = r.status;
@@ -212,9 +231,52 @@ int embed(const GraphOps& g, int K, double tol, const me_opts* o, const double* 
 // rest of each build, then all embedding solves in one engine.
 // ---------------------------------------------------------------------------
 
-int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opts* o,
-                double* const* Xs, double* const* lams, me_info* infos, hipStream_t s) {
+// Workspace of a batch: the sum of every allocation the batch makes (each
+// graph's build with T at its degree bound, both engines with all slots,
+// the dense solves and the searches' arguments), so that first fit over the
+// region never fails whatever the order in which graphs finish.
+int batch_workspace_bytes(int G, const me_csr* Ws, const int* Ks, const me_opts* o,
+                          hipStream_t s, size_t* bytes) {
+  (void)o;
+  *bytes = 0;
+  size_t total = kHeapAlign + DevHeap::round(order_args_bytes(G));
+  std::vector<std::pair<int64_t, int>> eps_slots, emb_slots;
+  for (int i = 0; i < G; ++i) {
+    int64_t tb = 0;
+    ME_TRY_STATUS(two_hop_bound(&Ws[i], s, &tb));
+    const int64_t n = Ws[i].n;
+    total += build_bytes_bound(n, Ws[i].nnz, tb);
+    if (n <= kDenseMaxN) {
+      total += DevHeap::round(dense_eps_bytes(n)) + DevHeap::round(dense_embed_bytes(n));
+    } else {
+      eps_slots.push_back({n, 4});
+      emb_slots.push_back({n, block_width(std::max(1, std::min(Ks[i], kMaxBlockCols)))});
+    }
+  }
+  total += Engine::run_bytes(eps_slots) + Engine::run_bytes(emb_slots);
+  *bytes = total;
+  return ME_OK;
+}
+
+static size_t sum_tiles(const std::vector<std::pair<int64_t, int>>& slots) {
+  size_t t = 0;
+  for (const auto& x : slots) t += Engine::tile_bytes(x.first, x.second);
+  return Engine::tile_area_bytes(t);
+}
+
+int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opts* o, void* ws,
+                size_t ws_bytes, double* const* Xs, double* const* lams, me_info* infos,
+                hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
+  if (ws) {
+    size_t need = 0;
+    ME_TRY_STATUS(batch_workspace_bytes(G, Ws, Ks, o, s, &need));
+    if (ws_bytes < need) return ME_ERR_WORKSPACE;
+  }
+  // with a workspace every device allocation of the batch is carved from it
+  DevHeap region(ws, ws_bytes);
+  DevHeap hip;
+  DevHeap& heap = ws ? region : hip;
   std::vector<GraphOps> gs(G);
   struct Release {
     std::vector<GraphOps>& v;
@@ -225,39 +287,41 @@ int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opt
   std::vector<int> st(G, ME_OK);
   std::vector<double> ms_build(G, 0.0);
   ME_TRY(hipStreamSynchronize(s));  // the caller's graphs are in place
-  for_each_graph(G, [&](int i, hipStream_t ws) {
+  for_each_graph(G, [&](int i, hipStream_t ws_i) {
     if (!Xs[i] || !lams[i]) st[i] = ME_ERR_INVALID_ARG;
     else if (Ks[i] < 1 || Ks[i] > kMaxBlockCols) st[i] = ME_ERR_K_RANGE;
     if (st[i] < 0) return;
-    st[i] = build_pre_a(&Ws[i], o, ws, &gs[i]);
+    st[i] = build_pre_a(&Ws[i], o, heap, ws_i, &gs[i]);
     if (st[i] >= 0) st[i] = check_k_range(gs[i], Ks[i]);
   });
+  heap.quiesce();  // every build stream is idle
   // the breadth-first searches of every graph in one launch, then each
   // graph's operator in its order
   {
     std::vector<GraphOps*> ok;
     for (int i = 0; i < G; ++i)
       if (st[i] >= 0) ok.push_back(&gs[i]);
-    void* args = nullptr;
-    ME_TRY_STATUS(order_launch(ok.data(), (int)ok.size(), s, &args));
-    ME_TRY_STATUS(order_finish(ok.data(), (int)ok.size(), s, args));
-    for_each_graph(G, [&](int i, hipStream_t ws) {
-      if (st[i] >= 0) st[i] = build_pre_b(&gs[i], ws);
+    OrderJob job;
+    ME_TRY_STATUS(order_launch(ok.data(), (int)ok.size(), heap, s, &job));
+    ME_TRY_STATUS(order_finish(ok.data(), (int)ok.size(), heap, s, &job));
+    for_each_graph(G, [&](int i, hipStream_t ws_i) {
+      if (st[i] >= 0) st[i] = build_pre_b(&gs[i], ws_i);
     });
   }
   // eps
   std::vector<double> eps(G, 0.0);
   std::vector<int> eps_it(G, 0);
   {
-    int cnt = 0;
-    for (int i = 0; i < G; ++i) cnt += st[i] >= 0 && gs[i].needs_eps && gs[i].n > kDenseMaxN;
-    Engine e(s, *o, std::max(cnt, 1), false);
+    std::vector<std::pair<int64_t, int>> slots;
+    for (int i = 0; i < G; ++i)
+      if (st[i] >= 0 && gs[i].needs_eps && gs[i].n > kDenseMaxN) slots.push_back({gs[i].n, 4});
+    Engine e(s, *o, std::max((int)slots.size(), 1), false, false, &heap, sum_tiles(slots));
     ME_TRY_STATUS(e.init());
     std::vector<int> id(G, -1);
     for (int i = 0; i < G; ++i) {
       if (st[i] < 0 || !gs[i].needs_eps) continue;
       if (gs[i].n <= kDenseMaxN) {
-        st[i] = dense_eps_solve(gs[i], s, &eps[i]);
+        st[i] = dense_eps_solve(gs[i], heap, s, &eps[i]);
         continue;
       }
       const int a = e.add(eps_slot_spec(gs[i], o), nullptr, 0, &id[i]);
@@ -272,31 +336,36 @@ int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opt
       else eps[i] = r.lam[0];
     }
   }
-  for_each_graph(G, [&](int i, hipStream_t ws) {
+  for_each_graph(G, [&](int i, hipStream_t ws_i) {
     if (st[i] < 0) return;
-    st[i] = build_post(&gs[i], eps[i], eps_it[i], ws);
-    (void)hipStreamSynchronize(ws);
+    st[i] = build_post(&gs[i], eps[i], eps_it[i], ws_i);
+    (void)hipStreamSynchronize(ws_i);
     ms_build[i] =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   });
   // embedding
   const auto t1 = std::chrono::steady_clock::now();
   {
-    int cnt = 0;
-    for (int i = 0; i < G; ++i) cnt += st[i] >= 0 && gs[i].n > kDenseMaxN;
+    std::vector<std::pair<int64_t, int>> slots;
+    for (int i = 0; i < G; ++i)
+      if (st[i] >= 0 && gs[i].n > kDenseMaxN) slots.push_back({gs[i].n, block_width(Ks[i])});
     // FP16 iterates only for a batch of one input graph (decided by G, not by
     // how many graphs reach the engine)
-    Engine e(s, *o, std::max(cnt, 1), false, /*solo=*/G == 1);
+    Engine e(s, *o, std::max((int)slots.size(), 1), false, /*solo=*/G == 1, &heap,
+             sum_tiles(slots));
     ME_TRY_STATUS(e.init());
     std::vector<int> id(G, -1);
     for (int i = 0; i < G; ++i) {
       if (st[i] < 0) continue;
       if (gs[i].n <= kDenseMaxN) {
         double* buf = nullptr;
-        const size_t bytes = embed_workspace_bytes(gs[i], Ks[i], o);
-        ME_TRY(hipMallocAsync((void**)&buf, bytes, s));
+        const int a = heap.alloc((void**)&buf, dense_embed_bytes(gs[i].n), s);
+        if (a < 0) {
+          st[i] = a;
+          continue;
+        }
         dense_embed_solve(gs[i], Ks[i], buf, Xs[i], lams[i], s);
-        ME_TRY(hipFreeAsync(buf, s));
+        heap.release_later(buf, s);
         continue;
       }
       const int a =
@@ -328,6 +397,7 @@ int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opt
     }
   }
   ME_TRY(hipStreamSynchronize(s));
+  heap.quiesce();
   int worst_st = ME_OK;
   for (int i = 0; i < G; ++i) {
     if (st[i] < 0) return st[i];

@@ -22,14 +22,16 @@ SlotSpec eps_slot_spec(const GraphOps& g, const me_opts* o);
 SlotSpec embed_slot_spec(const GraphOps& g, int K, double tol, const me_opts* o, const double* x0,
                          double* X, double* lambda);
 int check_k_range(const GraphOps& g, int K);
-int dense_eps_solve(const GraphOps& g, hipStream_t s, double* eps);
+int dense_eps_solve(const GraphOps& g, DevHeap& heap, hipStream_t s, double* eps);
 int dense_embed_solve(const GraphOps& g, int K, double* buf, double* X, double* lambda,
                       hipStream_t s);
-size_t embed_workspace_bytes(const GraphOps& g, int K, const me_opts* o);
+size_t dense_request_bytes(int64_t n);
 
 void free_graph_ops_async(GraphOps& g, hipStream_t s) {
-  if (g.mem) (void)hipFreeAsync(g.mem, s);
-  if (g.mem2) (void)hipFreeAsync(g.mem2, s);
+  if (!g.in_region) {
+    if (g.mem) (void)hipFreeAsync(g.mem, s);
+    if (g.mem2) (void)hipFreeAsync(g.mem2, s);
+  }
   g.mem = g.mem2 = nullptr;
 }
 
@@ -43,7 +45,13 @@ struct Request {
   double* X = nullptr;
   double* lambda = nullptr;
   GraphOps g;
-  size_t est = 0;   // footprint charged against the budget
+  size_t est = 0;   // footprint charged against the budget (an upper bound)
+  size_t tiles = 0; // work-list bytes charged against the engine's area
+  // over a caller region: the request's block (est bytes) and the heap that
+  // carves its operators, scratch and solver slots
+  void* block = nullptr;
+  DevHeap* sub = nullptr;
+  void* slot_ws = nullptr;
   int slot = -1;
   int phase = 0;  // 0 queued / building, 1 eps slot, 2 embedding slot
   int status = ME_OK;
@@ -52,10 +60,20 @@ struct Request {
   Clock::time_point t_admit, t_ops;
 };
 
+// Work-list area of a server over a caller region: a 128th of the region
+// (at least 256 KiB); each admitted request is charged its own entries.
+static size_t server_tile_sum(const me_server_opts& so) {
+  if (!so.workspace) return 0;
+  return std::max<size_t>(so.mem_budget / 128, (size_t)256 << 10);
+}
+
 class Server {
  public:
   Server(const me_server_opts& so, hipStream_t s)
-      : so_(so), main_(s), eng_(s, so.opts, std::max(1, so.max_active), false) {}
+      : so_(so), main_(s), region_(so.workspace, so.workspace ? so.mem_budget : 0),
+        heap_(so.workspace ? &region_ : &hip_), tile_cap_(server_tile_sum(so)),
+        eng_(s, so.opts, std::max(1, so.max_active), false, false, heap_,
+             so.workspace ? Engine::tile_area_bytes(server_tile_sum(so)) : 0) {}
   ~Server();
   int init();
   int submit(const me_csr* W, int K, double tol, double* X, double* lambda, int64_t* ticket);
@@ -63,14 +81,19 @@ class Server {
   int poll(int64_t* tickets, me_info* infos, int max, int* count);
 
  private:
-  size_t estimate(const me_csr& W, int K) const;
+  int estimate(Request* r);
   void finish(Request* r, int st);
+  void drop(Request* r);
   int admit();
   int add_slots();
 
   me_server_opts so_;
   hipStream_t main_;
   hipStream_t side_ = nullptr;
+  DevHeap hip_;      // no region: stream-ordered HIP allocations
+  DevHeap region_;   // the caller's region, when one is given
+  DevHeap* heap_;
+  size_t tile_cap_ = 0, tiles_held_ = 0;
   Engine eng_;
   size_t budget_ = 0, held_ = 0;
   int64_t next_ticket_ = 0;
@@ -83,11 +106,24 @@ class Server {
   std::vector<Request*> done_;
 };
 
+// Releases a request's device memory (its work is complete).
+void Server::drop(Request* r) {
+  if (r->block) {
+    delete r->sub;
+    r->sub = nullptr;
+    heap_->release(r->block, main_);
+    r->block = nullptr;
+    r->g.mem = r->g.mem2 = nullptr;
+  } else {
+    free_graph_ops_async(r->g, main_);
+  }
+}
+
 Server::~Server() {
   (void)hipStreamSynchronize(main_);
   if (side_) (void)hipStreamSynchronize(side_);
   auto drop = [&](Request* r) {
-    free_graph_ops_async(r->g, main_);
+    this->drop(r);
     delete r;
   };
   for (auto* r : queue_) drop(r);
@@ -112,16 +148,27 @@ int Server::init() {
   return ME_OK;
 }
 
-// Device bytes of one request: operators (W copy, T, the packed operator,
-// per-node arrays; T sized by the d^2 bound of the two-hop set), the build's
-// scratch, and the larger of its two solver slots.
-size_t Server::estimate(const me_csr& W, int K) const {
-  const double n = (double)W.n, nnz = (double)W.nnz;
-  const double dbar = nnz / std::max(1.0, n);
-  const double nnz_t = std::min(n * dbar * dbar, n * std::max(0.0, n - 1.0));
-  const double ops = n * 220.0 + nnz * 12.0 + (nnz + nnz_t) * 16.0 + nnz_t * 4.0 + (n + 2) * 40.0;
-  const size_t slot = std::max(Engine::slot_bytes(W.n, 4), Engine::slot_bytes(W.n, block_width(K)));
-  return (size_t)ops + slot + ((size_t)1 << 20);
+// Device bytes of one request, an upper bound: its build (T sized by the
+// degree bound of the two-hop set, search scratch), both solver slots (eps
+// and the embedding, each allocated once) or the dense solves.  Reads the
+// row pointers of W.
+size_t request_bytes(int64_t n, int64_t nnz, int64_t nnz_t_max, int K) {
+  size_t b = build_bytes_bound(n, nnz, nnz_t_max);
+  if (n <= kDenseMaxN)
+    b += eps_solve_bytes(n) + DevHeap::round(dense_request_bytes(n));
+  else
+    b += DevHeap::round(Engine::slot_bytes(n, 4)) +
+         DevHeap::round(Engine::slot_bytes(n, block_width(K)));
+  return b + kHeapAlign;
+}
+
+int Server::estimate(Request* r) {
+  int64_t tb = 0;
+  ME_TRY_STATUS(two_hop_bound(&r->W, side_, &tb));
+  const int64_t n = r->W.n;
+  r->est = request_bytes(n, r->W.nnz, tb, r->K);
+  r->tiles = n <= kDenseMaxN ? 0 : Engine::tile_bytes(n, std::max(4, block_width(r->K)));
+  return ME_OK;
 }
 
 int Server::submit(const me_csr* W, int K, double tol, double* X, double* lambda,
@@ -136,7 +183,6 @@ int Server::submit(const me_csr* W, int K, double tol, double* X, double* lambda
   r->tol = tol;
   r->X = X;
   r->lambda = lambda;
-  r->est = estimate(*W, K);
   queue_.push_back(r);
   *ticket = r->ticket;
   return ME_OK;
@@ -152,8 +198,9 @@ void Server::finish(Request* r, int st) {
     in_slot_.erase(r->slot);
     r->slot = -1;
   }
-  free_graph_ops_async(r->g, main_);
+  drop(r);
   held_ -= std::min(held_, r->est);
+  tiles_held_ -= std::min(tiles_held_, r->tiles);
   --admitted_;
   done_.push_back(r);
 }
@@ -175,13 +222,44 @@ int Server::admit() {
   want_post_.clear();
   while (!queue_.empty() && admitted_ < so_.max_active) {
     Request* r = queue_.front();
-    // a request larger than the budget runs when nothing else is admitted
-    if (held_ + r->est > budget_ && admitted_ > 0) break;
+    if (r->est == 0) {
+      const int se = estimate(r);
+      if (se < 0) {  // malformed row pointers: the request's own error
+        queue_.pop_front();
+        ++admitted_;
+        finish(r, se);
+        continue;
+      }
+    }
+    if (heap_->region()) {
+      // reserve the request's whole footprint in the region; a request that
+      // cannot fit even in an idle server fails, others wait for retirements
+      const bool tiles_fit = tiles_held_ + r->tiles <= tile_cap_;
+      void* blk = nullptr;
+      if (tiles_fit && heap_->alloc(&blk, r->est, side_) == ME_OK) {
+        r->block = blk;
+        r->sub = new (std::nothrow) DevHeap(blk, r->est);
+      }
+      if (!r->sub) {
+        if (blk) heap_->release(blk, side_);
+        r->block = nullptr;
+        if (admitted_ > 0) break;
+        queue_.pop_front();
+        ++admitted_;
+        finish(r, ME_ERR_WORKSPACE);
+        continue;
+      }
+    } else if (held_ + r->est > budget_ && admitted_ > 0) {
+      // a request larger than the budget runs when nothing else is admitted
+      break;
+    }
     queue_.pop_front();
     ++admitted_;
     held_ += r->est;
+    tiles_held_ += r->tiles;
     r->t_admit = Clock::now();
-    int st = build_pre(&r->W, &so_.opts, side_, &r->g);
+    DevHeap& rh = r->sub ? *r->sub : hip_;
+    int st = build_pre(&r->W, &so_.opts, rh, side_, &r->g);
     if (st >= 0) st = check_k_range(r->g, r->K);
     if (st < 0) {
       finish(r, st);
@@ -189,20 +267,18 @@ int Server::admit() {
     }
     if (r->g.n <= kDenseMaxN) {
       double eps = 0.0;
-      if (r->g.needs_eps) st = dense_eps_solve(r->g, side_, &eps);
+      if (r->g.needs_eps) st = dense_eps_solve(r->g, rh, side_, &eps);
       if (st >= 0) st = build_post(&r->g, eps, 0, side_);
       if (st >= 0) {
-        // a HIP failure here is this request's error: finish() releases its
+        // a failure here is this request's error: finish() releases its
         // budget and reports it through me_server_poll
         double* buf = nullptr;
-        hipError_t he =
-            hipMallocAsync((void**)&buf, embed_workspace_bytes(r->g, r->K, &so_.opts), side_);
-        if (he == hipSuccess) {
+        st = rh.alloc((void**)&buf, dense_request_bytes(r->g.n), side_);
+        if (st >= 0) {
           dense_embed_solve(r->g, r->K, buf, r->X, r->lambda, side_);
-          he = hipFreeAsync(buf, side_);
+          if (hipStreamSynchronize(side_) != hipSuccess) st = ME_ERR_HIP;
+          rh.release(buf, side_);
         }
-        if (he == hipSuccess) he = hipStreamSynchronize(side_);
-        if (he != hipSuccess) st = ME_ERR_HIP;
       }
       if (st >= 0) {
         r->info.block = (int)r->g.n;
@@ -229,10 +305,25 @@ int Server::admit() {
   return ME_OK;
 }
 
+// Over a region a slot's memory comes from its request's block (the engine
+// does not own it); otherwise the engine allocates it.
+static int slot_memory(Request* r, int kb, void** ws, size_t* bytes) {
+  *ws = nullptr;
+  *bytes = 0;
+  if (!r->sub) return ME_OK;
+  *bytes = Engine::slot_bytes(r->g.n, kb);
+  ME_TRY_STATUS(r->sub->alloc(ws, *bytes, nullptr));
+  r->slot_ws = *ws;
+  return ME_OK;
+}
+
 int Server::add_slots() {
   for (auto* r : want_eps_) {
     int id = -1;
-    const int st = eng_.add(eps_slot_spec(r->g, &so_.opts), nullptr, 0, &id);
+    void* ws = nullptr;
+    size_t wb = 0;
+    int st = slot_memory(r, 4, &ws, &wb);
+    if (st >= 0) st = eng_.add(eps_slot_spec(r->g, &so_.opts), ws, wb, &id);
     if (st < 0) {
       finish(r, st);
       continue;
@@ -244,9 +335,12 @@ int Server::add_slots() {
   want_eps_.clear();
   for (auto* r : want_embed_) {
     int id = -1;
-    const int st =
-        eng_.add(embed_slot_spec(r->g, r->K, r->tol, &so_.opts, nullptr, r->X, r->lambda),
-                 nullptr, 0, &id);
+    void* ws = nullptr;
+    size_t wb = 0;
+    int st = slot_memory(r, block_width(r->K), &ws, &wb);
+    if (st >= 0)
+      st = eng_.add(embed_slot_spec(r->g, r->K, r->tol, &so_.opts, nullptr, r->X, r->lambda),
+                    ws, wb, &id);
     if (st < 0) {
       finish(r, st);
       continue;
@@ -277,6 +371,10 @@ int Server::step(int* in_flight) {
     eng_.release(id);
     in_slot_.erase(it);
     r->slot = -1;
+    if (r->sub && r->slot_ws) {  // the round is complete: the slot's memory is free
+      r->sub->release(r->slot_ws, main_);
+      r->slot_ws = nullptr;
+    }
     if (eps_phase) {
       r->g.eps = res.lam[0];
       r->eps_iters = res.iterations;
@@ -330,6 +428,7 @@ void me_server_opts_default(me_server_opts* so) {
   if (!so) return;
   so->mem_budget = 0;
   so->max_active = 256;
+  so->workspace = nullptr;
   me_opts_default(&so->opts);
 }
 
@@ -339,6 +438,8 @@ int me_server_create(const me_server_opts* so, void* stream, me_server** out) {
   me_server_opts o;
   if (so) o = *so; else me_server_opts_default(&o);
   if (o.max_active < 1 || !me::opts_valid(o.opts)) return ME_ERR_INVALID_ARG;
+  // a region must hold at least the tables and the work-list areas
+  if (o.workspace && o.mem_budget < ((size_t)4 << 20)) return ME_ERR_WORKSPACE;
   auto* h = new (std::nothrow) me_server();
   if (!h) return ME_ERR_HIP;
   h->s = new (std::nothrow) me::Server(o, (hipStream_t)stream);
@@ -353,6 +454,15 @@ int me_server_create(const me_server_opts* so, void* stream, me_server** out) {
     return st;
   }
   *out = h;
+  return ME_OK;
+}
+
+int me_server_request_bytes(const me_csr* W, int K, void* stream, size_t* bytes) {
+  if (!W || !bytes || K < 1 || K > me::kMaxBlockCols) return ME_ERR_INVALID_ARG;
+  *bytes = 0;
+  int64_t tb = 0;
+  ME_TRY_STATUS(me::two_hop_bound(W, (hipStream_t)stream, &tb));
+  *bytes = me::request_bytes(W->n, W->nnz, tb, K);
   return ME_OK;
 }
 

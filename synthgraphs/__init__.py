@@ -25,7 +25,7 @@ __all__ = [
     "CSR", "from_edges", "sample_points", "knn_graph", "manifold_graph",
     "ring", "line", "complete", "star", "tri_mesh", "grid", "complete_bipartite",
     "random_graph", "disjoint_union", "initial_block", "batch_specs",
-    "serve_arrivals", "CONFIGS", "periodic_lattice", "lattice_stencil",
+    "serve_arrivals", "CONFIGS", "periodic_lattice", "lattice_stencil", "sparse_random_graph",
 ]
 
 
@@ -223,6 +223,27 @@ def random_graph(n: int, p: float, seed: int, wlo: float = 0.25, whi: float = 2.
     w = rng.uniform(wlo, whi, i.size)
     lo = np.minimum(i, j)
     hi = np.maximum(i, j)
+    key, first = np.unique(lo * n + hi, return_index=True)
+    return from_edges(n, key // n, key % n, w[first])
+
+
+def sparse_random_graph(n: int, avg_degree: float, seed: int, wlo: float = 0.25,
+                        whi: float = 2.0) -> CSR:
+    """About n * avg_degree / 2 uniformly random edges plus a random spanning
+    path (no isolated node), uniform random weights: an expander, whose
+    breadth-first levels grow geometrically."""
+    rng = np.random.default_rng(seed)
+    m = int(n * avg_degree / 2)
+    i = rng.integers(0, n, m)
+    j = rng.integers(0, n, m)
+    perm = rng.permutation(n)
+    i = np.concatenate([i, perm[:-1]])
+    j = np.concatenate([j, perm[1:]])
+    keep = i != j
+    i, j = i[keep], j[keep]
+    w = rng.uniform(wlo, whi, i.size)
+    lo = np.minimum(i, j).astype(np.int64)
+    hi = np.maximum(i, j).astype(np.int64)
     key, first = np.unique(lo * n + hi, return_index=True)
     return from_edges(n, key // n, key % n, w[first])
 

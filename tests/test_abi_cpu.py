@@ -19,7 +19,8 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for required in ("me_build_graph_ops", "me_embed", "me_embed_workspace_bytes",
+    for required in ("me_build_graph_ops", "me_build_workspace_bytes", "me_embed",
+                     "me_embed_workspace_bytes", "me_embed_batch_workspace_bytes",
                      "me_graph_ops_export", "me_graph_ops_destroy", "me_status_string"):
         assert required in names
 
@@ -59,8 +60,41 @@ def test_invalid_options_rejected_before_device_work():
         o = _lib.MeOpts()
         lib.me_opts_default(ctypes.byref(o))
         setattr(o, field, val)
-        st = lib.me_build_graph_ops(ctypes.byref(W), ctypes.byref(o), None, ctypes.byref(h), None)
+        st = lib.me_build_graph_ops(ctypes.byref(W), ctypes.byref(o), None, 0, None,
+                                    ctypes.byref(h), None)
         assert _lib.STATUS_NAMES[st] == "ME_ERR_INVALID_ARG", (field, val, st)
+
+
+def test_workspace_too_small_rejected_before_device_work():
+    """A caller workspace smaller than any call can use is ME_ERR_WORKSPACE,
+    decided on the host (no device call is made): the build, the batch and a
+    server over a region."""
+    from paper_2112_07862_amd import _lib
+    lib = _lib.load()
+    W = _lib.MeCsr()
+    W.n = 4
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(64)  # any non-null address; never dereferenced
+    ws = ctypes.cast(buf, ctypes.c_void_p)
+    st = lib.me_build_graph_ops(ctypes.byref(W), None, ws, 16, None, ctypes.byref(h), None)
+    assert _lib.STATUS_NAMES[st] == "ME_ERR_WORKSPACE"
+    Ws = (_lib.MeCsr * 1)(W)
+    Ks = (ctypes.c_int * 1)(4)
+    Xs = (ctypes.c_void_p * 1)(ws.value)
+    Ls = (ctypes.c_void_p * 1)(ws.value)
+    st = lib.me_embed_batch(1, Ws, Ks, 1e-6, None, ws, 16, Xs, Ls, None, None)
+    assert _lib.STATUS_NAMES[st] == "ME_ERR_WORKSPACE"
+    so = _lib.MeServerOpts()
+    lib.me_server_opts_default(ctypes.byref(so))
+    assert so.workspace is None
+    so.workspace = ws.value
+    so.mem_budget = 1 << 20
+    srv = ctypes.c_void_p()
+    st = lib.me_server_create(ctypes.byref(so), None, ctypes.byref(srv))
+    assert _lib.STATUS_NAMES[st] == "ME_ERR_WORKSPACE" and not srv.value
+    so.mem_budget = 0
+    st = lib.me_server_create(ctypes.byref(so), None, ctypes.byref(srv))
+    assert _lib.STATUS_NAMES[st] == "ME_ERR_WORKSPACE" and not srv.value
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -384,6 +384,34 @@ def test_solver_order_bit_exact(me, name):
     h.close()
 
 
+def _large_order_graph(name):
+    if name == "swiss_100k":
+        return sg.manifold_graph("swiss_roll", 100_000, 10, 0)
+    if name == "square_40k_plus_two":
+        # three components: the per-level search orders the first, the
+        # one-workgroup search continues with the others
+        return sg.disjoint_union([sg.manifold_graph("square", 40_000, 8, 5),
+                                  sg.manifold_graph("sphere", 3_000, 10, 6), sg.ring(50, 2)])
+    if name == "expander_60k":
+        # levels grow geometrically: a level of tens of thousands of nodes
+        # spans many scan chunks
+        return sg.sparse_random_graph(60_000, 6.0, 7)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["swiss_100k", "square_40k_plus_two", "expander_60k"])
+def test_solver_order_bit_exact_large(me, name):
+    """Graphs of 32768 nodes or more take the per-level multi-workgroup
+    searches; the order is still that of the sequential algorithm."""
+    g = _large_order_graph(name)
+    print(f"[gpu] order {name} n={g.n}", flush=True)
+    h = me.build_graph_ops(g)
+    perm = _np(h.order())
+    assert np.array_equal(np.sort(perm), np.arange(g.n))
+    assert np.array_equal(perm, cm_order_reference(g))
+    h.close()
+
+
 @pytest.mark.parametrize("name,K", [("square_2k", 4), ("swiss_3k", 8), ("sphere_3k", 16),
                                     ("ring_203", 8), ("grid_bipartite", 4)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
