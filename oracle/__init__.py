@@ -18,8 +18,12 @@ generalized eigenvectors for manifold graph embedding":
   B^-1/2 A B^-1/2 for small N and by shift-invert Lanczos (ARPACK, a library
   eigensolver) for large N; residuals, B-orthonormality and principal angles.
 
+* ``knn``: the k-nearest-neighbour graph of points (Section 5.1: kNN graphs
+  from Euclidean distances), union-symmetrised, with Gaussian weights
+  exp(-d^2 / sigma^2), sigma the median k-th neighbour distance.
+
 Readings of passages that are silent or ambiguous are listed at the top of
-``graph_ops``.
+``graph_ops`` and ``knn``.
 """
 from .graph_ops import (  # noqa: F401
     OracleInputError, validate, degrees, laplacian, two_hop, theta_sum_q,
