@@ -350,6 +350,23 @@ void me_server_destroy(me_server* s);
 int me_kernel_timing(int kind);
 int me_kernel_timing_read(int64_t* launches, double* total_ms, double* bytes);
 
+/* ---- Without device allocation ------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * me_embed_noalloc is me_embed whose workspace is a file-scope device array
+ * of the library, me_embed_noalloc_max_bytes() bytes (64 MiB) on each
+ * device the library runs on, held until the process ends.  The call makes
+ * no allocation of any kind.  Arguments, results and errors as me_embed
+ * (there is no workspace argument), plus ME_ERR_WORKSPACE, outputs
+ * untouched, when me_embed_workspace_bytes for this graph and K exceeds the
+ * array: about 880 000 rows x block width (n <= 110 000 at K <= 8).  Calls
+ * on one device share the array; the library serialises them (a second call
+ * waits until the first has returned), so calls that would overlap on one
+ * device do not race. */
+size_t me_embed_noalloc_max_bytes(void);
+int me_embed_noalloc(const me_graph_ops* ops, int K, double tol, const me_opts* opts,
+                     const double* X0, double* X, double* lambda, me_info* info, void* stream);
+
 /* Releases a handle (NULL is allowed). */
 void me_graph_ops_destroy(me_graph_ops* ops);
 

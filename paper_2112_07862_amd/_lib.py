@@ -84,6 +84,9 @@ SIGNATURES = {
                                ctypes.POINTER(MeOpts), c_void_p, c_size_t,
                                ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
                                ctypes.POINTER(MeInfo), c_void_p]),
+    "me_embed_noalloc_max_bytes": (c_size_t, []),
+    "me_embed_noalloc": (c_int, [c_void_p, c_int, c_double, ctypes.POINTER(MeOpts), c_void_p,
+                                 c_void_p, c_void_p, ctypes.POINTER(MeInfo), c_void_p]),
     "me_graph_ops_destroy": (None, [c_void_p]),
     "me_server_opts_default": (None, [ctypes.POINTER(MeServerOpts)]),
     "me_server_create": (c_int, [ctypes.POINTER(MeServerOpts), c_void_p,
