@@ -22,8 +22,11 @@ generalized eigenvectors for manifold graph embedding":
   from Euclidean distances), union-symmetrised, with Gaussian weights
   exp(-d^2 / sigma^2), sigma the median k-th neighbour distance.
 
+* ``cluster``: k-means and Gaussian-mixture clustering of the embedding and
+  the Rand index, Precision, Purity and NMI of Section 5.1 and Table 3.
+
 Readings of passages that are silent or ambiguous are listed at the top of
-``graph_ops`` and ``knn``.
+``graph_ops``, ``knn`` and ``cluster``.
 """
 from .graph_ops import (  # noqa: F401
     OracleInputError, validate, degrees, laplacian, two_hop, theta_sum_q,
