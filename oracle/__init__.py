@@ -25,8 +25,11 @@ generalized eigenvectors for manifold graph embedding":
 * ``cluster``: k-means and Gaussian-mixture clustering of the embedding and
   the Rand index, Precision, Purity and NMI of Section 5.1 and Table 3.
 
+* ``vbc``: betweenness centrality (eq. (3) of Section 3.3) and its variance,
+  the check that accepts a graph as a manifold graph (Table 1).
+
 Readings of passages that are silent or ambiguous are listed at the top of
-``graph_ops``, ``knn`` and ``cluster``.
+``graph_ops``, ``knn``, ``cluster`` and ``vbc``.
 """
 from .graph_ops import (  # noqa: F401
     OracleInputError, validate, degrees, laplacian, two_hop, theta_sum_q,
