@@ -350,6 +350,97 @@ void me_server_destroy(me_server* s);
 int me_kernel_timing(int kind);
 int me_kernel_timing_read(int64_t* launches, double* total_ms, double* bytes);
 
+/* ---- kNN graph of points (the step before the path) --------------------
+ * The symmetric weighted graph of Section 5.1's kNN construction ("kNN
+ * graphs ... based on Euclidean distances") with Gaussian weights:
+ *   - d2(i, j) = sum over coordinates, in order, of (x_id - x_jd)^2, each
+ *     square a plain product (no fused multiply-add), FP64;
+ *   - N_k(i) = the k points j != i of smallest d2(i, j), equal distances
+ *     ordered by the smaller j (exact: every pair is evaluated);
+ *   - edges: the union, (i, j) when j in N_k(i) or i in N_k(j);
+ *   - sigma = median over i of sqrt(d2(i, k-th neighbour)) (the mean of the
+ *     two middle values for even n);
+ *   - w_ij = exp(-d2(i, j) / (sigma * sigma)), raised to the smallest normal
+ *     FP64 number if it underflows.
+ * The result is a valid input of me_build_graph_ops (sorted columns,
+ * symmetric, no self loops, positive weights, no isolated node).
+ *   points  device float64[n * dim], row-major (point i at points + i*dim).
+ *   n       2 .. 2^31 - 2;  dim 1..64;  k 1..32 and k < n.
+ *   ws      device workspace of at least me_knn_workspace_bytes(n, dim, k)
+ *           bytes (no device allocation is made), or NULL.
+ *   rowptr  device int64[n + 1] output.
+ *   col     device int32 output, capacity 2 n k (nnz <= 2 n k).
+ *   val     device float64 output, capacity 2 n k.
+ *   nnz     host output: the number of entries written.
+ *   sigma   host output (may be NULL).
+ * Errors: ME_ERR_INVALID_ARG (null pointers, sizes, a non-finite coordinate,
+ * squared distances beyond FP64), ME_ERR_K_RANGE, ME_ERR_BAD_WEIGHT (sigma
+ * = 0: the median k-th neighbour distance is 0, so the weights are
+ * undefined), ME_ERR_WORKSPACE.  Synchronises `stream`. */
+size_t me_knn_workspace_bytes(int64_t n, int dim, int k);
+int me_knn_graph(const double* points, int64_t n, int dim, int k, void* ws, size_t ws_bytes,
+                 int64_t* rowptr, int32_t* col, double* val, int64_t* nnz, double* sigma,
+                 void* stream);
+
+/* ---- Clustering the embedding and scoring it (Section 5.1, Table 3) -------
+ * The rows of an embedding X (device float64, n x K row-major, K <= 16) are
+ * clustered into C <= 64 clusters (C <= n).
+ * me_kmeans: k-means++ seeds from the caller's uniforms u[0..C-1] (host,
+ *   each in [0, 1)): seed 0 is point floor(u_0 n); seed t is the first point
+ *   whose running sum of D^2 (squared distance to its nearest seed so far)
+ *   exceeds u_t times the total.  Then Lloyd iterations: each point joins its
+ *   nearest centre (ties to the lower index; squared distances summed over
+ *   coordinates in order, plain products), each centre becomes the mean of
+ *   its points (an empty cluster keeps its centre), until no point moves or
+ *   max_iter updates.  Outputs: labels (device int32[n]), centres (device
+ *   float64[C * K]), *iters (host) = centre updates made.
+ * me_gmm: EM for a C-component Gaussian mixture with full covariances from
+ *   the partition labels0 (device int32[n], values in 0..C-1): weights =
+ *   cluster fractions, means = cluster means (the data mean for an empty
+ *   one), covariances = within-cluster covariances; every covariance gets
+ *   reg I added, reg = 1e-6 times the mean per-coordinate variance of X.
+ *   Stops when the log-likelihood changes by at most tol times its
+ *   magnitude, or after max_iter steps.  Outputs: labels (most responsible
+ *   component, ties to the lower index), weights (device float64[C]),
+ *   means (C * K), covs (C * K * K), *loglik and *iters (host).
+ *   ME_ERR_BREAKDOWN if a covariance stops being positive definite.
+ * me_cluster_scores: Rand index, Precision (pairs), Purity and NMI
+ *   (I / sqrt(H_classes H_clusters)) of clusters (device int32[n], values in
+ *   0..n_clusters-1) against classes (0..n_classes-1), both counts <= 256:
+ *   scores (host float64[4]).
+ * Workspace: at least me_cluster_workspace_bytes(n, K, C) bytes (any of the
+ * three calls), or NULL.  All three synchronise `stream`. */
+size_t me_cluster_workspace_bytes(int64_t n, int K, int C);
+int me_kmeans(const double* X, int64_t n, int K, int C, const double* u, int max_iter, void* ws,
+              size_t ws_bytes, int32_t* labels, double* centres, int* iters, void* stream);
+int me_gmm(const double* X, int64_t n, int K, int C, const int32_t* labels0, int max_iter,
+           double tol, void* ws, size_t ws_bytes, int32_t* labels, double* weights, double* means,
+           double* covs, double* loglik, int* iters, void* stream);
+int me_cluster_scores(const int32_t* classes, const int32_t* clusters, int64_t n, int n_classes,
+                      int n_clusters, void* ws, size_t ws_bytes, double* scores, void* stream);
+
+/* ---- Manifold-graph check: betweenness centrality and its variance -------
+ * Section 3.3 (eq. (3), Table 1) accepts a graph as a manifold graph when the
+ * variance of its nodes' betweenness centralities (VBC) is small:
+ *   C_B(i) = sum over ordered pairs (s, t), s != t, s != i, t != i, of
+ *            sigma_st(i) / sigma_st,
+ * sigma_st the number of shortest paths from s to t (counted in edges: the
+ * weights of W do not enter) and sigma_st(i) those through i; pairs in
+ * different components add nothing; VBC = (1/n) sum_i (C_B(i) - mean)^2.
+ * Path counts are held in FP64 (exact below 2^53).  O(n |E|) work: meant for
+ * graphs of up to some 10^5 nodes.
+ *   W    host struct of device pointers; rowptr and col are read (val is
+ *        not), columns sorted, symmetric, no self loops (isolated nodes are
+ *        allowed: their centrality is 0).
+ *   ws   device workspace of at least me_betweenness_workspace_bytes(n)
+ *        bytes, or NULL.
+ *   cb   device float64[n] output.   vbc  host output (may be NULL).
+ * Errors: ME_ERR_INVALID_ARG (malformed CSR), ME_ERR_NOT_SYMMETRIC,
+ * ME_ERR_WORKSPACE.  Synchronises `stream`. */
+size_t me_betweenness_workspace_bytes(int64_t n);
+int me_betweenness(const me_csr* W, void* ws, size_t ws_bytes, double* cb, double* vbc,
+                   void* stream);
+
 /* ---- Without device allocation ------------------------------------------
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):

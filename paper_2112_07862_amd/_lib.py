@@ -84,6 +84,22 @@ SIGNATURES = {
                                ctypes.POINTER(MeOpts), c_void_p, c_size_t,
                                ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
                                ctypes.POINTER(MeInfo), c_void_p]),
+    "me_knn_workspace_bytes": (c_size_t, [c_int64, c_int, c_int]),
+    "me_knn_graph": (c_int, [c_void_p, c_int64, c_int, c_int, c_void_p, c_size_t, c_void_p,
+                             c_void_p, c_void_p, ctypes.POINTER(c_int64),
+                             ctypes.POINTER(c_double), c_void_p]),
+    "me_cluster_workspace_bytes": (c_size_t, [c_int64, c_int, c_int]),
+    "me_kmeans": (c_int, [c_void_p, c_int64, c_int, c_int, ctypes.POINTER(c_double), c_int,
+                          c_void_p, c_size_t, c_void_p, c_void_p, ctypes.POINTER(c_int),
+                          c_void_p]),
+    "me_gmm": (c_int, [c_void_p, c_int64, c_int, c_int, c_void_p, c_int, c_double, c_void_p,
+                       c_size_t, c_void_p, c_void_p, c_void_p, c_void_p,
+                       ctypes.POINTER(c_double), ctypes.POINTER(c_int), c_void_p]),
+    "me_cluster_scores": (c_int, [c_void_p, c_void_p, c_int64, c_int, c_int, c_void_p, c_size_t,
+                                  ctypes.POINTER(c_double), c_void_p]),
+    "me_betweenness_workspace_bytes": (c_size_t, [c_int64]),
+    "me_betweenness": (c_int, [ctypes.POINTER(MeCsr), c_void_p, c_size_t, c_void_p,
+                               ctypes.POINTER(c_double), c_void_p]),
     "me_embed_noalloc_max_bytes": (c_size_t, []),
     "me_embed_noalloc": (c_int, [c_void_p, c_int, c_double, ctypes.POINTER(MeOpts), c_void_p,
                                  c_void_p, c_void_p, ctypes.POINTER(MeInfo), c_void_p]),

@@ -174,6 +174,106 @@ def c_int64_():
     return ctypes.c_int64()
 
 
+def knn_graph(points: torch.Tensor, k: int, workspace: torch.Tensor | None = None,
+              stream=None):
+    """Symmetric Gaussian-weighted kNN graph of `points` (n x dim float64,
+    on the device) built on the GPU.  Returns (DeviceCSR, sigma)."""
+    x = points.to(dtype=torch.float64).contiguous()
+    if x.dim() != 2:
+        raise ValueError("points must be n x dim")
+    n, dim = int(x.shape[0]), int(x.shape[1])
+    lib = L.load()
+    cap = max(2 * n * int(k), 1)
+    rp = torch.empty(n + 1, dtype=torch.int64, device=x.device)
+    col = torch.empty(cap, dtype=torch.int32, device=x.device)
+    val = torch.empty(cap, dtype=torch.float64, device=x.device)
+    nnz, sigma = ctypes.c_int64(), ctypes.c_double()
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(lib.me_knn_graph(_ptr(x), n, dim, int(k), _ptr(workspace), nbytes, _ptr(rp), _ptr(col),
+                            _ptr(val), ctypes.byref(nnz), ctypes.byref(sigma),
+                            _stream_ptr(stream)), "knn_graph")
+    m = int(nnz.value)
+    return DeviceCSR(n, rp, col[:m].clone(), val[:m].clone()), float(sigma.value)
+
+
+def _ws_args(workspace):
+    return _ptr(workspace), (0 if workspace is None else workspace.numel() * workspace.element_size())
+
+
+def kmeans(X: torch.Tensor, C: int, u, max_iter: int = 100,
+           workspace: torch.Tensor | None = None, stream=None):
+    """k-means of the rows of X (n x K float64, device) into C clusters from
+    the uniforms u (C values in [0, 1), the k-means++ draws).  Returns
+    (labels int32 [n], centres [C, K], iterations)."""
+    X = X.to(dtype=torch.float64).contiguous()
+    n, K = int(X.shape[0]), int(X.shape[1])
+    uu = (ctypes.c_double * int(C))(*[float(v) for v in u])
+    labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    cen = torch.empty((int(C), K), dtype=torch.float64, device=X.device)
+    it = ctypes.c_int()
+    wp, wb = _ws_args(workspace)
+    _check(L.load().me_kmeans(_ptr(X), n, K, int(C), uu, int(max_iter), wp, wb, _ptr(labels),
+                              _ptr(cen), ctypes.byref(it), _stream_ptr(stream)), "kmeans")
+    return labels, cen, it.value
+
+
+def gmm(X: torch.Tensor, C: int, labels0: torch.Tensor, max_iter: int = 100, tol: float = 1e-6,
+        workspace: torch.Tensor | None = None, stream=None):
+    """EM for a full-covariance Gaussian mixture from the partition labels0.
+    Returns (labels, weights [C], means [C, K], covs [C, K, K], loglik,
+    iterations)."""
+    X = X.to(dtype=torch.float64).contiguous()
+    n, K = int(X.shape[0]), int(X.shape[1])
+    l0 = labels0.to(dtype=torch.int32).contiguous()
+    labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    w = torch.empty(int(C), dtype=torch.float64, device=X.device)
+    mu = torch.empty((int(C), K), dtype=torch.float64, device=X.device)
+    cov = torch.empty((int(C), K, K), dtype=torch.float64, device=X.device)
+    ll, it = ctypes.c_double(), ctypes.c_int()
+    wp, wb = _ws_args(workspace)
+    _check(L.load().me_gmm(_ptr(X), n, K, int(C), _ptr(l0), int(max_iter), float(tol), wp, wb,
+                           _ptr(labels), _ptr(w), _ptr(mu), _ptr(cov), ctypes.byref(ll),
+                           ctypes.byref(it), _stream_ptr(stream)), "gmm")
+    return labels, w, mu, cov, ll.value, it.value
+
+
+def cluster_scores(classes: torch.Tensor, clusters: torch.Tensor, n_classes: int,
+                   n_clusters: int, workspace: torch.Tensor | None = None, stream=None) -> dict:
+    """RI, Precision, Purity and NMI of a clustering against known classes."""
+    a = classes.to(dtype=torch.int32).contiguous()
+    b = clusters.to(dtype=torch.int32).contiguous()
+    out = (ctypes.c_double * 4)()
+    wp, wb = _ws_args(workspace)
+    _check(L.load().me_cluster_scores(_ptr(a), _ptr(b), int(a.numel()), int(n_classes),
+                                      int(n_clusters), wp, wb, out, _stream_ptr(stream)),
+           "cluster_scores")
+    return {"RI": out[0], "Precision": out[1], "Purity": out[2], "NMI": out[3]}
+
+
+def cluster_workspace_bytes(n: int, K: int, C: int) -> int:
+    return int(L.load().me_cluster_workspace_bytes(int(n), int(K), int(C)))
+
+
+def betweenness(csr, workspace: torch.Tensor | None = None, stream=None):
+    """Betweenness centrality of every node (eq. (3), hop-count shortest
+    paths) and its variance.  Returns (C_B tensor [n] float64, VBC)."""
+    d = to_device(csr)
+    cb = torch.empty(d.n, dtype=torch.float64, device=d.rowptr.device)
+    v = ctypes.c_double()
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(L.load().me_betweenness(ctypes.byref(d.as_struct()), _ptr(workspace), nbytes, _ptr(cb),
+                                   ctypes.byref(v), _stream_ptr(stream)), "betweenness")
+    return cb, float(v.value)
+
+
+def betweenness_workspace_bytes(n: int) -> int:
+    return int(L.load().me_betweenness_workspace_bytes(int(n)))
+
+
+def knn_workspace_bytes(n: int, dim: int, k: int) -> int:
+    return int(L.load().me_knn_workspace_bytes(int(n), int(dim), int(k)))
+
+
 def build_workspace_bytes(csr, stream=None, **opts) -> int:
     """Device bytes build_graph_ops needs when given a workspace (an upper
     bound: the two-hop pattern is sized by W's degrees)."""

@@ -302,8 +302,9 @@ __global__ void k_scan_add(int64_t n, int64_t* out, const int64_t* tile_sums) {
   if (i < n) out[i] += tile_sums[i / kScanTile];
 }
 
-static void scan_counts(int64_t n, const int32_t* cnt, int64_t* out, int64_t* tile_tmp,
-                        hipStream_t s) {
+int64_t scan_tmp_count(int64_t n) { return std::max<int64_t>(1, ceil_div(n, kScanTile)); }
+
+void scan_counts(int64_t n, const int32_t* cnt, int64_t* out, int64_t* tile_tmp, hipStream_t s) {
   int64_t ntiles = ceil_div(n, kScanTile);
   if (ntiles == 0) ntiles = 1;
   k_scan_tiles<<<ntiles, kBlock, 0, s>>>(n, cnt, out, tile_tmp);

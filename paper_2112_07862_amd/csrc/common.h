@@ -249,6 +249,10 @@ size_t twohop_bitmap_bytes(int64_t n);
 // Every allocation of build_pre for a graph of n nodes, nnz entries and at
 // most nnz_t_max two-hop entries (each rounded to the heap's unit).
 size_t build_bytes_bound(int64_t n, int64_t nnz, int64_t nnz_t_max);
+// Exclusive scan of int32 counts into int64 offsets out[0..n] (out[n] = the
+// total); tile_tmp holds scan_tmp_count(n) int64.
+int64_t scan_tmp_count(int64_t n);
+void scan_counts(int64_t n, const int32_t* cnt, int64_t* out, int64_t* tile_tmp, hipStream_t s);
 // Upper bound of nnz(T) from W's degrees (reads W's row pointers).
 int two_hop_bound(const me_csr* W, hipStream_t s, int64_t* bound);
 // option ranges of me_opts (shared by every entry point that takes them)
@@ -304,6 +308,20 @@ int ktimer_kind();
 int ktimer_new_phase();
 void ktimer_drop_after(int phase, int last_real);
 void ktimer_collect();
+
+// ---- knn.hip ----------------------------------------------------------------
+size_t knn_workspace_bytes(int64_t n, int k);
+int knn_graph(const double* x, int64_t n, int dim, int k, void* ws, size_t ws_bytes,
+              int64_t* rowptr, int32_t* col, double* val, int64_t* nnz, double* sigma,
+              hipStream_t s);
+
+// ---- cluster.hip ------------------------------------------------------------
+size_t cluster_workspace_bytes(int64_t n, int K, int C);
+
+// ---- vbc.hip ----------------------------------------------------------------
+size_t betweenness_workspace_bytes(int64_t n);
+int betweenness(const me_csr* W, void* ws, size_t ws_bytes, double* cb, double* vbc,
+                hipStream_t s);
 
 // ---- lobpcg.hip -------------------------------------------------------------
 int solve_eps(GraphOps& g, const me_opts* o, DevHeap& heap, hipStream_t s, double* eps,
