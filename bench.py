@@ -49,6 +49,7 @@ KERNEL_NAMES = {"spmm": "k_spmm (difference-form SpMM of A on the LOBPCG block)"
 TRAFFIC_FILES = {
     ("swiss_roll_100k", "mixed", "fp32"): "cheb_step_swiss_roll_100k_hbm_bytes.txt",
     ("sphere_1m", "mixed", "fp16"): "cheb_step_fp16_sphere_1m.txt",
+    ("sphere_1m", "mixed", "fp32"): "cheb_step_sphere_1m_hbm_bytes.txt",
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2112_07862_amd", "csrc", f)
                   for f in ("slot_ops.hip", "rowops.h", "engine.h", "common.h")]
@@ -160,7 +161,7 @@ def generate(main_spec, batch_count: int, serve_count: int, workers: int = 16):
 
 
 def batch_leg(me, specs, graphs, precision: str, cheb_degree: int, steps: int,
-              warmup: int) -> dict:
+              warmup: int, launch: str = "auto") -> dict:
     """Batched mix: every graph embedded by one batched call per step
     (mixed precision); beside it the plain FP64 single-graph path (one me.embed
     per graph, FP64) on every 8th graph of the same mix."""
@@ -169,7 +170,7 @@ def batch_leg(me, specs, graphs, precision: str, cheb_degree: int, steps: int,
     dev = [me.to_device(g) for g in graphs]
     torch.cuda.synchronize()
     total_n = sum(g.n for g in graphs)
-    opts = dict(precision=precision, seed=0, cheb_degree=cheb_degree)
+    opts = dict(precision=precision, seed=0, cheb_degree=cheb_degree, launch=launch)
     tol = 1e-6
     for w in range(warmup):
         t = time.perf_counter()
@@ -266,6 +267,97 @@ def serve_run(me, specs, dev, ns, rate: float, precision: str, cheb_degree: int)
     return out
 
 
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def _events_ms(fn, reps: int = 1):
+    """Milliseconds of fn() on the current stream, HIP events around it."""
+    import torch
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        r = fn()
+    b.record(st)
+    b.synchronize()
+    return a.elapsed_time(b) / reps, r
+
+
+def knn_leg(me, points_by_name: dict) -> dict:
+    """GPU kNN graph construction (exact brute force) of the workloads' point
+    sets; checked against the input generator's graph of the same points.
+    The distance kernel is bound by FP64 vector arithmetic: per pair, dim
+    subtractions, dim products and dim - 1 additions."""
+    import torch
+    out = {}
+    for name, (x, k, g) in points_by_name.items():
+        pts = torch.as_tensor(x, device="cuda")
+        me.knn_graph(pts, k)  # warm-up
+        ms, (csr, sigma) = _events_ms(lambda: me.knn_graph(pts, k))
+        n, dim = x.shape
+        same = bool(np.array_equal(csr.rowptr.cpu().numpy(), g.rowptr)
+                    and np.array_equal(csr.col.cpu().numpy(), g.col))
+        flops = float(n) * float(n - 1) * (3 * dim - 1)
+        tf = flops / (ms * 1e-3) / 1e12
+        out[name] = {"n": int(n), "dim": int(dim), "k": int(k), "ms": ms,
+                     "points_per_s": n / (ms * 1e-3), "nnz": int(csr.nnz),
+                     "same_graph_as_generator": same,
+                     "roofline": {"bound": "alu", "achieved": tf,
+                                  "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": tf / FP64_VECTOR_PEAK_TFLOPS,
+                                  "note": "whole call (distances, selection, union); the "
+                                          "distance arithmetic has no fused multiply-adds, "
+                                          "so half the FMA peak is its ceiling"}}
+        print(f"[bench] knn {name}: {ms:.1f} ms, {tf:.1f} TFLOP/s, same graph {same}",
+              file=sys.stderr, flush=True)
+        del pts, csr
+    return out
+
+
+def vbc_leg(me, graphs_by_name: dict) -> dict:
+    """Betweenness centrality and its variance (the manifold-graph check):
+    n breadth-first searches with path counts and the accumulation, about
+    4 nnz edge visits per source."""
+    out = {}
+    for name, g in graphs_by_name.items():
+        d = me.to_device(g)
+        me.betweenness(d)
+        ms, (cb, v) = _events_ms(lambda: me.betweenness(d))
+        ev = 4.0 * g.n * g.nnz
+        out[name] = {"n": int(g.n), "nnz": int(g.nnz), "ms": ms, "vbc": v,
+                     "edge_visits_per_s": ev / (ms * 1e-3)}
+        print(f"[bench] betweenness {name}: {ms:.1f} ms, VBC {v:.4g}", file=sys.stderr,
+              flush=True)
+    return out
+
+
+def cluster_leg(me, per_square: int = 30000) -> dict:
+    """Section 5.1's evaluation on a labelled synthetic manifold: three unit
+    squares side by side, one 10-NN graph, embedded with K = 3 on the GPU;
+    k-means and GMM into 3 clusters; RI, Precision, Purity and NMI of each
+    and their average (Table 3's convention)."""
+    import torch
+    import synthgraphs as sg
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.random((per_square, 2)) + np.array([1.0 * q, 0.0])
+                        for q in range(3)])
+    y = torch.as_tensor(np.repeat(np.arange(3), per_square), device="cuda")
+    g = sg.knn_graph(x, 10)
+    X, lam, info = me.embed(g, 3, tol=1e-6, seed=0, precision="mixed")
+    u = [0.2, 0.5, 0.8]
+    me.kmeans(X, 3, u)
+    ms_k, (lab, cen, it_k) = _events_ms(lambda: me.kmeans(X, 3, u))
+    ms_g, (labg, w, mu, cov, ll, it_g) = _events_ms(lambda: me.gmm(X, 3, lab))
+    sk = me.cluster_scores(y, lab, 3, 3)
+    sgm = me.cluster_scores(y, labg, 3, 3)
+    avg = {k: (sk[k] + sgm[k]) / 2 for k in sk}
+    print(f"[bench] clustering: kmeans {ms_k:.1f} ms, gmm {ms_g:.1f} ms, average {avg}",
+          file=sys.stderr, flush=True)
+    return {"n": int(3 * per_square), "K": 3, "C": 3, "embed_status": info["status_name"],
+            "kmeans": {"ms": ms_k, "iterations": it_k, **sk},
+            "gmm": {"ms": ms_g, "iterations": it_g, **sgm}, "average": avg}
+
+
 def serve_leg(me, specs, graphs, rates, precision: str, cheb_degree: int) -> dict:
     """Serving: the same request stream (N log-uniform in [1000, 200000] on
     square / Swiss roll / sphere, 10-NN, K = 8, tol 1e-6) offered at several
@@ -307,7 +399,8 @@ def bench_batch(args) -> int:
     print(f"[bench] generating batch of {args.batch_count}", file=sys.stderr, flush=True)
     _, (specs, graphs), _ = generate(None, args.batch_count, 0)
     import paper_2112_07862_amd as me
-    b = batch_leg(me, specs, graphs, args.precision, args.cheb_degree, args.steps, args.warmup)
+    b = batch_leg(me, specs, graphs, args.precision, args.cheb_degree, args.steps, args.warmup,
+                  args.launch)
     out = envelope(args, b["nodes_per_s"], b["s_per_batch"] * 1e3, args.steps, args.warmup,
                    "f64" if args.precision == "fp64" else "f32+f64",
                    {k: b[k] for k in ("workload", "graphs", "total_nodes", "n_range", "knn",
@@ -350,6 +443,8 @@ def main() -> int:
     ap.add_argument("--cheb-iterates", default="fp32", choices=["fp32", "fp16"],
                     help="storage of the Chebyshev iterates (mixed precision)")
     ap.add_argument("--eps-tol", type=float, default=None)
+    ap.add_argument("--launch", default="auto", choices=["auto", "stream", "graph"],
+                    help="enqueue LOBPCG rounds kernel by kernel or as a replayed HIP graph")
     ap.add_argument("--cpu-sample-n", type=int, default=None,
                     help="nodes of the CPU oracle's sample graph (default per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -402,7 +497,7 @@ def main() -> int:
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     opts = dict(precision=args.precision, seed=0, cheb_degree=args.cheb_degree,
-                cheb_iterates=args.cheb_iterates)
+                cheb_iterates=args.cheb_iterates, launch=args.launch)
     if args.eps_tol is not None:
         opts["eps_tol"] = args.eps_tol
 
@@ -442,7 +537,7 @@ def main() -> int:
                    {"workload": args.workload, "manifold": kind, "n": n, "knn": knn, "K": K,
                     "tol": tol, "precision": args.precision, "preconditioner": "chebyshev",
                     "cheb_degree": args.cheb_degree, "cheb_iterates": args.cheb_iterates,
-                    "seed": 0})
+                    "launch": args.launch, "seed": 0})
     out.update({
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                        "p99": float(np.percentile(lat, 99) * 1e3),
@@ -499,6 +594,19 @@ def main() -> int:
         print("[bench] serving ...", file=sys.stderr, flush=True)
         out["serving"] = serve_leg(me, sspecs, sgraphs, args.serve_rates, "mixed",
                                    args.cheb_degree)
+        # the rows around the path: graph construction, the manifold check,
+        # the clustering of the embedding
+        import synthgraphs as sg
+        pts = {}
+        for wl in ("swiss_roll_100k", "sphere_1m"):
+            kd, nn, kk, _, _ = sg.CONFIGS[wl]
+            xp = sg.sample_points(kd, nn, np.random.default_rng(0))
+            pts[wl] = (xp, kk, g if wl == args.workload else sg.knn_graph(xp, kk))
+        out["knn"] = knn_leg(me, pts)
+        del pts
+        out["vbc"] = vbc_leg(me, {"square_2k": sg.manifold_graph("square", 2000, 8, 0),
+                                  "swiss_roll_20k": sg.manifold_graph("swiss_roll", 20_000, 10, 0)})
+        out["clustering"] = cluster_leg(me)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         cn = args.cpu_sample_n or CPU_SAMPLE_N.get(args.workload, 50_000)

@@ -93,6 +93,18 @@ enum { ME_ADDR_AUTO = 0, ME_ADDR_GLOBAL = 1 };
  * step is bound by HBM bandwidth), on Swiss rolls up to 40% (net loss).  The
  * converged pairs meet the same FP64 residual test either way. */
 enum { ME_ITER_FP32 = 0, ME_ITER_FP16 = 1 };
+/* How a round of LOBPCG iterations is enqueued: kernel by kernel on the
+ * stream (ME_LAUNCH_STREAM), or as a HIP graph of one iteration, captured
+ * once per set of active solves on a private stream and replayed
+ * (ME_LAUNCH_GRAPH).  ME_LAUNCH_AUTO (default) replays graphs for a solve
+ * of one graph of at most 16384 nodes, whose kernels are short enough for
+ * launch costs to matter (2000 nodes: 11% faster), and launches kernel by
+ * kernel otherwise (a batch re-captures whenever a graph finishes: 5%
+ * slower with graphs).  The same kernels with the same arguments run in
+ * the same order either way, so results are bitwise identical.  Calls given
+ * a caller workspace, and rounds whose kernels are being timed, always
+ * launch kernel by kernel. */
+enum { ME_LAUNCH_AUTO = 0, ME_LAUNCH_STREAM = 1, ME_LAUNCH_GRAPH = 2 };
 
 /* Input graph W (Section 3.1), CSR, device memory, owned by the caller and
  * only read during the call.  rowptr int64[n+1] (rowptr[0] = 0), col int32[nnz]
@@ -122,6 +134,7 @@ typedef struct {
                          embedding solve: ME_CHEB_LAPLACIAN (default) or ME_CHEB_FULL */
   int addressing;     /* ME_ADDR_AUTO (default) or ME_ADDR_GLOBAL                     */
   int cheb_iterates;  /* ME_ITER_FP32 (default) or ME_ITER_FP16                        */
+  int launch;         /* ME_LAUNCH_AUTO (default), ME_LAUNCH_STREAM or ME_LAUNCH_GRAPH */
 } me_opts;
 
 /* Per-solve report.  Times are host wall-clock milliseconds of the phases. */

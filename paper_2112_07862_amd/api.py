@@ -41,11 +41,12 @@ _PRECOND = {"none": L.ME_PRECOND_NONE, "jacobi": L.ME_PRECOND_JACOBI,
 _CHEB_OP = {"laplacian": L.ME_CHEB_LAPLACIAN, "full": L.ME_CHEB_FULL}
 _ADDRESSING = {"auto": L.ME_ADDR_AUTO, "global": L.ME_ADDR_GLOBAL}
 _ITERATES = {"fp32": L.ME_ITER_FP32, "fp16": L.ME_ITER_FP16}
+_LAUNCH = {"auto": L.ME_LAUNCH_AUTO, "stream": L.ME_LAUNCH_STREAM, "graph": L.ME_LAUNCH_GRAPH}
 
 
 def make_opts(precision="fp64", precond="chebyshev", max_iter=None, eps_max_iter=None,
               eps_tol=None, check_every=None, seed=None, cheb_degree=None,
-              cheb_op=None, addressing=None, cheb_iterates=None) -> L.MeOpts:
+              cheb_op=None, addressing=None, cheb_iterates=None, launch=None) -> L.MeOpts:
     o = L.MeOpts()
     L.load().me_opts_default(ctypes.byref(o))
     o.precision = _PRECISION[precision]
@@ -68,6 +69,8 @@ def make_opts(precision="fp64", precond="chebyshev", max_iter=None, eps_max_iter
         o.addressing = _ADDRESSING[addressing]
     if cheb_iterates is not None:
         o.cheb_iterates = _ITERATES[cheb_iterates]
+    if launch is not None:
+        o.launch = _LAUNCH[launch]
     return o
 
 

@@ -26,6 +26,8 @@ bool me::opts_valid(const me_opts& o) {
          o.eps_tol > 0 && (o.cheb_op == ME_CHEB_LAPLACIAN || o.cheb_op == ME_CHEB_FULL) &&
          (o.addressing == ME_ADDR_AUTO || o.addressing == ME_ADDR_GLOBAL) &&
          (o.cheb_iterates == ME_ITER_FP32 || o.cheb_iterates == ME_ITER_FP16) &&
+         (o.launch == ME_LAUNCH_AUTO || o.launch == ME_LAUNCH_STREAM ||
+          o.launch == ME_LAUNCH_GRAPH) &&
          (o.precond != ME_PRECOND_CHEBYSHEV ||
           (o.cheb_degree >= 2 && o.cheb_degree <= kMaxChebDegree));
 }
@@ -45,6 +47,7 @@ void me_opts_default(me_opts* o) {
   o->cheb_op = ME_CHEB_LAPLACIAN;
   o->addressing = ME_ADDR_AUTO;
   o->cheb_iterates = ME_ITER_FP32;
+  o->launch = ME_LAUNCH_AUTO;
 }
 
 const char* me_status_string(int st) {

@@ -282,6 +282,12 @@ class Engine {
   bool round_open_ = false;
   int round_length();
   bool sets_dirty_ = true;
+  // one iteration of every active set as a replayable graph (ME_LAUNCH_GRAPH)
+  int enqueue_round(int ce);
+  void drop_graph();
+  hipStream_t cap_s_ = nullptr;  // private capture stream
+  hipGraphExec_t gexec_ = nullptr;
+  int sets_ver_ = 0, gexec_ver_ = -1;
   size_t bytes_in_use_ = 0;
   int phase_ = 0, tag_ = 0;
 };

@@ -126,6 +126,8 @@ int Engine::init() {
 
 Engine::~Engine() {
   (void)hipStreamSynchronize(s_);
+  drop_graph();
+  if (cap_s_) (void)hipStreamDestroy(cap_s_);
   free_sets(&sets_);
   for (auto& h : sh_)
     if (h.used && h.own_ws && h.ws) heap_->release(h.ws, s_);
@@ -600,15 +602,66 @@ int Engine::begin_round() {
     std::sort(active_.begin(), active_.end());
     ME_TRY_STATUS(sets_for(active_, &sets_, 0));
     sets_dirty_ = false;
+    ++sets_ver_;
   }
   iter0_.resize(active_.size());
   for (size_t q = 0; q < active_.size(); ++q) iter0_[q] = h_ctrl_[active_[q]].iter;
   if (timed_) phase_ = ktimer_new_phase();
   tag_ = 0;
   const int ce = round_length();
-  for (int q = 0; q < ce; ++q)
-    for (auto& ts : sets_) iteration(ts);
+  ME_TRY_STATUS(enqueue_round(ce));
   round_open_ = true;
+  return ME_OK;
+}
+
+void Engine::drop_graph() {
+  if (gexec_) (void)hipGraphExecDestroy(gexec_);
+  gexec_ = nullptr;
+  gexec_ver_ = -1;
+}
+
+// ce iterations of every active set: kernel by kernel, or one captured
+// iteration replayed ce times (captured again whenever the active sets
+// change).  Captures run on a private stream (the caller's may be the
+// legacy default stream, which cannot be captured); the replays go to the
+// engine's stream.
+// Largest one-graph solve that ME_LAUNCH_AUTO replays as a graph.
+constexpr int64_t kGraphMaxRows = 16384;
+
+int Engine::enqueue_round(int ce) {
+  bool graph = o_.launch == ME_LAUNCH_GRAPH;
+  if (o_.launch == ME_LAUNCH_AUTO) {
+    int64_t rows = 0;
+    for (int id : active_) rows += hdev_[id].n;
+    graph = cap_ == 1 && rows <= kGraphMaxRows;
+  }
+  graph = graph && !heap_->region() && !(timed_ && ktimer_kind() != 0);
+  if (!graph) {
+    for (int q = 0; q < ce; ++q)
+      for (auto& ts : sets_) iteration(ts);
+    return ME_OK;
+  }
+  if (!gexec_ || gexec_ver_ != sets_ver_) {
+    drop_graph();
+    if (!cap_s_) ME_TRY(hipStreamCreateWithFlags(&cap_s_, hipStreamNonBlocking));
+    hipStream_t keep = s_;
+    s_ = cap_s_;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap_s_, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (auto& ts : sets_) iteration(ts);
+      e = hipStreamEndCapture(cap_s_, &g);
+    }
+    s_ = keep;
+    if (e == hipSuccess) e = hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      gexec_ = nullptr;
+      return ME_ERR_HIP;
+    }
+    gexec_ver_ = sets_ver_;
+  }
+  for (int q = 0; q < ce; ++q) ME_TRY(hipGraphLaunch(gexec_, s_));
   return ME_OK;
 }
 

@@ -470,3 +470,24 @@ def test_mixed_without_packed_entries(me):
     assert np.array_equal(_np(X3), X) and np.array_equal(_np(lam3), lam)
     h3.close()
     h.close()
+
+
+@pytest.mark.parametrize("name,K,precision", [("square_2k", 4, "fp64"), ("swiss_3k", 8, "mixed"),
+                                              ("sphere_3k", 16, "mixed"), ("tri_mesh", 3, "mixed")])
+def test_graph_launch_identical(me, name, K, precision):
+    """Rounds replayed as a captured HIP graph run the same kernels with the
+    same arguments: the same pairs bit for bit, in a single solve and in a
+    batch (whose active sets change as graphs finish, so the graph is
+    captured again)."""
+    g, _ = oracle_ops(name)
+    X1, l1, i1 = me.embed(g, K, tol=1e-8, seed=3, precision=precision, launch="stream")
+    X2, l2, i2 = me.embed(g, K, tol=1e-8, seed=3, precision=precision, launch="graph")
+    assert i1["status"] == i2["status"] and i1["iterations"] == i2["iterations"]
+    assert torch.equal(X1, X2) and torch.equal(l1, l2)
+    other = sg.manifold_graph("torus", 1500, 8, 21)
+    a = me.embed_batch([g, other], [K, 8], tol=1e-8, seed=3, precision=precision,
+                       launch="stream")
+    b = me.embed_batch([g, other], [K, 8], tol=1e-8, seed=3, precision=precision, launch="graph")
+    for (xa, la, ia), (xb, lb, ib) in zip(a, b):
+        assert ia["iterations"] == ib["iterations"]
+        assert torch.equal(xa, xb) and torch.equal(la, lb)
