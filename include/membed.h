@@ -106,6 +106,20 @@ enum { ME_ITER_FP32 = 0, ME_ITER_FP16 = 1 };
  * launch kernel by kernel. */
 enum { ME_LAUNCH_AUTO = 0, ME_LAUNCH_STREAM = 1, ME_LAUNCH_GRAPH = 2 };
 
+/* Precision of the product A W inside each LOBPCG iteration (Section 4.3
+ * names the method only).  ME_PRODUCT_FP64 (default): the difference-form
+ * product in FP64.  ME_PRODUCT_FP32 (ME_MIXED only): W is rounded to FP32 and
+ * multiplied in FP32 (FP32 weights), the result widened to FP64; AX and AP
+ * follow from it through the block updates.  X, the Grams, the Rayleigh-Ritz
+ * step and the certificate stay FP64, and a result is returned as converged
+ * only once the FP64 certificate accepts it.  Kept for measurement, not
+ * recommended: the 2000-node square converges (15 iterations against 14),
+ * but on the 3000-node Swiss roll the implicitly updated A X drifts away
+ * from A X and the solve never converges.  Applies to the embedding solve of
+ * me_embed and me_embed_batch; the eps solve keeps FP64 products, and a
+ * server rejects the option (ME_ERR_INVALID_ARG). */
+enum { ME_PRODUCT_FP64 = 0, ME_PRODUCT_FP32 = 1 };
+
 /* Input graph W (Section 3.1), CSR, device memory, owned by the caller and
  * only read during the call.  rowptr int64[n+1] (rowptr[0] = 0), col int32[nnz]
  * strictly increasing inside each row, val float64[nnz].  Must be symmetric
@@ -135,6 +149,10 @@ typedef struct {
   int addressing;     /* ME_ADDR_AUTO (default) or ME_ADDR_GLOBAL                     */
   int cheb_iterates;  /* ME_ITER_FP32 (default) or ME_ITER_FP16                        */
   int launch;         /* ME_LAUNCH_AUTO (default), ME_LAUNCH_STREAM or ME_LAUNCH_GRAPH */
+  int cholqr_passes;  /* B-orthonormalisations of the preconditioned block per
+                         iteration (projection off X, then CholQR): 1 (default)
+                         or 2 (CholQR2)                                            */
+  int product;        /* ME_PRODUCT_FP64 (default) or ME_PRODUCT_FP32             */
 } me_opts;
 
 /* Per-solve report.  Times are host wall-clock milliseconds of the phases. */
@@ -364,8 +382,8 @@ int me_kernel_timing(int kind);
 int me_kernel_timing_read(int64_t* launches, double* total_ms, double* bytes);
 
 /* ---- kNN graph of points (the step before the path) --------------------
- * The symmetric weighted graph of Section 5.1's kNN construction ("kNN
- * graphs ... based on Euclidean distances") with Gaussian weights:
+ * The symmetric weighted graph of Section 5.1's kNN construction (the k
+ * nearest neighbours by Euclidean distance) with Gaussian weights:
  *   - d2(i, j) = sum over coordinates, in order, of (x_id - x_jd)^2, each
  *     square a plain product (no fused multiply-add), FP64;
  *   - N_k(i) = the k points j != i of smallest d2(i, j), equal distances

@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Section 5.1 builds the kNN graphs of its face datasets "based on Euclidean
-distances" and says no more.  The workloads here add the weighting recipe of
+Section 5.1 builds the kNN graphs of its face datasets from Euclidean
+distances and gives no further detail.  The workloads here add the weighting recipe of
 their configurations.  Readings:
 
 K1  Distance: the squared Euclidean distance computed in FP64 as

@@ -22,6 +22,7 @@ ME_CHEB_LAPLACIAN, ME_CHEB_FULL = 0, 1
 ME_ADDR_AUTO, ME_ADDR_GLOBAL = 0, 1
 ME_ITER_FP32, ME_ITER_FP16 = 0, 1
 ME_LAUNCH_AUTO, ME_LAUNCH_STREAM, ME_LAUNCH_GRAPH = 0, 1, 2
+ME_PRODUCT_FP64, ME_PRODUCT_FP32 = 0, 1
 
 STATUS_NAMES = {
     0: "ME_OK", 1: "ME_WARN_NOT_CONVERGED", 2: "ME_WARN_EPS_ZERO", -1: "ME_ERR_INVALID_ARG",
@@ -40,7 +41,8 @@ class MeOpts(ctypes.Structure):
     _fields_ = [("precision", c_int), ("precond", c_int), ("max_iter", c_int),
                 ("eps_max_iter", c_int), ("eps_tol", c_double), ("check_every", c_int),
                 ("seed", c_uint64), ("cheb_degree", c_int), ("cheb_op", c_int),
-                ("addressing", c_int), ("cheb_iterates", c_int), ("launch", c_int)]
+                ("addressing", c_int), ("cheb_iterates", c_int), ("launch", c_int),
+                ("cholqr_passes", c_int), ("product", c_int)]
 
 
 class MeInfo(ctypes.Structure):

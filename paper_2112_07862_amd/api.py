@@ -42,11 +42,13 @@ _CHEB_OP = {"laplacian": L.ME_CHEB_LAPLACIAN, "full": L.ME_CHEB_FULL}
 _ADDRESSING = {"auto": L.ME_ADDR_AUTO, "global": L.ME_ADDR_GLOBAL}
 _ITERATES = {"fp32": L.ME_ITER_FP32, "fp16": L.ME_ITER_FP16}
 _LAUNCH = {"auto": L.ME_LAUNCH_AUTO, "stream": L.ME_LAUNCH_STREAM, "graph": L.ME_LAUNCH_GRAPH}
+_PRODUCT = {"fp64": L.ME_PRODUCT_FP64, "fp32": L.ME_PRODUCT_FP32}
 
 
 def make_opts(precision="fp64", precond="chebyshev", max_iter=None, eps_max_iter=None,
               eps_tol=None, check_every=None, seed=None, cheb_degree=None,
-              cheb_op=None, addressing=None, cheb_iterates=None, launch=None) -> L.MeOpts:
+              cheb_op=None, addressing=None, cheb_iterates=None, launch=None,
+              cholqr_passes=None, product=None) -> L.MeOpts:
     o = L.MeOpts()
     L.load().me_opts_default(ctypes.byref(o))
     o.precision = _PRECISION[precision]
@@ -71,6 +73,10 @@ def make_opts(precision="fp64", precond="chebyshev", max_iter=None, eps_max_iter
         o.cheb_iterates = _ITERATES[cheb_iterates]
     if launch is not None:
         o.launch = _LAUNCH[launch]
+    if cholqr_passes is not None:
+        o.cholqr_passes = int(cholqr_passes)
+    if product is not None:
+        o.product = _PRODUCT[product]
     return o
 
 

@@ -28,6 +28,8 @@ bool me::opts_valid(const me_opts& o) {
          (o.cheb_iterates == ME_ITER_FP32 || o.cheb_iterates == ME_ITER_FP16) &&
          (o.launch == ME_LAUNCH_AUTO || o.launch == ME_LAUNCH_STREAM ||
           o.launch == ME_LAUNCH_GRAPH) &&
+         (o.cholqr_passes == 1 || o.cholqr_passes == 2) &&
+         (o.product == ME_PRODUCT_FP64 || (o.product == ME_PRODUCT_FP32 && o.precision == ME_MIXED)) &&
          (o.precond != ME_PRECOND_CHEBYSHEV ||
           (o.cheb_degree >= 2 && o.cheb_degree <= kMaxChebDegree));
 }
@@ -48,6 +50,8 @@ void me_opts_default(me_opts* o) {
   o->addressing = ME_ADDR_AUTO;
   o->cheb_iterates = ME_ITER_FP32;
   o->launch = ME_LAUNCH_AUTO;
+  o->cholqr_passes = 1;
+  o->product = ME_PRODUCT_FP64;
 }
 
 const char* me_status_string(int st) {

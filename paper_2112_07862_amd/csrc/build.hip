@@ -1317,10 +1317,12 @@ __device__ __forceinline__ uint32_t pack_entry(int64_t row, int32_t col, double 
 __global__ void __launch_bounds__(kBlock) k_pack_perm(
     int64_t n, int64_t nnz_w, const int32_t* perm, const int32_t* iperm, const int64_t* woff,
     const int64_t* toff, const int64_t* w_rp, const int32_t* w_col, const double* w_val,
-    const int64_t* t_rp, const int32_t* t_col, const double* invt, int32_t* a_rp, int32_t* a_tp,
-    int32_t* a_col, double* a_w, float* a_w32, uint32_t* a_pk, int* max_offset) {
+    const int64_t* t_rp, const int32_t* t_col, const int32_t* t_cnt, const double* invt,
+    int32_t* a_rp, int32_t* a_tp, int32_t* a_col, double* a_w, float* a_w32, uint32_t* a_pk,
+    uint32_t* a_tq, int* max_offset, int* max_tcnt) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t far = 0;  // largest |column - row| of this row
+  int32_t tmax = 0;  // largest T_j over the row's two-hop columns
   if (i <= n) {
     const int64_t ws = woff[i], ts = nnz_w + toff[i];
     a_rp[i] = (int32_t)ws;
@@ -1345,16 +1347,27 @@ __global__ void __launch_bounds__(kBlock) k_pack_perm(
       const int64_t k = ts + (t - tb);
       const int32_t c = iperm[t_col[t]];
       const double q = invt[o] + invt[t_col[t]];
+      const int32_t tj = t_cnt[t_col[t]];
       a_col[k] = c;
       a_w[k] = q;
       a_w32[k] = (float)q;
       a_pk[k] = pack_entry(i, c, q);
+      int64_t dd = (int64_t)c - i;
+      dd = dd > 32767 ? 32767 : (dd < -32768 ? -32768 : dd);
+      a_tq[k - nnz_w] = (uint32_t)(uint16_t)(int16_t)dd | ((uint32_t)(tj & 0xffff) << 16);
       far = max(far, (int64_t)llabs((int64_t)c - i));
+      tmax = max(tmax, tj);
     }
   }
   int32_t f = far > INT32_MAX ? INT32_MAX : (int32_t)far;
-  for (int o = kWave / 2; o > 0; o >>= 1) f = max(f, __shfl_xor(f, o));
-  if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(max_offset, f);
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    f = max(f, __shfl_xor(f, o));
+    tmax = max(tmax, __shfl_xor(tmax, o));
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomicMax(max_offset, f);
+    atomicMax(max_tcnt, tmax);
+  }
 }
 
 // dst[i'] = src[perm[i']] for a double array and its FP32 copy
@@ -1364,7 +1377,7 @@ __global__ void k_gather_node(int64_t n, const int32_t* perm, const double* src,
   if (i >= n) return;
   const double v = src[perm[i]];
   dst[i] = v;
-  dst32[i] = (float)v;
+  if (dst32) dst32[i] = (float)v;
 }
 
 // r_i = sum_{j != i} |A_ij| = d_i + mu Q_ii; log r partial sums (fixed order).
@@ -1470,14 +1483,14 @@ size_t build_mem1_bytes(int64_t n, int64_t nnz) {
   b1 += Arena::round((n + 1) * 8) + Arena::round(n * 4);                            // t_rp, t_cnt
   b1 += 9 * Arena::round(n * 8) + 5 * Arena::round(n * 4);                          // per node
   b1 += 2 * Arena::round((n + 1) * 4);                                              // a_rp, a_tp
-  b1 += 3 * Arena::round(n * 4) + 4 * Arena::round(n * 8) + 4 * Arena::round(n * 4);  // solver order
+  b1 += 3 * Arena::round(n * 4) + 5 * Arena::round(n * 8) + 4 * Arena::round(n * 4);  // solver order
   b1 += 2 * Arena::round((n + 1) * 8);                                              // offsets
   b1 += Arena::round(sizeof(int) * 64);
   return b1;
 }
 
 size_t build_mem2_bytes(int64_t nnz, int64_t nnz_t) {
-  return Arena::round(nnz_t * 4 + 4) + Arena::round((nnz + nnz_t) * 4 + 4) +
+  return 2 * Arena::round(nnz_t * 4 + 4) + Arena::round((nnz + nnz_t) * 4 + 4) +
          Arena::round((nnz + nnz_t) * 8 + 8) + 2 * Arena::round((nnz + nnz_t) * 4 + 4);
 }
 
@@ -1565,6 +1578,7 @@ static int build_pre_a_impl(const me_csr* W, const me_opts* o, DevHeap& heap, hi
   g->b_s = ar.take<double>(n);
   g->dinv_s = ar.take<double>(n);
   g->pdinv_s = ar.take<double>(n);
+  g->invt_s = ar.take<double>(n);
   g->qinv32_s = ar.take<float>(n);
   g->b32_s = ar.take<float>(n);
   g->dinv32_s = ar.take<float>(n);
@@ -1643,6 +1657,7 @@ static int build_pre_a_impl(const me_csr* W, const me_opts* o, DevHeap& heap, hi
   g->a_w = ar2.take<double>(nnz + nnz_t + 1);
   g->a_w32 = ar2.take<float>(nnz + nnz_t + 1);
   g->a_pk = ar2.take<uint32_t>(nnz + nnz_t + 1);
+  g->a_tq = ar2.take<uint32_t>(nnz_t + 1);
   g->mem_bytes += b2;
 
   k_twohop_lds<<<grid_lds, kWave, 0, s>>>(n, g->w_rp, g->w_col, 1, g->t_cnt, g->t_rp, g->t_col,
@@ -1682,13 +1697,16 @@ int build_pre_b(GraphOps* g, hipStream_t s) {
   scan_counts(n, wlen, woff, tile_tmp, s);
   scan_counts(n, tlen, toff, tile_tmp, s);
   int* max_offset = g->dflags + 12;
+  int* max_tcnt = g->dflags + 13;
   k_pack_perm<<<ceil_div(n + 1, kBlock), kBlock, 0, s>>>(
       n, nnz, g->perm, g->iperm, woff, toff, g->w_rp, g->w_col, g->w_val, g->t_rp, g->t_col,
-      g->invt, g->a_rp, g->a_tp, g->a_col, g->a_w, g->a_w32, g->a_pk, max_offset);
+      g->t_cnt, g->invt, g->a_rp, g->a_tp, g->a_col, g->a_w, g->a_w32, g->a_pk, g->a_tq,
+      max_offset, max_tcnt);
   k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->qinv, g->qinv_s,
                                                        g->qinv32_s);
-  // roots (2), the mu denominator's bits (4, 5) and the largest offset (12)
-  // in one read
+  k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->invt, g->invt_s, nullptr);
+  // roots (2), the mu denominator's bits (4, 5), the largest offset (12) and
+  // the largest two-hop count of a column (13) in one read
   int hf[16];
   ME_TRY(hipMemcpyAsync(hf, g->dflags, sizeof(hf), hipMemcpyDeviceToHost, s));
   ME_TRY(hipStreamSynchronize(s));
@@ -1700,6 +1718,7 @@ int build_pre_b(GraphOps* g, hipStream_t s) {
   std::memcpy(&maxden, &hmaxden, 8);
   g->maxden = maxden;
   g->pk_ok = hf[12] <= 32767;
+  g->tq_ok = g->pk_ok && hf[13] <= 65535;
 
   g->needs_eps = !(hroots > 1 || n < 2);
   return ME_OK;

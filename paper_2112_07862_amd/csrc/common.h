@@ -211,6 +211,7 @@ struct GraphOps {
   int32_t max_level = 0;       // deepest level
   int32_t* iperm = nullptr;    // user index -> solver index
   double *qinv_s = nullptr, *b_s = nullptr, *dinv_s = nullptr, *pdinv_s = nullptr;
+  double* invt_s = nullptr;    // 1 / T_i in solver order (two-hop weights of the FP64 products)
   float *qinv32_s = nullptr, *b32_s = nullptr, *dinv32_s = nullptr, *pdinv32_s = nullptr;
   // difference-form operator in solver order: W entries of row i at [a_rp[i], a_rp[i+1]),
   // T entries at [a_tp[i], a_tp[i+1]) (all W entries precede all T entries)
@@ -224,6 +225,12 @@ struct GraphOps {
   // every |column - row| fits (pk_ok)
   uint32_t* a_pk = nullptr;
   bool pk_ok = false;
+  // the two-hop entries packed for the FP64 products: bits 0-15 the column
+  // minus the row (int16), bits 16-31 T_j of the column (the weight is
+  // 1/T_i + 1/T_j, formed on the fly); usable when offsets and counts fit
+  // (tq_ok).  Entry k of the T block (position nnz_w + k) is a_tq[k].
+  uint32_t* a_tq = nullptr;
+  bool tq_ok = false;
   double* scratch_d = nullptr;  // n doubles of build scratch
   int64_t *woff = nullptr, *toff = nullptr;  // row offsets of the packed blocks
   OrderArgs ord{};              // search arguments while the order is pending

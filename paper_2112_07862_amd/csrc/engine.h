@@ -43,6 +43,13 @@ struct SlotDev {
   int64_t nnz_ops;  // entries of a_col / a_w (W and T)
   const uint32_t* a_pk;  // packed entries of the FP32 preconditioner (pk_ok)
   int pk_ok;
+  // FP64 products with tq_ok read a two-hop entry as one packed word (column
+  // offset, T_j) at a_tq[position - tq_base] and form its weight 1/T_i + 1/T_j
+  // from invt (1 / T_i, solver order) and 1 / T_j
+  const double* invt;
+  const uint32_t* a_tq;
+  int64_t tq_base;
+  int tq_ok;
   double c_t, s_diag;
   const double* bdiag;  // null: B = I
   const double* dinv;   // diag(Op)^-1 (Jacobi preconditioner)

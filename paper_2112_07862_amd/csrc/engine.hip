@@ -208,6 +208,10 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
   d.nnz_ops = g.nnz_w + g.nnz_t + 1;
   d.a_pk = g.a_pk;
   d.pk_ok = g.pk_ok ? 1 : 0;
+  d.invt = g.invt_s;
+  d.a_tq = g.a_tq;
+  d.tq_base = g.nnz_w;
+  d.tq_ok = g.tq_ok ? 1 : 0;
   if (sp.op == OP_A) {
     d.c_t = -g.mu;
     d.s_diag = g.eps;
@@ -400,19 +404,23 @@ void Engine::iteration(const TileSet& ts) {
       for (int id : ts.ids) {
         const GraphOps& g = *sh_[id].sp.g;
         // algorithmic bytes of one step: every entry of the preconditioner's
-        // operator (packed: 4 B; else column index and weight), row bounds
-        // (8 B), D^-1_i, and the blocks y_k (neighbour rows counted once),
-        // y_{k-1}, R read and y_{k+1} written
+        // operator (packed: 4 B; else column index and weight; FP64 two-hop
+        // entries: the column, with 1/T_i per row), row bounds (8 B), D^-1_i,
+        // and the blocks y_k (neighbour rows counted once), y_{k-1}, R read
+        // and y_{k+1} written
         const double sz = cheb32_ ? 4.0 : 8.0;
         const double ent = (cheb32_ && ts.pk) ? 4.0 : 4.0 + sz;
+        const bool tq = !cheb32_ && g.tq_ok && kb <= 4;  // packed two-hop entries
+        const double ent_t = ((cheb32_ && ts.pk) || tq) ? 4.0 : 4.0 + sz;
         const int rg = hdev_[id].cheb_range;
-        const double nnz = rg == kRangeW ? (double)g.nnz_w
-                                         : (rg == kRangeT ? (double)g.nnz_t
-                                                          : (double)(g.nnz_w + g.nnz_t));
+        const double nw = rg == kRangeT ? 0.0 : (double)g.nnz_w;
+        const double nt = rg == kRangeW ? 0.0 : (double)g.nnz_t;
+        const double tin = (tq && nt > 0.0) ? 8.0 * (double)g.n : 0.0;
         if (h16)  // y_k, y_{k-1} read and y_{k+1} written in FP16, R in FP32
-          cb += 4.0 * nnz + (double)g.n * 12.0 + 10.0 * (double)g.n * kb;
+          cb += 4.0 * (nw + nt) + (double)g.n * 12.0 + 10.0 * (double)g.n * kb;
         else
-          cb += ent * nnz + (double)g.n * (8.0 + sz) + 4.0 * (double)g.n * kb * sz;
+          cb += ent * nw + ent_t * nt + tin + (double)g.n * (8.0 + sz) +
+                4.0 * (double)g.n * kb * sz;
       }
     }
     const int w = cheb32_ ? BW32 : BW, y = cheb32_ ? BY32 : BY;
@@ -441,8 +449,8 @@ void Engine::iteration(const TileSet& ts) {
     else if (cheb32_) sl_to64(d_slots_, ts, BW32, BW, s_);
   }
   sl_deflate(d_slots_, ts, BW, 0, s_);
-  // W <- (W - X C) R^-1
-  {
+  // W <- (W - X C) R^-1, once, or twice (CholQR2)
+  for (int pass = 0; pass < o_.cholqr_passes; ++pass) {
     const int u[2] = {BX, BW}, v[1] = {BW}, o[1] = {BW};
     sl_gram(d_slots_, ts, 2, u, 1, v, 0, nullptr, 1, 0, s_);
     sl_reduce(d_slots_, ts, 2 * kb * kb, 0, s_);
@@ -453,15 +461,24 @@ void Engine::iteration(const TileSet& ts) {
   if (tm) {
     for (int id : ts.ids) {
       const GraphOps& g = *sh_[id].sp.g;
-      // column index and weight of every entry, row bounds, x in, y out
-      sb += 12.0 * (double)(g.nnz_w + g.nnz_t) + (double)g.n * 8.0 +
-            2.0 * (double)g.n * kb * 8.0;
+      // column index and weight of every one-hop entry, the packed word of
+      // every two-hop entry (its weight is 1/T_i + 1/T_j) with 1/T_i per row
+      // (else column index and weight), row bounds, x in, y out
+      const bool tq = g.tq_ok && kb <= 4;
+      sb += 12.0 * (double)g.nnz_w + (tq ? 4.0 : 12.0) * (double)g.nnz_t +
+            (double)g.n * (tq ? 16.0 : 8.0) + 2.0 * (double)g.n * kb * 8.0;
       blk += (double)g.n * kb * 8.0;
     }
   }
   {
     KScope ks(tm ? KT_SPMM_A : -1, s_, sb, tag_);
-    sl_spmm<double>(d_slots_, ts, BW, BAW, 0, s_);
+    if (o_.product == ME_PRODUCT_FP32) {  // W rounded to FP32, product in FP32
+      sl_to32(d_slots_, ts, BW, BY32, s_);
+      sl_spmm<float>(d_slots_, ts, BY32, BR32, 0, s_);
+      sl_to64(d_slots_, ts, BR32, BAW, s_);
+    } else {
+      sl_spmm<double>(d_slots_, ts, BW, BAW, 0, s_);
+    }
   }
   const int m = 3 * kb;
   const int S[3] = {BX, BW, BP}, AS[3] = {BAX, BAW, BAP};

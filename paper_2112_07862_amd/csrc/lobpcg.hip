@@ -117,11 +117,20 @@ size_t eps_solve_bytes(int64_t n) {
   return Engine::run_bytes({{n, 4}});
 }
 
+// Options of an eps solve: the embedding solve's, with the product in FP64
+// (the FP32 product option concerns the embedding solve only).
+static me_opts eps_opts(const me_opts& o) {
+  me_opts e = o;
+  e.product = ME_PRODUCT_FP64;
+  return e;
+}
+
 int solve_eps(GraphOps& g, const me_opts* o, DevHeap& heap, hipStream_t s, double* eps,
               int* iters) {
   *iters = 0;
   if (g.n <= kDenseMaxN) return dense_eps_solve(g, heap, s, eps);
-  Engine e(s, *o, 1, false, false, &heap, Engine::tile_area_bytes(Engine::tile_bytes(g.n, 4)));
+  const me_opts eo = eps_opts(*o);
+  Engine e(s, eo, 1, false, false, &heap, Engine::tile_area_bytes(Engine::tile_bytes(g.n, 4)));
   ME_TRY_STATUS(e.init());
   int id = -1;
   ME_TRY_STATUS(e.add(eps_slot_spec(g, o), nullptr, 0, &id));
@@ -315,7 +324,8 @@ int embed_batch(int G, const me_csr* Ws, const int* Ks, double tol, const me_opt
     std::vector<std::pair<int64_t, int>> slots;
     for (int i = 0; i < G; ++i)
       if (st[i] >= 0 && gs[i].needs_eps && gs[i].n > kDenseMaxN) slots.push_back({gs[i].n, 4});
-    Engine e(s, *o, std::max((int)slots.size(), 1), false, false, &heap, sum_tiles(slots));
+    const me_opts eo = eps_opts(*o);
+    Engine e(s, eo, std::max((int)slots.size(), 1), false, false, &heap, sum_tiles(slots));
     ME_TRY_STATUS(e.init());
     std::vector<int> id(G, -1);
     for (int i = 0; i < G; ++i) {

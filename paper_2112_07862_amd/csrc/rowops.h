@@ -177,12 +177,20 @@ __device__ __forceinline__ RowSpan row_span(bool live, int64_t row,
 // span; an entry past the span loads column 0 and weight 0 (out-of-range
 // loads) and adds 0 * (x_i - x_0).  Loop counts are per lane.  RANGE fixes
 // the entry kinds at compile time (kRangeW: W only, kRangeT: T only) or
-// leaves them to the span (-1).
+// leaves them to the span (-1).  In FP64 with tq (two-hop entries packed as
+// column offset and T_j in rq, entry position minus tq_base), a T entry is
+// one 4-byte load and its weight is formed as ti + 1 / T_j: the same two
+// doubles the stored weight was summed from (1 / T_j correctly rounded), so
+// the products equal those over the stored weights bit for bit.  An entry
+// past the span loads 0: offset 0 (the row itself), weight 0.
 template <typename T, int KB, int RANGE = -1>
 __device__ __forceinline__ void spmm_span_buf(int32_t ws, int32_t nw, int32_t ts, int32_t len,
-                                              int q, BufRsrc rc, BufRsrc rw, BufRsrc rx,
-                                              T c_t, const T (&xi)[RowCfg<T, KB>::V16],
+                                              int q, int64_t rs, BufRsrc rc, BufRsrc rw,
+                                              BufRsrc rq, uint32_t tq_base, bool tq, T ti,
+                                              BufRsrc rx, T c_t,
+                                              const T (&xi)[RowCfg<T, KB>::V16],
                                               T (&acc)[RowCfg<T, KB>::V16]) {
+  constexpr bool TQ = sizeof(T) == 8;
   using C = RowCfg<T, KB>;
   constexpr int V = C::V16, EPL = C::EPL, UNR = C::UNR;
   const int ch = q % C::NCH, e0 = q / C::NCH;
@@ -196,17 +204,14 @@ __device__ __forceinline__ void spmm_span_buf(int32_t ws, int32_t nw, int32_t ts
     for (int u = 0; u < UNR; ++u) {
       const int32_t k = (r + u) * EPL + e0;
       const bool ok = r + u < mine;
-      if constexpr (RANGE == kRangeW) {
-        const uint32_t at = (uint32_t)(ws + k);
-        c[u] = buf_i32(rc, ok ? at * 4u : kBufOut);
-        cf[u] = buf_scalar<T>(rw, ok ? at * (uint32_t)sizeof(T) : kBufOut);
-      } else if constexpr (RANGE == kRangeT) {
-        const uint32_t at = (uint32_t)(ts + k);
-        c[u] = buf_i32(rc, ok ? at * 4u : kBufOut);
-        cf[u] = c_t * buf_scalar<T>(rw, ok ? at * (uint32_t)sizeof(T) : kBufOut);
+      const bool isw = RANGE == kRangeW ? true : (RANGE == kRangeT ? false : k < nw);
+      const uint32_t at = (uint32_t)((isw ? ws : ts) + k);
+      if (TQ && tq && !isw) {
+        const uint32_t pv = (uint32_t)buf_i32(rq, ok ? (at - tq_base) * 4u : kBufOut);
+        c[u] = (int32_t)rs + (int32_t)(int16_t)(pv & 0xffffu);
+        const T tj = (T)(pv >> 16);
+        cf[u] = ok ? c_t * (ti + (T)1 / tj) : (T)0;
       } else {
-        const bool isw = k < nw;
-        const uint32_t at = (uint32_t)((isw ? ws : ts) + k);
         c[u] = buf_i32(rc, ok ? at * 4u : kBufOut);
         const T w = buf_scalar<T>(rw, ok ? at * (uint32_t)sizeof(T) : kBufOut);
         cf[u] = isw ? w : c_t * w;

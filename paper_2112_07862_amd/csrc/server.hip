@@ -437,7 +437,8 @@ int me_server_create(const me_server_opts* so, void* stream, me_server** out) {
   *out = nullptr;
   me_server_opts o;
   if (so) o = *so; else me_server_opts_default(&o);
-  if (o.max_active < 1 || !me::opts_valid(o.opts)) return ME_ERR_INVALID_ARG;
+  if (o.max_active < 1 || !me::opts_valid(o.opts) || o.opts.product != ME_PRODUCT_FP64)
+    return ME_ERR_INVALID_ARG;
   // a region must hold at least the tables and the work-list areas
   if (o.workspace && o.mem_budget < ((size_t)4 << 20)) return ME_ERR_WORKSPACE;
   auto* h = new (std::nothrow) me_server();

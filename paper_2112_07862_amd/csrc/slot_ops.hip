@@ -25,6 +25,14 @@
 
 namespace me {
 
+// FP64 rows of at most two 16-byte chunks (block width 4: the eps solve)
+// read the packed two-hop entries (measured faster there: 78 against 87 us
+// for the 1M sphere's Q product); wider rows repeat the entry decode, a
+// correctly rounded 1 / T_j, in every chunk lane and read the stored weight
+// instead (692 against 536-600 us at width 16).
+template <typename T, int KB>
+constexpr bool kTqRows = sizeof(T) == 8 && RowCfg<T, KB>::NCH <= 2;
+
 template <typename T>
 struct SB;
 template <>
@@ -82,9 +90,17 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_spmm(const Slot
 #pragma unroll
     for (int v = 0; v < C::V16; ++v) xi[v] = own.v[v];
     const RowSpan sp = row_span(live, row, d.a_rp, d.a_tp, d.range);
-    spmm_span_buf<T, KB>(sp.ws, sp.nw, sp.ts, sp.len, q, buf_rsrc(d.a_col, d.nnz_ops * 4),
-                         buf_rsrc(SB<T>::w(d), d.nnz_ops * (int64_t)sizeof(T)), rx, (T)d.c_t,
-                         xi, acc);
+    const int64_t rs = live ? row : 0;
+    BufRsrc rq{};
+    T ti = 0;
+    const bool tq = kTqRows<T, KB> && d.tq_ok;
+    if (tq) {
+      rq = buf_rsrc(d.a_tq, (d.nnz_ops - d.tq_base) * 4);
+      ti = (T)glob(d.invt)[rs];
+    }
+    spmm_span_buf<T, KB>(sp.ws, sp.nw, sp.ts, sp.len, q, rs, buf_rsrc(d.a_col, d.nnz_ops * 4),
+                         buf_rsrc(SB<T>::w(d), d.nnz_ops * (int64_t)sizeof(T)), rq,
+                         (uint32_t)d.tq_base, tq, ti, rx, (T)d.c_t, xi, acc);
   } else {
     load_chunk<T, C::V16>(x + (live ? row : 0) * KB + ch * C::V16, xi);
     spmm_row<T, KB>(live, row, q, d.a_rp, d.a_tp, d.a_col, SB<T>::w(d), (T)d.c_t, d.range, x,
@@ -113,6 +129,7 @@ void sl_spmm(const SlotDev* sl, const TileSet& ts, int in, int out, int cert, hi
   });
 }
 template void sl_spmm<double>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
+template void sl_spmm<float>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Chebyshev preconditioner: approximate solve of Op y = R with Jacobi
@@ -156,6 +173,10 @@ struct ChebView {
   const uint32_t* a_pk;
   const T *a_w, *cdinv, *yin, *r;
   T* yout;
+  const double* invt;      // 1 / T_i in solver order (FP64 two-hop weights)
+  const uint32_t* a_tq;    // packed two-hop entries of the FP64 form (tq_ok)
+  int64_t tq_base;
+  int tq_ok;
   const double *alpha, *beta;
   const int* done;
   double c_t, s_diag;
@@ -176,6 +197,10 @@ __device__ __forceinline__ ChebView<T> cheb_view(const SlotDev& d, int r, int yi
   v.yin = SB<T>::blk(d, yin);
   v.r = SB<T>::blk(d, r);
   v.yout = SB<T>::blk(d, yout);
+  v.invt = d.invt;
+  v.a_tq = d.a_tq;
+  v.tq_base = d.tq_base;
+  v.tq_ok = d.tq_ok;
   v.alpha = d.cheb->alpha;
   v.beta = d.cheb->beta;
   v.done = &d.ctrl->done;
@@ -218,9 +243,17 @@ __device__ __forceinline__ void cheb_step_rows(const ChebView<T>& d, int64_t row
     spmm_span_pk<KB, RANGE, true>(sp.ws, sp.nw, sp.ts, sp.len, q, rs, d.a_pk, d.nnz_ops, d.yin,
                                   d.n, (float)d.c_t, yi, acc);
   } else {
-    spmm_span_buf<T, KB, RANGE>(sp.ws, sp.nw, sp.ts, sp.len, q, buf_rsrc(d.a_col, d.nnz_ops * 4),
-                                buf_rsrc(d.a_w, d.nnz_ops * (int64_t)sizeof(T)), rx, (T)d.c_t,
-                                yi, acc);
+    BufRsrc rq{};
+    T ti = 0;
+    const bool tq = kTqRows<T, KB> && d.tq_ok;
+    if (tq) {
+      rq = buf_rsrc(d.a_tq, (d.nnz_ops - d.tq_base) * 4);
+      ti = (T)glob(d.invt)[rs];
+    }
+    spmm_span_buf<T, KB, RANGE>(sp.ws, sp.nw, sp.ts, sp.len, q, rs,
+                                buf_rsrc(d.a_col, d.nnz_ops * 4),
+                                buf_rsrc(d.a_w, d.nnz_ops * (int64_t)sizeof(T)), rq,
+                                (uint32_t)d.tq_base, tq, ti, rx, (T)d.c_t, yi, acc);
   }
   if (!live || q >= C::NCH) return;
   // lane q < NCH updates chunk q of the row
@@ -329,6 +362,10 @@ static ChebView<T> cheb_view_host(const SlotDev& d, int r, int yin, int yout) {
     v.r = d.b32[r];
     v.yout = d.b32[yout];
   }
+  v.invt = d.invt;
+  v.a_tq = d.a_tq;
+  v.tq_base = d.tq_base;
+  v.tq_ok = d.tq_ok;
   v.alpha = (const double*)((const char*)d.cheb + offsetof(ChebCoef, alpha));
   v.beta = (const double*)((const char*)d.cheb + offsetof(ChebCoef, beta));
   v.done = (const int*)((const char*)d.ctrl + offsetof(Ctrl, done));
@@ -721,10 +758,15 @@ struct Ids {
 // Grams of one reduction tile, G1 = U^T diag(b) V and G2 = U^T V2, where V's
 // blocks are blocks of U (vsel[i] = position in U of V's block i).  Each wave
 // takes 16-row chunks (rows r0 + 16 wave, + 16 NW, ...): it stages the chunk
-// of every U and V2 block in its own LDS area with one contiguous load per
-// block (a 16-row chunk of a row-major n x KB block is 16 KB contiguous
-// doubles), then feeds the FP64 MFMA 16x16x4 from LDS.  The waves' sums are
-// added in wave order in LDS and written as the tile's partial.
+// of every U and V2 block in its own LDS area (a 16-row chunk of a row-major
+// n x KB block is 16 KB contiguous doubles: one contiguous load per block),
+// requests the next chunk into registers, and feeds the FP64 MFMA 16x16x4
+// from LDS while those loads are in flight.  SYM (V = U, V2 = A U: both Grams
+// symmetric) computes only the 16x16 tiles on and above the diagonal and
+// mirrors them, so both triangles of an off-diagonal tile hold the same sums.
+// The waves' sums are added in wave order in LDS and written as the tile's
+// partial.
+constexpr int kGramThreads = 512;
 template <int KB, int NU, int NV, int NV2>
 struct GramCfg {
   static constexpr int MU = NU * KB, MV = NV * KB, MV2 = NV2 * KB;
@@ -732,7 +774,7 @@ struct GramCfg {
   static constexpr int E1 = MU * MV, E2 = MU * MV2;
   static constexpr int NB = NU + NV2;         // staged blocks
   static constexpr int LD = NB * KB + 1;      // LDS row stride (doubles)
-  static constexpr int NW = kBlock / kWave;
+  static constexpr int NW = kGramThreads / kWave;
   static constexpr int WAVE_LDS = 16 * LD + 16;  // chunk + row weights
   static constexpr int LDS = NW * WAVE_LDS > E1 + E2 ? NW * WAVE_LDS : E1 + E2;
   static constexpr int EPL = KB / 4;          // doubles per lane when staging
@@ -744,13 +786,14 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int KB, int NU, int NV, int NV2>
-__global__ void __launch_bounds__(kBlock) k_sl_gram(const SlotDev* __restrict__ sl,
-                                                    const Tile* __restrict__ tiles, Ids u, Ids vsel,
-                                                    Ids v2, int use_b, int cert) {
+template <int KB, int NU, int NV, int NV2, bool SYM>
+__global__ void __launch_bounds__(kGramThreads) k_sl_gram(const SlotDev* __restrict__ sl,
+                                                          const Tile* __restrict__ tiles, Ids u,
+                                                          Ids vsel, Ids v2, int use_b, int cert) {
   using C = GramCfg<KB, NU, NV, NV2>;
   constexpr int MU = C::MU, MV = C::MV, MV2 = C::MV2, TU = C::TU, TV = C::TV, TV2 = C::TV2;
-  constexpr int E1 = C::E1, E2 = C::E2, LD = C::LD, NW = C::NW, EPL = C::EPL;
+  constexpr int E1 = C::E1, E2 = C::E2, LD = C::LD, NW = C::NW, EPL = C::EPL, NB = C::NB;
+  static_assert(!SYM || (NU == NV && (NV2 == 0 || NV2 == NU)), "symmetric Grams are square");
   using Acc = typename Mfma<double>::Acc;
   __shared__ double lds[C::LDS];
   const Tile t = tiles[blockIdx.x];
@@ -769,7 +812,7 @@ __global__ void __launch_bounds__(kBlock) k_sl_gram(const SlotDev* __restrict__ 
   const int64_t r0 = (int64_t)t.blk * d.per;
   const int64_t r1 = r0 + d.per < d.n ? r0 + d.per : d.n;
   const double* wd = use_b ? d.bdiag : nullptr;
-  const double* bp[C::NB];
+  const double* bp[NB];
 #pragma unroll
   for (int i = 0; i < NU; ++i) bp[i] = d.b64[u.v[i]];
 #pragma unroll
@@ -784,22 +827,32 @@ __global__ void __launch_bounds__(kBlock) k_sl_gram(const SlotDev* __restrict__ 
   }
   double* st = lds + wave * C::WAVE_LDS;
   const int se = lane * EPL, sr = se / KB, sc = se % KB;  // staging: row, column
-  for (int64_t base = r0 + 16 * wave; base < r1; base += 16 * NW) {
+  // one chunk's share of this lane: EPL doubles of each block, a row weight
+  VecT<double, EPL> nx[NB];
+  double nwt = 0.0;
+  auto fetch = [&](int64_t base) {
     const bool ok = base + sr < r1;
 #pragma unroll
-    for (int bi = 0; bi < C::NB; ++bi) {
-      VecT<double, EPL> x;
+    for (int bi = 0; bi < NB; ++bi) {
       if (ok) {
-        x = ldv<double, EPL>(bp[bi] + (base + sr) * KB + sc);
+        nx[bi] = ldv<double, EPL>(bp[bi] + (base + sr) * KB + sc);
       } else {
 #pragma unroll
-        for (int q = 0; q < EPL; ++q) x.v[q] = 0.0;
+        for (int q = 0; q < EPL; ++q) nx[bi].v[q] = 0.0;
       }
-#pragma unroll
-      for (int q = 0; q < EPL; ++q) st[sr * LD + bi * KB + sc + q] = x.v[q];
     }
-    if (lane < 16)
-      st[16 * LD + lane] = (base + lane < r1) ? (wd ? glob(wd)[base + lane] : 1.0) : 0.0;
+    if (lane < 16) nwt = (base + lane < r1) ? (wd ? glob(wd)[base + lane] : 1.0) : 0.0;
+  };
+  int64_t base = r0 + 16 * wave;
+  if (base < r1) fetch(base);
+  for (; base < r1; base += 16 * NW) {
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+      for (int q = 0; q < EPL; ++q) st[sr * LD + bi * KB + sc + q] = nx[bi].v[q];
+    }
+    if (lane < 16) st[16 * LD + lane] = nwt;
+    if (base + 16 * NW < r1) fetch(base + 16 * NW);  // in flight during the MFMAs
     wave_lds_sync();
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
@@ -817,9 +870,11 @@ __global__ void __launch_bounds__(kBlock) k_sl_gram(const SlotDev* __restrict__ 
 #pragma unroll
       for (int a = 0; a < TU; ++a) {
 #pragma unroll
-        for (int b = 0; b < TV; ++b) acc1[a][b] = Mfma<double>::step(ua[a], vb[b], acc1[a][b]);
+        for (int b = 0; b < TV; ++b)
+          if (!SYM || b >= a) acc1[a][b] = Mfma<double>::step(ua[a], vb[b], acc1[a][b]);
 #pragma unroll
-        for (int b = 0; b < TV2; ++b) acc2[a][b] = Mfma<double>::step(ua[a], v2b[b], acc2[a][b]);
+        for (int b = 0; b < TV2; ++b)
+          if (!SYM || b >= a) acc2[a][b] = Mfma<double>::step(ua[a], v2b[b], acc2[a][b]);
       }
     }
     wave_lds_sync();  // the chunk is read before the next one overwrites it
@@ -836,18 +891,26 @@ __global__ void __launch_bounds__(kBlock) k_sl_gram(const SlotDev* __restrict__ 
           if (i >= MU) continue;
 #pragma unroll
           for (int b = 0; b < TV; ++b) {
+            if (SYM && b < a) continue;
             const int j = 16 * b + li;
             if (j < MV) {
               const double val = acc1[a][b][q];
               if (wv == 0) sh[i * MV + j] = val; else sh[i * MV + j] += val;
+              if (SYM && b > a) {
+                if (wv == 0) sh[j * MV + i] = val; else sh[j * MV + i] += val;
+              }
             }
           }
 #pragma unroll
           for (int b = 0; b < TV2; ++b) {
+            if (SYM && b < a) continue;
             const int j = 16 * b + li;
             if (j < MV2) {
               const double val = acc2[a][b][q];
               if (wv == 0) sh[E1 + i * MV2 + j] = val; else sh[E1 + i * MV2 + j] += val;
+              if (SYM && b > a) {
+                if (wv == 0) sh[E1 + j * MV2 + i] = val; else sh[E1 + j * MV2 + i] += val;
+              }
             }
           }
         }
@@ -856,7 +919,7 @@ __global__ void __launch_bounds__(kBlock) k_sl_gram(const SlotDev* __restrict__ 
     __syncthreads();
   }
   double* out = d.partials + (int64_t)t.blk * (E1 + E2);
-  for (int e = tid; e < E1 + E2; e += kBlock) out[e] = sh[e];
+  for (int e = tid; e < E1 + E2; e += kGramThreads) out[e] = sh[e];
 }
 
 void sl_gram(const SlotDev* sl, const TileSet& ts, int nu, const int* u, int nv, const int* v,
@@ -865,26 +928,30 @@ void sl_gram(const SlotDev* sl, const TileSet& ts, int nu, const int* u, int nv,
   Ids iu{{0, 0, 0}}, iv{{0, 0, 0}}, iv2{{0, 0, 0}};
   for (int i = 0; i < nu; ++i) iu.v[i] = u[i];
   // V's blocks are blocks of U: pass their positions in U
+  bool same = nv == nu;
   for (int i = 0; i < nv; ++i) {
     iv.v[i] = -1;
     for (int j = 0; j < nu; ++j)
       if (u[j] == v[i]) iv.v[i] = j;
     if (iv.v[i] < 0) std::abort();  // no caller asks for a V outside U
+    same = same && iv.v[i] == i;
   }
   for (int i = 0; i < nv2; ++i) iv2.v[i] = v2[i];
-#define ME_SL_GRAM(NU_, NV_, NV2_)                                                           \
-  if (nu == NU_ && nv == NV_ && nv2 == NV2_) {                                               \
+#define ME_SL_GRAM(NU_, NV_, NV2_, SYM_)                                                    \
+  if (nu == NU_ && nv == NV_ && nv2 == NV2_ && (!(SYM_) || same)) {                          \
     ME_DISPATCH_KB(ts.kb, {                                                                  \
-      k_sl_gram<KB, NU_, NV_, NV2_><<<ts.n_red, kBlock, 0, s>>>(sl, ts.red, iu, iv, iv2,     \
-                                                                use_b, cert);                \
+      k_sl_gram<KB, NU_, NV_, NV2_, SYM_><<<ts.n_red, kGramThreads, 0, s>>>(                 \
+          sl, ts.red, iu, iv, iv2, use_b, cert);                                             \
     });                                                                                      \
     return;                                                                                  \
   }
-  ME_SL_GRAM(2, 1, 0)  // [X W]^T B W
-  ME_SL_GRAM(1, 1, 1)  // X^T B X, X^T AX
-  ME_SL_GRAM(3, 3, 3)  // [X W P] pair
-  ME_SL_GRAM(1, 1, 0)  // X^T B X
+  // symmetric pairs: U^T B U with U^T (A U) (each call passes V2 = A U)
+  ME_SL_GRAM(3, 3, 3, true)   // [X W P] pair
+  ME_SL_GRAM(1, 1, 1, true)   // X^T B X, X^T AX
+  ME_SL_GRAM(1, 1, 0, true)   // X^T B X
+  ME_SL_GRAM(2, 1, 0, false)  // [X W]^T B W
 #undef ME_SL_GRAM
+  std::abort();  // no other shape is requested
 }
 
 // out[e] = sum_p partials[p][e], p ascending, per slot (target 0: gram,
