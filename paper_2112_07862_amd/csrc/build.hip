@@ -1370,6 +1370,89 @@ __global__ void __launch_bounds__(kBlock) k_pack_perm(
   }
 }
 
+// Halo of one tile of kHaloRows consecutive solver rows over one entry range
+// (row pointers rp: a_rp for W, a_tp for T; the tile's entries are
+// contiguous): its distinct columns, sorted (bitonic sort in LDS, then a
+// block scan of first occurrences), written at the tile's first entry
+// position; each entry's slot in that list (binary search) with the FP16
+// weight of the packed entry.  Entries keep their order, so a product over
+// the halo visits them exactly as the packed product does.  A tile with more
+// than kHaloMaxE entries sets *fail (the range then runs without halos).
+constexpr int kHaloBuildThreads = 256;
+__global__ void __launch_bounds__(kHaloBuildThreads) k_halo_build(
+    int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ a_col,
+    const uint32_t* __restrict__ a_pk, uint32_t* __restrict__ h_pk, int32_t* __restrict__ h_list,
+    int32_t* __restrict__ h_cnt, int* hmax, int* fail) {
+  __shared__ int32_t key[kHaloMaxE];
+  __shared__ int32_t wsum[kHaloBuildThreads / kWave];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * kHaloRows;
+  const int64_t r1 = r0 + kHaloRows < n ? r0 + kHaloRows : n;
+  const int32_t e0 = rp[r0], e1 = rp[r1];
+  const int E = e1 - e0;
+  if (E > kHaloMaxE) {
+    if (tid == 0) {
+      h_cnt[blockIdx.x] = 0;
+      atomicOr(fail, 1);
+    }
+    return;
+  }
+  int P = 1;
+  while (P < E) P <<= 1;
+  for (int i = tid; i < P; i += kHaloBuildThreads) key[i] = i < E ? a_col[e0 + i] : INT32_MAX;
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < P / 2; i += kHaloBuildThreads) {
+        const int lo = 2 * i - (i & (stride - 1));  // pair (lo, lo + stride)
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const int32_t a = key[lo], b = key[hi];
+        if ((a > b) == up) {
+          key[lo] = b;
+          key[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // first occurrences, compacted in order (chunks of kHaloBuildThreads)
+  int32_t base = 0;
+  for (int c0 = 0; c0 < E; c0 += kHaloBuildThreads) {
+    const int i = c0 + tid;
+    const bool first = i < E && (i == 0 || key[i] != key[i - 1]);
+    const int32_t v = i < E ? key[i] : 0;
+    const unsigned long long m = __ballot(first);
+    const int lane = tid % kWave, wv = tid / kWave;
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wv] = __popcll(m);
+    __syncthreads();
+    int off = 0;
+    for (int q = 0; q < wv; ++q) off += wsum[q];
+    int all = 0;
+    for (int q = 0; q < kHaloBuildThreads / kWave; ++q) all += wsum[q];
+    __syncthreads();  // every read of key[i - 1] and wsum is done
+    if (first) key[base + off + before] = v;  // base + off + before <= i
+    __syncthreads();
+    base += all;
+  }
+  const int H = base;
+  for (int j = tid; j < H; j += kHaloBuildThreads) h_list[e0 + j] = key[j];
+  for (int i = tid; i < E; i += kHaloBuildThreads) {
+    const int32_t c = a_col[e0 + i];
+    int lo = 0, hi = H - 1;  // key[0..H) sorted, distinct; c is among them
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (key[mid] < c) lo = mid + 1; else hi = mid;
+    }
+    h_pk[e0 + i] = (uint32_t)lo | (a_pk[e0 + i] & 0xffff0000u);
+  }
+  if (tid == 0) {
+    h_cnt[blockIdx.x] = H;
+    atomicMax(hmax, H);
+  }
+}
+
 // dst[i'] = src[perm[i']] for a double array and its FP32 copy
 __global__ void k_gather_node(int64_t n, const int32_t* perm, const double* src, double* dst,
                               float* dst32) {
@@ -1485,13 +1568,14 @@ size_t build_mem1_bytes(int64_t n, int64_t nnz) {
   b1 += 2 * Arena::round((n + 1) * 4);                                              // a_rp, a_tp
   b1 += 3 * Arena::round(n * 4) + 5 * Arena::round(n * 8) + 4 * Arena::round(n * 4);  // solver order
   b1 += 2 * Arena::round((n + 1) * 8);                                              // offsets
+  b1 += 2 * Arena::round((n / kHaloRows + 1) * 4);                                  // halo sizes
   b1 += Arena::round(sizeof(int) * 64);
   return b1;
 }
 
 size_t build_mem2_bytes(int64_t nnz, int64_t nnz_t) {
   return 2 * Arena::round(nnz_t * 4 + 4) + Arena::round((nnz + nnz_t) * 4 + 4) +
-         Arena::round((nnz + nnz_t) * 8 + 8) + 2 * Arena::round((nnz + nnz_t) * 4 + 4);
+         Arena::round((nnz + nnz_t) * 8 + 8) + 4 * Arena::round((nnz + nnz_t) * 4 + 4);
 }
 
 // Bitmaps of the two-hop rows with more than the LDS hash's candidates.
@@ -1585,6 +1669,9 @@ static int build_pre_a_impl(const me_csr* W, const me_opts* o, DevHeap& heap, hi
   g->pdinv32_s = ar.take<float>(n);
   g->woff = ar.take<int64_t>(n + 1);
   g->toff = ar.take<int64_t>(n + 1);
+  g->h_cnt_w = ar.take<int32_t>(n / kHaloRows + 1);
+  g->h_cnt_t = ar.take<int32_t>(n / kHaloRows + 1);
+
   int* dflags = ar.take<int>(64);
   if (!dflags) return ME_ERR_HIP;
   g->scratch_d = scratch_d;
@@ -1658,6 +1745,8 @@ static int build_pre_a_impl(const me_csr* W, const me_opts* o, DevHeap& heap, hi
   g->a_w32 = ar2.take<float>(nnz + nnz_t + 1);
   g->a_pk = ar2.take<uint32_t>(nnz + nnz_t + 1);
   g->a_tq = ar2.take<uint32_t>(nnz_t + 1);
+  g->h_pk = ar2.take<uint32_t>(nnz + nnz_t + 1);
+  g->h_list = ar2.take<int32_t>(nnz + nnz_t + 1);
   g->mem_bytes += b2;
 
   k_twohop_lds<<<grid_lds, kWave, 0, s>>>(n, g->w_rp, g->w_col, 1, g->t_cnt, g->t_rp, g->t_col,
@@ -1705,9 +1794,17 @@ int build_pre_b(GraphOps* g, hipStream_t s) {
   k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->qinv, g->qinv_s,
                                                        g->qinv32_s);
   k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->invt, g->invt_s, nullptr);
-  // roots (2), the mu denominator's bits (4, 5), the largest offset (12) and
-  // the largest two-hop count of a column (13) in one read
-  int hf[16];
+  // halos of the W and T ranges (largest list: 14, 15; overflow: 16, 17)
+  const int64_t ntile = ceil_div(n, kHaloRows);
+  k_halo_build<<<ntile, kHaloBuildThreads, 0, s>>>(n, g->a_rp, g->a_col, g->a_pk, g->h_pk,
+                                                   g->h_list, g->h_cnt_w, g->dflags + 14,
+                                                   g->dflags + 16);
+  k_halo_build<<<ntile, kHaloBuildThreads, 0, s>>>(n, g->a_tp, g->a_col, g->a_pk, g->h_pk,
+                                                   g->h_list, g->h_cnt_t, g->dflags + 15,
+                                                   g->dflags + 17);
+  // roots (2), the mu denominator's bits (4, 5), the largest offset (12),
+  // the largest two-hop count of a column (13) and the halo sizes in one read
+  int hf[20];
   ME_TRY(hipMemcpyAsync(hf, g->dflags, sizeof(hf), hipMemcpyDeviceToHost, s));
   ME_TRY(hipStreamSynchronize(s));
   const int hroots = hf[roots - g->dflags];
@@ -1719,6 +1816,10 @@ int build_pre_b(GraphOps* g, hipStream_t s) {
   g->maxden = maxden;
   g->pk_ok = hf[12] <= 32767;
   g->tq_ok = g->pk_ok && hf[13] <= 65535;
+  g->h_max_w = hf[14];
+  g->h_max_t = hf[15];
+  g->halo_w = g->pk_ok && hf[16] == 0;
+  g->halo_t = g->pk_ok && hf[17] == 0;
 
   g->needs_eps = !(hroots > 1 || n < 2);
   return ME_OK;

@@ -28,6 +28,8 @@ namespace me {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;          // threads of the streaming kernels
+constexpr int kHaloRows = 16;        // rows per tile of the halo-staged preconditioner step
+constexpr int kHaloMaxE = 2048;      // entries of one tile and range the halo build sorts
 constexpr int kMaxBlockCols = 16;    // largest LOBPCG block width
 constexpr int kMaxBasis = 48;        // 3 x kMaxBlockCols: Rayleigh-Ritz basis size
 constexpr int kDenseMaxN = 48;       // graphs up to this size are solved densely
@@ -231,6 +233,19 @@ struct GraphOps {
   // (tq_ok).  Entry k of the T block (position nnz_w + k) is a_tq[k].
   uint32_t* a_tq = nullptr;
   bool tq_ok = false;
+  // Neighbour halos of the FP32 preconditioner (tiles of kHaloRows rows in
+  // the solver order, per entry range W and T): h_list holds each tile's
+  // distinct columns, sorted, at the position of the tile's first entry of
+  // the range (a tile has no more distinct columns than entries); h_pk holds
+  // per entry its column's slot in that list (bits 0-15) and the FP16 weight
+  // of a_pk (bits 16-31); h_cnt_w / h_cnt_t the list lengths, h_max_w /
+  // h_max_t their maxima; halo_w / halo_t whether every tile fitted.
+  uint32_t* h_pk = nullptr;
+  int32_t* h_list = nullptr;
+  int32_t* h_cnt_w = nullptr;
+  int32_t* h_cnt_t = nullptr;
+  int32_t h_max_w = 0, h_max_t = 0;
+  bool halo_w = false, halo_t = false;
   double* scratch_d = nullptr;  // n doubles of build scratch
   int64_t *woff = nullptr, *toff = nullptr;  // row offsets of the packed blocks
   OrderArgs ord{};              // search arguments while the order is pending

@@ -50,6 +50,13 @@ struct SlotDev {
   const uint32_t* a_tq;
   int64_t tq_base;
   int tq_ok;
+  // halos of the preconditioner's entry range (tiles of kHaloRows rows;
+  // null h_cnt: none): per entry its slot in the tile's list and its FP16
+  // weight, the lists, their lengths and the largest
+  const uint32_t* h_pk;
+  const int32_t* h_list;
+  const int32_t* h_cnt;
+  int h_max;
   double c_t, s_diag;
   const double* bdiag;  // null: B = I
   const double* dinv;   // diag(Op)^-1 (Jacobi preconditioner)
@@ -94,6 +101,7 @@ struct Tile {
 };
 
 constexpr int kGatherRows = 32;  // rows per workgroup of the gathering kernels
+constexpr int kGramBigRows = 512;  // reduction tiles this tall run the Grams in 8 waves
 
 // Work lists of one set of slots with a common block width kb (device).
 struct TileSet {
@@ -105,6 +113,7 @@ struct TileSet {
   const Tile* elem32 = nullptr;    // kBlock / LPR(float, kb) rows per tile
   const Tile* red = nullptr;       // reduction tiles (slot.per rows)
   int64_t n_gather = 0, n_elem64 = 0, n_elem32 = 0, n_red = 0;
+  int64_t n_red_big = 0;           // leading reduction tiles of slots with kGramBigRows rows and more
   bool buf = false;                // every array below kBufMaxBytes (buffer loads)
   bool pk = false;                 // every slot has packed preconditioner entries
   void* mem = nullptr;             // device allocation behind the lists

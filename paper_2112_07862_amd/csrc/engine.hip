@@ -212,6 +212,10 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
   d.a_tq = g.a_tq;
   d.tq_base = g.nnz_w;
   d.tq_ok = g.tq_ok ? 1 : 0;
+  d.h_pk = g.h_pk;
+  d.h_list = g.h_list;
+  d.h_cnt = nullptr;
+  d.h_max = 0;
   if (sp.op == OP_A) {
     d.c_t = -g.mu;
     d.s_diag = g.eps;
@@ -235,6 +239,13 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
     d.cheb_s_diag = 0.0;
     d.cheb_dinv = g.qinv_s;
     d.cheb_dinv32 = g.qinv32_s;
+  }
+  if (d.cheb_range == kRangeW && g.halo_w) {
+    d.h_cnt = g.h_cnt_w;
+    d.h_max = g.h_max_w;
+  } else if (d.cheb_range == kRangeT && g.halo_t) {
+    d.h_cnt = g.h_cnt_t;
+    d.h_max = g.h_max_t;
   }
   d.perm = g.perm;
   d.iperm = g.iperm;
@@ -287,6 +298,7 @@ int Engine::build_set(const std::vector<int>& ids, int kb, TileSet* ts, int area
   std::vector<Tile> gat, e64, e32, red;
   ts->buf = o_.addressing == ME_ADDR_AUTO;
   ts->pk = true;
+  ts->n_red_big = 0;
   for (int id : ids) {
     const SlotDev& d = hdev_[id];
     ts->buf = ts->buf && d.n * kb * 8 < kBufMaxBytes && d.nnz_ops * 8 < kBufMaxBytes;
@@ -294,8 +306,16 @@ int Engine::build_set(const std::vector<int>& ids, int kb, TileSet* ts, int area
     for (int64_t b = 0; b < ceil_div(d.n, kGatherRows); ++b) gat.push_back({id, (int32_t)b});
     for (int64_t b = 0; b < ceil_div(d.n, rb64); ++b) e64.push_back({id, (int32_t)b});
     for (int64_t b = 0; b < ceil_div(d.n, rb32); ++b) e32.push_back({id, (int32_t)b});
-    for (int b = 0; b < d.nparts; ++b) red.push_back({id, b});
   }
+  // reduction tiles: slots with tall tiles first (their Grams run in wider
+  // workgroups; the split depends on the slot alone)
+  for (int big = 1; big >= 0; --big)
+    for (int id : ids) {
+      const SlotDev& d = hdev_[id];
+      if ((d.per >= kGramBigRows) != (big == 1)) continue;
+      for (int b = 0; b < d.nparts; ++b) red.push_back({id, b});
+      if (big) ts->n_red_big += d.nparts;
+    }
   ts->n_gather = (int64_t)gat.size();
   ts->n_elem64 = (int64_t)e64.size();
   ts->n_elem32 = (int64_t)e32.size();

@@ -177,6 +177,10 @@ struct ChebView {
   const uint32_t* a_tq;    // packed two-hop entries of the FP64 form (tq_ok)
   int64_t tq_base;
   int tq_ok;
+  const uint32_t* h_pk;    // halos of the range (h_cnt null: none)
+  const int32_t* h_list;
+  const int32_t* h_cnt;
+  int h_max;
   const double *alpha, *beta;
   const int* done;
   double c_t, s_diag;
@@ -201,6 +205,10 @@ __device__ __forceinline__ ChebView<T> cheb_view(const SlotDev& d, int r, int yi
   v.a_tq = d.a_tq;
   v.tq_base = d.tq_base;
   v.tq_ok = d.tq_ok;
+  v.h_pk = d.h_pk;
+  v.h_list = d.h_list;
+  v.h_cnt = d.h_cnt;
+  v.h_max = d.h_max;
   v.alpha = d.cheb->alpha;
   v.beta = d.cheb->beta;
   v.done = &d.ctrl->done;
@@ -331,6 +339,172 @@ __global__ void __launch_bounds__((step1_threads<T, KB>())) k_sl_cheb_step1(Cheb
   cheb_step_rows<T, KB, RANGE, PK>(v, b * kStep1Rows, k);
 }
 
+// One-slot FP32 step over packed entries with the tile's neighbour rows of
+// y_k staged in LDS: the tile's distinct columns (its halo list) are loaded
+// once, coalesced, and each entry reads its neighbour's chunk from LDS at
+// the entry's halo slot.  Entries, weights and their order are those of the
+// packed product (an entry past the span reads the row itself with weight
+// 0), so the step equals k_sl_cheb_step1's bit for bit.  The tile's first
+// round of entries and its list are requested with the row's own data,
+// before the rows of the halo.
+static_assert(kStep1Rows == kHaloRows, "halo tiles are the one-slot workgroups");
+// halo chunks a thread stages per pass (4 measured faster than 8: fewer
+// registers)
+constexpr int kHaloStage = 4;
+// One halo tile (kHaloRows rows from row0 = tile kHaloRows) by NT =
+// kHaloRows G threads (tid in [0, NT)), its halo staged at hl.  RANGE is the
+// entry range (kRangeW, kRangeT) or -1: taken from the slot (tr: T range).
+// Every thread of the workgroup reaches the one barrier (the done test and
+// the tile's existence are the same for all of them).
+template <int KB, int RANGE>
+__device__ __forceinline__ void cheb_tile_halo(const ChebView<float>& d, int64_t tile, int tid,
+                                               int k, float* hl) {
+  using C = RowCfg<float, KB>;
+  constexpr int V = C::V16, EPL = C::EPL, UNR = C::UNR, NCH = C::NCH, G = C::G;
+  constexpr int NT = kHaloRows * G;
+  const bool tr = RANGE == -1 ? d.range == kRangeT : RANGE == kRangeT;
+  const int64_t row0 = tile * kHaloRows;
+  const int64_t row = row0 + tid / G;
+  const int q = tid % G;
+  const bool tile_live = row0 < d.n;
+  const bool live = row < d.n;
+  const int ch = q % NCH, e0 = q / NCH;
+  const int64_t rs = live ? row : 0;
+  const uint32_t oo = (uint32_t)rs * (uint32_t)(KB * 4) + (uint32_t)(ch * 16);
+  const int64_t xb = d.n * KB * 4;
+  const BufRsrc rx = buf_rsrc(d.yin, xb);
+  const auto own = buf_vec16<float, V>(rx, oo);
+  const auto ri = buf_vec16<float, V>(buf_rsrc(d.r, xb), oo);
+  auto yo = buf_vec16<float, V>(buf_rsrc(d.yout, xb), oo);  // y_{k-1}
+  const float cd = glob(d.cdinv)[rs];
+  const float alpha = (float)*glob(&d.alpha[k]);
+  const float bk = (float)*glob(&d.beta[k]);
+  const RowSpan sp = row_span(live, row, d.a_rp, d.a_tp, tr ? kRangeT : kRangeW);
+  const int32_t hs = tile_live ? glob(tr ? d.a_tp : d.a_rp)[row0] : 0;  // the tile's list
+  const int H = tile_live ? glob(d.h_cnt)[tile] : 0;
+  asm volatile("" ::: "memory");  // keeps the requests above ahead of the test
+  if (*glob(d.done)) return;      // the same slot for the whole workgroup
+  const BufRsrc rh = buf_rsrc(d.h_pk, d.nnz_ops * 4);
+  const int32_t base = tr ? sp.ts : sp.ws;
+  const int32_t mine = sp.len > e0 ? (sp.len - e0 + EPL - 1) / EPL : 0;  // this lane's entries
+  uint32_t pv[UNR];
+#pragma unroll
+  for (int u = 0; u < UNR; ++u)
+    pv[u] = (uint32_t)buf_i32(rh, u < mine ? (uint32_t)(base + u * EPL + e0) * 4u : kBufOut);
+  // stage the halo: chunk c of halo row h at hl[(h NCH + c) V]
+  const BufRsrc rl = buf_rsrc(d.h_list, d.nnz_ops * 4);
+  for (int i0 = tid; i0 < H * NCH; i0 += NT * kHaloStage) {
+    uint32_t col[kHaloStage];
+#pragma unroll
+    for (int j = 0; j < kHaloStage; ++j) {
+      const int i = i0 + j * NT;
+      col[j] = (uint32_t)buf_i32(rl, i < H * NCH ? (uint32_t)(hs + i / NCH) * 4u : kBufOut);
+    }
+    VecT<float, V> hv[kHaloStage];
+#pragma unroll
+    for (int j = 0; j < kHaloStage; ++j) {
+      const int i = i0 + j * NT;
+      hv[j] = buf_vec16<float, V>(
+          rx, i < H * NCH ? col[j] * (uint32_t)(KB * 4) + (uint32_t)((i % NCH) * 16) : kBufOut);
+    }
+#pragma unroll
+    for (int j = 0; j < kHaloStage; ++j) {
+      const int i = i0 + j * NT;
+      if (i < H * NCH) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) hl[i * V + v] = hv[j].v[v];
+      }
+    }
+  }
+  __syncthreads();
+  float yi[V], acc[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    yi[v] = own.v[v];
+    acc[v] = 0.0f;
+  }
+  const float ct = (float)d.c_t;
+  for (int32_t r = 0; r < mine; r += UNR) {
+    if (r > 0) {
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+        pv[u] = (uint32_t)buf_i32(
+            rh, r + u < mine ? (uint32_t)(base + (r + u) * EPL + e0) * 4u : kBufOut);
+    }
+    float cf[UNR];
+    VecT<float, V> xj[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const float w = (float)__builtin_bit_cast(_Float16, (uint16_t)(pv[u] >> 16));
+      cf[u] = tr ? ct * w : w;
+      if (r + u < mine) {
+        const float* src = hl + ((pv[u] & 0xffffu) * NCH + ch) * V;
+#pragma unroll
+        for (int v = 0; v < V; ++v) xj[u].v[v] = src[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) xj[u].v[v] = yi[v];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v] = fmaT(cf[u], yi[v] - xj[u].v[v], acc[v]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+    for (int o = NCH; o < G; o <<= 1) acc[v] += __shfl_xor(acc[v], o);
+  if (!live || q >= NCH) return;
+  const float sd = (float)d.s_diag;
+  const float beta = bk * cd;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const float res = ri.v[v] - fmaT(sd, yi[v], acc[v]);
+    yo.v[v] = yi[v] + fmaT(alpha, yi[v] - yo.v[v], beta * res);
+  }
+  stv<float, V>(d.yout + row * KB + q * V, yo);
+}
+
+template <int KB, int RANGE>
+__global__ void __launch_bounds__((step1_threads<float, KB>())) k_sl_cheb_step1_halo(
+    ChebView<float> d, int64_t nblocks, int k) {
+  static_assert(RANGE == kRangeW || RANGE == kRangeT, "halos exist per entry range");
+  extern __shared__ float4 halo_lds[];
+  const int64_t b = xcd_block(nblocks);
+  if (b >= nblocks) return;
+  cheb_tile_halo<KB, RANGE>(d, b, threadIdx.x, k, reinterpret_cast<float*>(halo_lds));
+}
+
+// Work-list form over slots with halos (every slot of the set has them):
+// a tile of kGatherRows rows is two halo tiles, each staged in its own half
+// of the LDS (hstride floats each).  Equal bit for bit to k_sl_cheb_step.
+template <int KB>
+__global__ void __launch_bounds__((RowCfg<float, KB>::THREADS)) k_sl_cheb_step_halo(
+    const SlotDev* __restrict__ sl, const Tile* __restrict__ tiles, int64_t ntiles, int k, int r,
+    int yin, int yout, int hstride) {
+  static_assert(kGatherRows == 2 * kHaloRows, "a gather tile is two halo tiles");
+  constexpr int NT = kHaloRows * RowCfg<float, KB>::G;
+  extern __shared__ float4 halo_lds[];
+  const int64_t b = xcd_block(ntiles);
+  if (b >= ntiles) return;
+  const Tile t = tiles[b];
+  const ChebView<float> d = cheb_view<float>(sl[t.slot], r, yin, yout);
+  const int half = threadIdx.x / NT;
+  cheb_tile_halo<KB, -1>(d, 2 * (int64_t)t.blk + half, threadIdx.x % NT, k,
+                         reinterpret_cast<float*>(halo_lds) + half * hstride);
+}
+
+// Dynamic LDS of the halo step (its largest list), or 0 when the slot has
+// no halos or they would not fit.
+constexpr int kHaloMaxLds = 32768;
+template <int KB>
+static int halo_lds_bytes(const ChebView<float>& v) {
+  if (!v.h_cnt || (v.range != kRangeW && v.range != kRangeT)) return 0;
+  const int64_t b = (int64_t)v.h_max * KB * 4;
+  return b <= kHaloMaxLds ? (int)(b > 16 ? b : 16) : 0;
+}
+
 template <typename T>
 void sl_cheb_first(const SlotDev* sl, const TileSet& ts, int r, int y, int yprev, hipStream_t s) {
   const Tile* tl = sizeof(T) == 8 ? ts.elem64 : ts.elem32;
@@ -366,6 +540,10 @@ static ChebView<T> cheb_view_host(const SlotDev& d, int r, int yin, int yout) {
   v.a_tq = d.a_tq;
   v.tq_base = d.tq_base;
   v.tq_ok = d.tq_ok;
+  v.h_pk = d.h_pk;
+  v.h_list = d.h_list;
+  v.h_cnt = d.h_cnt;
+  v.h_max = d.h_max;
   v.alpha = (const double*)((const char*)d.cheb + offsetof(ChebCoef, alpha));
   v.beta = (const double*)((const char*)d.cheb + offsetof(ChebCoef, beta));
   v.done = (const int*)((const char*)d.ctrl + offsetof(Ctrl, done));
@@ -383,6 +561,16 @@ static void launch_cheb_step(const SlotDev* sl, const SlotDev* host_sl, const Ti
     const ChebView<T> v = cheb_view_host<T>(host_sl[ts.ids[0]], r, yin, yout);
     const int64_t nb = (v.n + kStep1Rows - 1) / kStep1Rows;
     const dim3 g1(xcd_grid(nb)), b1(step1_threads<T, KB>());
+    if constexpr (PK && sizeof(T) == 4) {
+      const int lds = halo_lds_bytes<KB>(v);
+      if (lds > 0) {
+        if (v.range == kRangeW)
+          k_sl_cheb_step1_halo<KB, kRangeW><<<g1, b1, lds, s>>>(v, nb, k);
+        else
+          k_sl_cheb_step1_halo<KB, kRangeT><<<g1, b1, lds, s>>>(v, nb, k);
+        return;
+      }
+    }
     if (v.range == kRangeW)
       k_sl_cheb_step1<T, KB, kRangeW, PK><<<g1, b1, 0, s>>>(v, nb, k);
     else if (v.range == kRangeT)
@@ -390,6 +578,22 @@ static void launch_cheb_step(const SlotDev* sl, const SlotDev* host_sl, const Ti
     else
       k_sl_cheb_step1<T, KB, kRangeAll, PK><<<g1, b1, 0, s>>>(v, nb, k);
   } else if (ts.buf) {
+    if constexpr (PK && sizeof(T) == 4) {
+      // halos when every slot of the set has them and two fit the LDS
+      int64_t hmax = 0;
+      bool all = true;
+      for (int id : ts.ids) {
+        const SlotDev& h = host_sl[id];
+        all = all && h.h_cnt && (h.cheb_range == kRangeW || h.cheb_range == kRangeT);
+        hmax = std::max<int64_t>(hmax, h.h_max);
+      }
+      const int64_t hstride = std::max<int64_t>(hmax, 1) * KB;  // floats per half
+      if (all && 2 * hstride * 4 <= kHaloMaxLds) {
+        k_sl_cheb_step_halo<KB><<<grid, blk, 2 * hstride * 4, s>>>(
+            sl, ts.gather, ts.n_gather, k, r, yin, yout, (int)hstride);
+        return;
+      }
+    }
     k_sl_cheb_step<T, KB, true, PK><<<grid, blk, 0, s>>>(sl, ts.gather, ts.n_gather, k, r, yin,
                                                           yout);
   } else {
@@ -766,15 +970,14 @@ struct Ids {
 // mirrors them, so both triangles of an off-diagonal tile hold the same sums.
 // The waves' sums are added in wave order in LDS and written as the tile's
 // partial.
-constexpr int kGramThreads = 512;
-template <int KB, int NU, int NV, int NV2>
+template <int KB, int NU, int NV, int NV2, int NTH>
 struct GramCfg {
   static constexpr int MU = NU * KB, MV = NV * KB, MV2 = NV2 * KB;
   static constexpr int TU = (MU + 15) / 16, TV = (MV + 15) / 16, TV2 = (MV2 + 15) / 16;
   static constexpr int E1 = MU * MV, E2 = MU * MV2;
   static constexpr int NB = NU + NV2;         // staged blocks
   static constexpr int LD = NB * KB + 1;      // LDS row stride (doubles)
-  static constexpr int NW = kGramThreads / kWave;
+  static constexpr int NW = NTH / kWave;
   static constexpr int WAVE_LDS = 16 * LD + 16;  // chunk + row weights
   static constexpr int LDS = NW * WAVE_LDS > E1 + E2 ? NW * WAVE_LDS : E1 + E2;
   static constexpr int EPL = KB / 4;          // doubles per lane when staging
@@ -786,11 +989,11 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int KB, int NU, int NV, int NV2, bool SYM>
-__global__ void __launch_bounds__(kGramThreads) k_sl_gram(const SlotDev* __restrict__ sl,
-                                                          const Tile* __restrict__ tiles, Ids u,
-                                                          Ids vsel, Ids v2, int use_b, int cert) {
-  using C = GramCfg<KB, NU, NV, NV2>;
+template <int KB, int NU, int NV, int NV2, bool SYM, int NTH>
+__global__ void __launch_bounds__(NTH) k_sl_gram(const SlotDev* __restrict__ sl,
+                                                 const Tile* __restrict__ tiles, Ids u, Ids vsel,
+                                                 Ids v2, int use_b, int cert) {
+  using C = GramCfg<KB, NU, NV, NV2, NTH>;
   constexpr int MU = C::MU, MV = C::MV, MV2 = C::MV2, TU = C::TU, TV = C::TV, TV2 = C::TV2;
   constexpr int E1 = C::E1, E2 = C::E2, LD = C::LD, NW = C::NW, EPL = C::EPL, NB = C::NB;
   static_assert(!SYM || (NU == NV && (NV2 == 0 || NV2 == NU)), "symmetric Grams are square");
@@ -919,7 +1122,7 @@ __global__ void __launch_bounds__(kGramThreads) k_sl_gram(const SlotDev* __restr
     __syncthreads();
   }
   double* out = d.partials + (int64_t)t.blk * (E1 + E2);
-  for (int e = tid; e < E1 + E2; e += kGramThreads) out[e] = sh[e];
+  for (int e = tid; e < E1 + E2; e += NTH) out[e] = sh[e];
 }
 
 void sl_gram(const SlotDev* sl, const TileSet& ts, int nu, const int* u, int nv, const int* v,
@@ -937,11 +1140,18 @@ void sl_gram(const SlotDev* sl, const TileSet& ts, int nu, const int* u, int nv,
     same = same && iv.v[i] == i;
   }
   for (int i = 0; i < nv2; ++i) iv2.v[i] = v2[i];
+  // tiles of tall slots in 8 waves (one wave per 16-row chunk column of
+  // the tile), the others in 4; a slot's tiles always run in the same form
+  const int64_t nb = ts.n_red_big, ns = ts.n_red - ts.n_red_big;
 #define ME_SL_GRAM(NU_, NV_, NV2_, SYM_)                                                    \
   if (nu == NU_ && nv == NV_ && nv2 == NV2_ && (!(SYM_) || same)) {                          \
     ME_DISPATCH_KB(ts.kb, {                                                                  \
-      k_sl_gram<KB, NU_, NV_, NV2_, SYM_><<<ts.n_red, kGramThreads, 0, s>>>(                 \
-          sl, ts.red, iu, iv, iv2, use_b, cert);                                             \
+      if (nb > 0)                                                                            \
+        k_sl_gram<KB, NU_, NV_, NV2_, SYM_, 512><<<nb, 512, 0, s>>>(sl, ts.red, iu, iv, iv2, \
+                                                                    use_b, cert);           \
+      if (ns > 0)                                                                            \
+        k_sl_gram<KB, NU_, NV_, NV2_, SYM_, 256><<<ns, 256, 0, s>>>(sl, ts.red + nb, iu, iv, \
+                                                                    iv2, use_b, cert);      \
     });                                                                                      \
     return;                                                                                  \
   }
