@@ -152,6 +152,7 @@ void sl_deflate(const SlotDev* sl, const TileSet& ts, int blk, int cert, hipStre
 void sl_to32(const SlotDev* sl, const TileSet& ts, int from64, int to32, hipStream_t s);
 void sl_to64(const SlotDev* sl, const TileSet& ts, int from32, int to64, hipStream_t s);
 void sl_to32_scaled(const SlotDev* sl, const TileSet& ts, int from64, int to32, hipStream_t s);
+void sl_to16_scaled(const SlotDev* sl, const TileSet& ts, int from64, int to32, hipStream_t s);
 bool sl_cheb_h_ok(const SlotDev* host_sl, const TileSet& ts);
 void sl_cheb_first_h(const SlotDev* sl, const TileSet& ts, int r, int y, int yprev, hipStream_t s);
 void sl_cheb_step_h(const SlotDev* host_sl, const TileSet& ts, int k, int r, int yin, int yout,

@@ -73,9 +73,9 @@ size_t Engine::tile_bytes(int64_t n, int kb) {
 }
 
 size_t Engine::tile_area_bytes(size_t sum) {
-  // each of at most three lists (one per block width) rounds five sections
-  // and its start to the heap's unit
-  return DevHeap::round(sum + 3 * 6 * kHeapAlign);
+  // each of at most six lists (per block width, packed entries or not)
+  // rounds five sections and its start to the heap's unit
+  return DevHeap::round(sum + 6 * 6 * kHeapAlign);
 }
 
 size_t Engine::run_bytes(const std::vector<std::pair<int64_t, int>>& slots) {
@@ -362,14 +362,17 @@ void Engine::free_set(TileSet* ts) {
 
 int Engine::sets_for(const std::vector<int>& ids, std::vector<TileSet>* sets, int area) {
   areas_[area].used = 0;  // the area's previous lists are freed
-  for (int kb : {4, 8, 16}) {
-    std::vector<int> sub;
-    for (int id : ids)
-      if (sh_[id].sp.kb == kb) sub.push_back(id);
-    if (sub.empty()) continue;
-    sets->emplace_back();
-    ME_TRY_STATUS(build_set(sub, kb, &sets->back(), area));
-  }
+  // one set per block width and kind of preconditioner entries (packed or
+  // not), so that the kernels a slot runs depend on the slot alone
+  for (int kb : {4, 8, 16})
+    for (int pk : {1, 0}) {
+      std::vector<int> sub;
+      for (int id : ids)
+        if (sh_[id].sp.kb == kb && (hdev_[id].pk_ok != 0) == (pk == 1)) sub.push_back(id);
+      if (sub.empty()) continue;
+      sets->emplace_back();
+      ME_TRY_STATUS(build_set(sub, kb, &sets->back(), area));
+    }
   return ME_OK;
 }
 
@@ -426,8 +429,8 @@ void Engine::iteration(const TileSet& ts) {
         // algorithmic bytes of one step: every entry of the preconditioner's
         // operator (packed: 4 B; else column index and weight; FP64 two-hop
         // entries: the column, with 1/T_i per row), row bounds (8 B), D^-1_i,
-        // and the blocks y_k (neighbour rows counted once), y_{k-1}, R read
-        // and y_{k+1} written
+        // and the blocks y_k (neighbour rows counted once), y_{k-1}, R
+        // (packed FP32 sets: FP16) read and y_{k+1} written
         const double sz = cheb32_ ? 4.0 : 8.0;
         const double ent = (cheb32_ && ts.pk) ? 4.0 : 4.0 + sz;
         const bool tq = !cheb32_ && g.tq_ok && kb <= 4;  // packed two-hop entries
@@ -440,7 +443,7 @@ void Engine::iteration(const TileSet& ts) {
           cb += 4.0 * (nw + nt) + (double)g.n * 12.0 + 10.0 * (double)g.n * kb;
         else
           cb += ent * nw + ent_t * nt + tin + (double)g.n * (8.0 + sz) +
-                4.0 * (double)g.n * kb * sz;
+                (3.0 * sz + ((cheb32_ && ts.pk) ? 2.0 : sz)) * (double)g.n * kb;
       }
     }
     const int w = cheb32_ ? BW32 : BW, y = cheb32_ ? BY32 : BY;
@@ -451,7 +454,8 @@ void Engine::iteration(const TileSet& ts) {
       sl_to32_scaled(d_slots_, ts, BR, BR32, s_);
       sl_cheb_first_h(d_slots_, ts, r, cur, nxt, s_);
     } else if (cheb32_) {
-      sl_to32(d_slots_, ts, BR, BR32, s_);
+      if (ts.pk) sl_to16_scaled(d_slots_, ts, BR, BR32, s_);  // packed: FP16 right-hand side
+      else sl_to32(d_slots_, ts, BR, BR32, s_);
       sl_cheb_first<float>(d_slots_, ts, r, cur, nxt, s_);
     } else {
       sl_cheb_first<double>(d_slots_, ts, r, cur, nxt, s_);

@@ -89,6 +89,22 @@ __device__ __forceinline__ VecT<T, V> buf_vec16(BufRsrc r, uint32_t off) {
   static_assert(sizeof(T) * V == 16, "16-byte chunk");
   return __builtin_bit_cast(VecT<T, V>, me_buf_load_v4i32(r, off, 0, 0));
 }
+// Four FP16 values (8 bytes) widened to FP32: the preconditioner's
+// right-hand side beside a 16-byte chunk of FP32 iterates.
+__device__ __forceinline__ VecT<float, 4> buf_half4(BufRsrc r, uint32_t off) {
+  const auto h = __builtin_bit_cast(VecT<_Float16, 4>, me_buf_load_v2i32(r, off, 0, 0));
+  VecT<float, 4> f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) f.v[q] = (float)h.v[q];
+  return f;
+}
+__device__ __forceinline__ VecT<float, 4> ld_half4(const _Float16* p) {
+  const auto h = ldv<_Float16, 4>(p);
+  VecT<float, 4> f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) f.v[q] = (float)h.v[q];
+  return f;
+}
 
 // Multiply-adds of the products and recurrences are written out, so that
 // every kernel form of the same arithmetic rounds identically, whatever the

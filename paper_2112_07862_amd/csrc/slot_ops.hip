@@ -141,7 +141,7 @@ template void sl_spmm<float>(const SlotDev*, const TileSet&, int, int, int, hipS
 // own y_{k-1} before writing it; neighbours only read y_k).
 // ---------------------------------------------------------------------------
 
-template <typename T, int KB>
+template <typename T, int KB, bool R16>
 __global__ void __launch_bounds__(kBlock) k_sl_cheb_first(const SlotDev* __restrict__ sl,
                                                           const Tile* __restrict__ tiles, int r,
                                                           int y, int yprev) {
@@ -154,7 +154,19 @@ __global__ void __launch_bounds__(kBlock) k_sl_cheb_first(const SlotDev* __restr
   if (row >= d.n) return;
   const T sc = (T)(1.0 / *glob(&d.cheb->theta)) * glob(SB<T>::cdinv(d))[row];
   const int64_t o = row * KB + sub * E::VEC;
-  auto v = ldv<T, E::VEC>(SB<T>::blk(d, r) + o);
+  VecT<T, E::VEC> v;
+  if constexpr (R16) {  // right-hand side in FP16
+    static_assert(sizeof(T) == 4 && E::VEC % 4 == 0, "FP16 right-hand side of FP32 steps");
+    const _Float16* rh = reinterpret_cast<const _Float16*>(SB<T>::blk(d, r)) + o;
+#pragma unroll
+    for (int h = 0; h < E::VEC / 4; ++h) {
+      const auto f = ld_half4(rh + 4 * h);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v.v[4 * h + q] = f.v[q];
+    }
+  } else {
+    v = ldv<T, E::VEC>(SB<T>::blk(d, r) + o);
+  }
 #pragma unroll
   for (int q = 0; q < E::VEC; ++q) v.v[q] *= sc;
   stv<T, E::VEC>(SB<T>::blk(d, y) + o, v);
@@ -236,7 +248,13 @@ __device__ __forceinline__ void cheb_step_rows(const ChebView<T>& d, int64_t row
   const int64_t xb = d.n * KB * (int64_t)sizeof(T);
   const BufRsrc rx = buf_rsrc(d.yin, xb);
   const auto own = buf_vec16<T, C::V16>(rx, oo);
-  const auto ri = buf_vec16<T, C::V16>(buf_rsrc(d.r, xb), oo);
+  VecT<T, C::V16> ri;
+  if constexpr (PK) {  // packed sets: right-hand side in FP16
+    static_assert(sizeof(T) == 4, "packed entries serve the FP32 preconditioner");
+    ri = buf_half4(buf_rsrc(d.r, d.n * KB * 2), (uint32_t)rs * (uint32_t)(KB * 2) + (uint32_t)(ch * 8));
+  } else {
+    ri = buf_vec16<T, C::V16>(buf_rsrc(d.r, xb), oo);
+  }
   auto yo = buf_vec16<T, C::V16>(buf_rsrc(d.yout, xb), oo);  // y_{k-1}
   const T cd = glob(d.cdinv)[rs];
   const T alpha = (T)*glob(&d.alpha[k]);
@@ -310,7 +328,11 @@ __global__ void __launch_bounds__((RowCfg<T, KB>::THREADS)) k_sl_cheb_step(const
     const T alpha = (T)*glob(&d.cheb->alpha[k]);
     const T beta = (T)*glob(&d.cheb->beta[k]) * glob(SB<T>::cdinv(d))[row];
     const int64_t o = row * KB + q * C::V16;
-    const auto ri = ldv<T, C::V16>(SB<T>::blk(d, r) + o);
+    VecT<T, C::V16> ri;
+    if constexpr (PK)  // packed sets: right-hand side in FP16
+      ri = ld_half4(reinterpret_cast<const _Float16*>(SB<T>::blk(d, r)) + o);
+    else
+      ri = ldv<T, C::V16>(SB<T>::blk(d, r) + o);
     T* yo_p = SB<T>::blk(d, yout);
     auto yo = ldv<T, C::V16>(yo_p + o);  // y_{k-1} of this row
 #pragma unroll
@@ -374,7 +396,9 @@ __device__ __forceinline__ void cheb_tile_halo(const ChebView<float>& d, int64_t
   const int64_t xb = d.n * KB * 4;
   const BufRsrc rx = buf_rsrc(d.yin, xb);
   const auto own = buf_vec16<float, V>(rx, oo);
-  const auto ri = buf_vec16<float, V>(buf_rsrc(d.r, xb), oo);
+  // right-hand side in FP16 (packed sets)
+  const auto ri = buf_half4(buf_rsrc(d.r, d.n * KB * 2),
+                            (uint32_t)rs * (uint32_t)(KB * 2) + (uint32_t)(ch * 8));
   auto yo = buf_vec16<float, V>(buf_rsrc(d.yout, xb), oo);  // y_{k-1}
   const float cd = glob(d.cdinv)[rs];
   const float alpha = (float)*glob(&d.alpha[k]);
@@ -510,7 +534,13 @@ void sl_cheb_first(const SlotDev* sl, const TileSet& ts, int r, int y, int yprev
   const Tile* tl = sizeof(T) == 8 ? ts.elem64 : ts.elem32;
   const int64_t nt = sizeof(T) == 8 ? ts.n_elem64 : ts.n_elem32;
   if (nt == 0) return;
-  ME_DISPATCH_KB(ts.kb, { k_sl_cheb_first<T, KB><<<nt, kBlock, 0, s>>>(sl, tl, r, y, yprev); });
+  // packed FP32 sets read the right-hand side in FP16 (sl_to16_scaled)
+  ME_DISPATCH_KB(ts.kb, {
+    if (sizeof(T) == 4 && ts.pk)
+      k_sl_cheb_first<T, KB, sizeof(T) == 4><<<nt, kBlock, 0, s>>>(sl, tl, r, y, yprev);
+    else
+      k_sl_cheb_first<T, KB, false><<<nt, kBlock, 0, s>>>(sl, tl, r, y, yprev);
+  });
 }
 // The view of a slot from the host copy of its descriptor (device
 // addresses of the same fields the device-side view reads).
@@ -1399,6 +1429,40 @@ void sl_to32_scaled(const SlotDev* sl, const TileSet& ts, int from64, int to32, 
     k_sl_convert<KB, true, true><<<ts.n_elem32, kBlock, 0, s>>>(sl, ts.elem32, from64, to32);
   });
 }
+// R (FP64) to FP16 in the FP32 block's memory, each column scaled by
+// 1 / |r_j| from the residual pass (unit columns: FP16's range; the scale
+// leaves the span of the preconditioned block unchanged).
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_sl_to16_scaled(const SlotDev* __restrict__ sl,
+                                                           const Tile* __restrict__ tiles, int b64,
+                                                           int b32) {
+  using E = ElemCfg<float, KB>;
+  constexpr int VEC = E::VEC, LPR = E::LPR;
+  const Tile t = tiles[blockIdx.x];
+  const SlotDev& d = sl[t.slot];
+  if (slot_done(d)) return;
+  const int64_t row = (int64_t)t.blk * E::RB + threadIdx.x / LPR;
+  const int sub = threadIdx.x % LPR;
+  if (row >= d.n) return;
+  const int64_t o = row * KB + sub * VEC;
+  const double* p64 = d.b64[b64] + o;
+  const double* ri = d.ctrl->rinv + sub * VEC;
+  VecT<_Float16, VEC> h;
+#pragma unroll
+  for (int q = 0; q < VEC; q += 2) {
+    const auto v = ldv<double, 2>(p64 + q);
+    h.v[q] = (_Float16)(float)(v.v[0] * glob(ri)[q]);
+    h.v[q + 1] = (_Float16)(float)(v.v[1] * glob(ri)[q + 1]);
+  }
+  stv<_Float16, VEC>(reinterpret_cast<_Float16*>(d.b32[b32]) + o, h);
+}
+void sl_to16_scaled(const SlotDev* sl, const TileSet& ts, int from64, int to32, hipStream_t s) {
+  if (ts.n_elem32 == 0) return;
+  ME_DISPATCH_KB(ts.kb, {
+    k_sl_to16_scaled<KB><<<ts.n_elem32, kBlock, 0, s>>>(sl, ts.elem32, from64, to32);
+  });
+}
+
 void sl_to64(const SlotDev* sl, const TileSet& ts, int from32, int to64, hipStream_t s) {
   if (ts.n_elem32 == 0) return;
   ME_DISPATCH_KB(ts.kb, {
