@@ -52,7 +52,7 @@ TRAFFIC_FILES = {
     ("sphere_1m", "mixed", "fp32"): "cheb_step_sphere_1m_hbm_bytes.txt",
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2112_07862_amd", "csrc", f)
-                  for f in ("slot_ops.hip", "rowops.h", "engine.h", "common.h")]
+                  for f in ("slot_ops.hip", "rowops.h", "engine.h", "common.h", "build.hip")]
 
 
 def code_text(text: str) -> str:

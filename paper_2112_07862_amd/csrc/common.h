@@ -28,7 +28,10 @@ namespace me {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;          // threads of the streaming kernels
-constexpr int kHaloRows = 16;        // rows per tile of the halo-staged preconditioner step
+#ifndef ME_HALO_ROWS
+#define ME_HALO_ROWS 32
+#endif
+constexpr int kHaloRows = ME_HALO_ROWS;  // rows per tile of the halo-staged preconditioner step
 constexpr int kHaloMaxE = 2048;      // entries of one tile and range the halo build sorts
 constexpr int kMaxBlockCols = 16;    // largest LOBPCG block width
 constexpr int kMaxBasis = 48;        // 3 x kMaxBlockCols: Rayleigh-Ritz basis size

@@ -369,7 +369,11 @@ __global__ void __launch_bounds__((step1_threads<T, KB>())) k_sl_cheb_step1(Cheb
 // 0), so the step equals k_sl_cheb_step1's bit for bit.  The tile's first
 // round of entries and its list are requested with the row's own data,
 // before the rows of the halo.
-static_assert(kStep1Rows == kHaloRows, "halo tiles are the one-slot workgroups");
+static_assert(kGatherRows % kHaloRows == 0, "a gather tile is a whole number of halo tiles");
+template <int KB>
+constexpr int halo_threads() {
+  return kHaloRows * RowCfg<float, KB>::G;
+}
 // halo chunks a thread stages per pass (4 measured faster than 8: fewer
 // registers)
 constexpr int kHaloStage = 4;
@@ -491,7 +495,7 @@ __device__ __forceinline__ void cheb_tile_halo(const ChebView<float>& d, int64_t
 }
 
 template <int KB, int RANGE>
-__global__ void __launch_bounds__((step1_threads<float, KB>())) k_sl_cheb_step1_halo(
+__global__ void __launch_bounds__((halo_threads<KB>())) k_sl_cheb_step1_halo(
     ChebView<float> d, int64_t nblocks, int k) {
   static_assert(RANGE == kRangeW || RANGE == kRangeT, "halos exist per entry range");
   extern __shared__ float4 halo_lds[];
@@ -501,22 +505,23 @@ __global__ void __launch_bounds__((step1_threads<float, KB>())) k_sl_cheb_step1_
 }
 
 // Work-list form over slots with halos (every slot of the set has them):
-// a tile of kGatherRows rows is two halo tiles, each staged in its own half
-// of the LDS (hstride floats each).  Equal bit for bit to k_sl_cheb_step.
+// a tile of kGatherRows rows is kGatherRows / kHaloRows halo tiles, each
+// staged in its own part of the LDS (hstride floats each).  Equal bit for
+// bit to k_sl_cheb_step.
 template <int KB>
 __global__ void __launch_bounds__((RowCfg<float, KB>::THREADS)) k_sl_cheb_step_halo(
     const SlotDev* __restrict__ sl, const Tile* __restrict__ tiles, int64_t ntiles, int k, int r,
     int yin, int yout, int hstride) {
-  static_assert(kGatherRows == 2 * kHaloRows, "a gather tile is two halo tiles");
-  constexpr int NT = kHaloRows * RowCfg<float, KB>::G;
+  constexpr int NT = halo_threads<KB>();
+  constexpr int PARTS = kGatherRows / kHaloRows;
   extern __shared__ float4 halo_lds[];
   const int64_t b = xcd_block(ntiles);
   if (b >= ntiles) return;
   const Tile t = tiles[b];
   const ChebView<float> d = cheb_view<float>(sl[t.slot], r, yin, yout);
-  const int half = threadIdx.x / NT;
-  cheb_tile_halo<KB, -1>(d, 2 * (int64_t)t.blk + half, threadIdx.x % NT, k,
-                         reinterpret_cast<float*>(halo_lds) + half * hstride);
+  const int part = threadIdx.x / NT;
+  cheb_tile_halo<KB, -1>(d, PARTS * (int64_t)t.blk + part, threadIdx.x % NT, k,
+                         reinterpret_cast<float*>(halo_lds) + part * hstride);
 }
 
 // Dynamic LDS of the halo step (its largest list), or 0 when the slot has
@@ -594,10 +599,12 @@ static void launch_cheb_step(const SlotDev* sl, const SlotDev* host_sl, const Ti
     if constexpr (PK && sizeof(T) == 4) {
       const int lds = halo_lds_bytes<KB>(v);
       if (lds > 0) {
+        const int64_t nh = (v.n + kHaloRows - 1) / kHaloRows;
+        const dim3 gh(xcd_grid(nh)), bh(halo_threads<KB>());
         if (v.range == kRangeW)
-          k_sl_cheb_step1_halo<KB, kRangeW><<<g1, b1, lds, s>>>(v, nb, k);
+          k_sl_cheb_step1_halo<KB, kRangeW><<<gh, bh, lds, s>>>(v, nh, k);
         else
-          k_sl_cheb_step1_halo<KB, kRangeT><<<g1, b1, lds, s>>>(v, nb, k);
+          k_sl_cheb_step1_halo<KB, kRangeT><<<gh, bh, lds, s>>>(v, nh, k);
         return;
       }
     }
@@ -617,9 +624,10 @@ static void launch_cheb_step(const SlotDev* sl, const SlotDev* host_sl, const Ti
         all = all && h.h_cnt && (h.cheb_range == kRangeW || h.cheb_range == kRangeT);
         hmax = std::max<int64_t>(hmax, h.h_max);
       }
-      const int64_t hstride = std::max<int64_t>(hmax, 1) * KB;  // floats per half
-      if (all && 2 * hstride * 4 <= kHaloMaxLds) {
-        k_sl_cheb_step_halo<KB><<<grid, blk, 2 * hstride * 4, s>>>(
+      const int64_t hstride = std::max<int64_t>(hmax, 1) * KB;  // floats per halo tile
+      constexpr int parts = kGatherRows / kHaloRows;
+      if (all && parts * hstride * 4 <= kHaloMaxLds) {
+        k_sl_cheb_step_halo<KB><<<grid, blk, parts * hstride * 4, s>>>(
             sl, ts.gather, ts.n_gather, k, r, yin, yout, (int)hstride);
         return;
       }
