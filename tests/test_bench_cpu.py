@@ -37,7 +37,7 @@ def test_traffic_only_from_the_matching_summary(monkeypatch):
         monkeypatch.setattr(bench, "kernel_source_hash", lambda texts=None: "0" * 64)
         assert bench.measured_traffic(_args(workload=wl, precision=prec, cheb_iterates=it)) is None
     monkeypatch.undo()
-    assert bench.measured_traffic(_args(workload="sphere_1m")) is None
+    assert bench.measured_traffic(_args(workload="square_2k")) is None
     assert bench.measured_traffic(_args(precision="fp64")) is None
     assert bench.measured_traffic(_args(cheb_degree=96)) is None
     assert bench.measured_traffic(_args(eps_tol=1e-8)) is None
