@@ -556,3 +556,31 @@ def test_option_errors(me):
         me.embed(g, 3, precision="fp64", product="fp32")  # FP32 product needs ME_MIXED
     with pytest.raises(me.MembedError):
         me.embed(g, 3, cholqr_passes=3)
+
+
+def test_embed_without_halos(me):
+    """A wheel (a hub joined to 598 of 600 ring nodes, random weights): the
+    hub's tile has some 600 distinct neighbours, more than the width-16 step
+    stages in LDS, and every ring node has some 600 two-hop neighbours, more
+    than the halo build sorts per tile, so both solves' preconditioners run
+    the gathering kernels instead of the halo-staged ones.  Parity with the
+    oracle at the usual bars, and bit for bit with the 64-bit-address form."""
+    m = 600
+    rng = np.random.default_rng(21)
+    hub = 1 + np.arange(2, m)
+    i = np.concatenate([np.zeros(hub.size, dtype=np.int64), 1 + np.arange(m)])
+    j = np.concatenate([hub, 1 + (np.arange(m) + 1) % m])
+    g = sg.from_edges(m + 1, i, j, rng.uniform(0.5, 2.0, i.size))
+    ops = oracle.build_ops(g.n, g.rowptr, g.col, g.val)
+    K = 16
+    lam_o, V_o = oracle.generalized_eigs(ops["A"], ops["b"], K)
+    relgap = (lam_o[K] - lam_o[K - 1]) / lam_o[K - 1]
+    tol = min(1e-6, 1e-5 * relgap / 4)
+    print(f"[gpu] wheel n={g.n} nnz={g.nnz} relgap={relgap:.3g}", flush=True)
+    X, lam, info = me.embed(g, K, tol=tol, seed=1, precision="mixed")
+    assert info["status"] == 0, info
+    Xn, lamn = _np(X), _np(lam)
+    np.testing.assert_array_less(np.abs(lamn - lam_o[:K]) / np.abs(lam_o[:K]), 1e-6)
+    assert oracle.sin_principal_angle_b(Xn, V_o[:, :K], ops["b"]) <= 1e-5
+    X2, lam2, info2 = me.embed(g, K, tol=tol, seed=1, precision="mixed", addressing="global")
+    assert torch.equal(X, X2) and torch.equal(lam, lam2)
