@@ -381,6 +381,18 @@ void me_server_destroy(me_server* s);
 int me_kernel_timing(int kind);
 int me_kernel_timing_read(int64_t* launches, double* total_ms, double* bytes);
 
+/* Run-time tuner of the FP32 preconditioner step (diagnostic).  A one-graph
+ * solve runs each Chebyshev step either with the workgroup's neighbour rows
+ * staged in LDS (form 0) or gathered from L2 (form 1); the two give the same
+ * results bit for bit.  The first iteration of a kind of solve not seen
+ * before in the process (block width, entry range: 1 = one-hop entries of
+ * the embedding solve, 2 = two-hop entries of the eps solve, and
+ * floor(log2 rows)) times half its steps in each form and keeps the faster
+ * for that kind.  me_step_form returns the kept form of a kind (-1: not
+ * timed yet or being timed); me_step_form_reset forgets every choice. */
+int me_step_form(int block_width, int range, int64_t rows);
+void me_step_form_reset(void);
+
 /* ---- kNN graph of points (the step before the path) --------------------
  * The symmetric weighted graph of Section 5.1's kNN construction (the k
  * nearest neighbours by Euclidean distance) with Gaussian weights:

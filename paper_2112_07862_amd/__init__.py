@@ -8,5 +8,5 @@ from .api import (  # noqa: F401
     build_graph_ops, build_workspace_bytes, cluster_scores, cluster_workspace_bytes, embed,
     embed_batch, embed_batch_workspace_bytes, gmm, kernel_timing, kernel_timing_read, kmeans,
     knn_graph, knn_workspace_bytes, make_opts,
-    server_request_bytes, to_device,
+    server_request_bytes, step_form, step_form_reset, to_device,
 )

@@ -121,6 +121,8 @@ SIGNATURES = {
     "me_kernel_timing": (c_int, [c_int]),
     "me_kernel_timing_read": (c_int, [ctypes.POINTER(c_int64), ctypes.POINTER(c_double),
                                       ctypes.POINTER(c_double)]),
+    "me_step_form": (c_int, [c_int, c_int, c_int64]),
+    "me_step_form_reset": (None, []),
 }
 
 KT_OFF, KT_SPMM_A, KT_GRAM_RR, KT_COMBINE, KT_CHEB = 0, 1, 2, 3, 4

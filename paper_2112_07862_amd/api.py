@@ -496,6 +496,18 @@ def kernel_timing(kind: int) -> None:
     _check(L.load().me_kernel_timing(int(kind)), "kernel_timing")
 
 
+def step_form(block_width: int, range_: int, rows: int) -> int:
+    """Form the run-time tuner kept for a kind of one-graph preconditioner
+    step (0 halo-staged, 1 gathering, -1 not timed yet); range_ 1 = one-hop
+    entries (embedding solve), 2 = two-hop entries (eps solve)."""
+    return int(L.load().me_step_form(int(block_width), int(range_), int(rows)))
+
+
+def step_form_reset() -> None:
+    """Forgets every choice of the run-time tuner."""
+    L.load().me_step_form_reset()
+
+
 def kernel_timing_read() -> dict:
     n, ms, b = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
     _check(L.load().me_kernel_timing_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)),

@@ -130,10 +130,13 @@ void sl_spmm(const SlotDev* sl, const TileSet& ts, int in, int out, int cert, hi
 template <typename T>
 void sl_cheb_first(const SlotDev* sl, const TileSet& ts, int r, int y, int yprev, hipStream_t s);
 // host_sl: the host copy of the slot table (a one-slot set passes its
-// slot's pointers in the kernel arguments)
+// slot's pointers in the kernel arguments).  form: kFormHalo (the
+// halo-staged step where the slots have halos that fit) or kFormGather (the
+// gathering step); both give the same results bit for bit.
+enum { kFormHalo = 0, kFormGather = 1 };
 template <typename T>
 void sl_cheb_step(const SlotDev* sl, const SlotDev* host_sl, const TileSet& ts, int k, int r,
-                  int yin, int yout, hipStream_t s);
+                  int yin, int yout, hipStream_t s, int form = kFormHalo);
 // R = AX - B X Lambda (-> block w unless w < 0; Jacobi-scaled if jacobi),
 // per-tile sums of |r|^2, |Bx|^2, x^T D x.
 void sl_resid(const SlotDev* sl, const TileSet& ts, int w, int jacobi, int cert, hipStream_t s);
@@ -303,6 +306,18 @@ class Engine {
   int enqueue_round(int ce);
   void drop_graph();
   hipStream_t cap_s_ = nullptr;  // private capture stream
+  bool capturing_ = false;        // iterations are being recorded into a graph
+  // run-time choice of the one-slot preconditioner step's form: the first
+  // iteration of a kind of slot not seen before in this process times half
+  // its steps in each form; the faster is kept for that kind
+  struct FormTune {
+    bool live = false;
+    int key[3] = {0, 0, 0};  // block width, entry range, log2 of the rows
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    int n0 = 0, n1 = 0;      // steps timed in each form
+  } tune_;
+  int step_form(const TileSet& ts, bool* tune);
+  void finish_tune();
   hipGraphExec_t gexec_ = nullptr;
   int sets_ver_ = 0, gexec_ver_ = -1;
   size_t bytes_in_use_ = 0;

@@ -21,8 +21,11 @@
 // certificate misses the tolerance the slot iterates again (at most three
 // times).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "engine.h"
 #include "rowops.h"
@@ -124,8 +127,21 @@ int Engine::init() {
   return ME_OK;
 }
 
+// The form of the one-slot FP32 preconditioner step per kind of slot
+// (block width, entry range, log2 of the rows): kFormHalo or kFormGather
+// once timed, -1 while its first iteration times both.  Process-wide: every
+// engine of the process shares what was measured.
+static std::mutex g_form_mu;
+static std::map<std::array<int, 3>, int> g_form;
+
 Engine::~Engine() {
   (void)hipStreamSynchronize(s_);
+  if (tune_.live) {  // timed but never read: time that kind again later
+    std::lock_guard<std::mutex> l(g_form_mu);
+    g_form.erase({tune_.key[0], tune_.key[1], tune_.key[2]});
+  }
+  for (auto& e : tune_.ev)
+    if (e) (void)hipEventDestroy(e);
   drop_graph();
   if (cap_s_) (void)hipStreamDestroy(cap_s_);
   free_sets(&sets_);
@@ -409,6 +425,42 @@ void Engine::start_pass(const TileSet& ts) {
   rr_x(ts, 0);
 }
 
+
+int Engine::step_form(const TileSet& ts, bool* tune) {
+  *tune = false;
+  if (!cheb32_ || !ts.pk || ts.nslots != 1 || capturing_ || tune_.live) return kFormHalo;
+  const SlotDev& h = hdev_[ts.ids[0]];
+  if (!h.h_cnt) return kFormHalo;  // no halos: the gathering step in either case
+  int lg = 0;
+  while ((int64_t)1 << (lg + 1) <= h.n) ++lg;
+  const std::array<int, 3> key{ts.kb, h.cheb_range, lg};
+  std::lock_guard<std::mutex> l(g_form_mu);
+  const auto it = g_form.find(key);
+  if (it != g_form.end()) return it->second < 0 ? kFormHalo : it->second;
+  g_form[key] = -1;
+  for (int q = 0; q < 3; ++q) tune_.key[q] = key[q];
+  *tune = true;
+  return kFormHalo;
+}
+
+// After the round of a timed iteration: keep the faster form per step.
+void Engine::finish_tune() {
+  if (!tune_.live) return;
+  tune_.live = false;
+  float t0 = 0.f, t1 = 0.f;
+  const bool ok = hipEventElapsedTime(&t0, tune_.ev[0], tune_.ev[1]) == hipSuccess &&
+                  hipEventElapsedTime(&t1, tune_.ev[1], tune_.ev[2]) == hipSuccess &&
+                  tune_.n0 > 0 && tune_.n1 > 0;
+  const std::array<int, 3> key{tune_.key[0], tune_.key[1], tune_.key[2]};
+  std::lock_guard<std::mutex> l(g_form_mu);
+  if (!ok) {
+    (void)hipGetLastError();
+    g_form.erase(key);  // time it again later
+    return;
+  }
+  g_form[key] = (double)t1 / tune_.n1 < (double)t0 / tune_.n0 ? kFormGather : kFormHalo;
+}
+
 void Engine::iteration(const TileSet& ts) {
   const int kb = ts.kb;
   ++tag_;
@@ -462,12 +514,30 @@ void Engine::iteration(const TileSet& ts) {
     }
     {
       KScope ks(tm ? KT_CHEB : -1, s_, (deg - 1) * cb, tag_, deg - 1);
+      bool tune = false;
+      int form = h16 ? kFormHalo : step_form(ts, &tune);
+      const int half = deg / 2;  // timed: steps 1 .. half - 1 halo, the rest gathering
+      if (tune) {
+        for (auto& e : tune_.ev)
+          if (!e && hipEventCreate(&e) != hipSuccess) tune = false;
+        if (tune) {
+          tune_.live = true;
+          tune_.n0 = half - 1;
+          tune_.n1 = deg - half;
+          (void)hipEventRecord(tune_.ev[0], s_);
+        }
+      }
       for (int k = 1; k < deg; ++k) {
+        if (tune && k == half) {
+          (void)hipEventRecord(tune_.ev[1], s_);
+          form = kFormGather;
+        }
         if (h16) sl_cheb_step_h(hdev_.data(), ts, k, r, cur, nxt, s_);
-        else if (cheb32_) sl_cheb_step<float>(d_slots_, hdev_.data(), ts, k, r, cur, nxt, s_);
+        else if (cheb32_) sl_cheb_step<float>(d_slots_, hdev_.data(), ts, k, r, cur, nxt, s_, form);
         else sl_cheb_step<double>(d_slots_, hdev_.data(), ts, k, r, cur, nxt, s_);
         std::swap(cur, nxt);
       }
+      if (tune) (void)hipEventRecord(tune_.ev[2], s_);
     }
     if (h16) sl_to64_h(d_slots_, ts, BW32, BW, s_);
     else if (cheb32_) sl_to64(d_slots_, ts, BW32, BW, s_);
@@ -690,7 +760,9 @@ int Engine::enqueue_round(int ce) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cap_s_, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
+      capturing_ = true;
       for (auto& ts : sets_) iteration(ts);
+      capturing_ = false;
       e = hipStreamEndCapture(cap_s_, &g);
     }
     s_ = keep;
@@ -712,6 +784,7 @@ int Engine::end_round(std::vector<int>* finished) {
   if (!round_open_) return ME_OK;
   round_open_ = false;
   ME_TRY_STATUS(read_ctrl());
+  finish_tune();  // the round's events are complete
   int adv = 0;
   std::vector<int> stopped;
   for (size_t q = 0; q < active_.size(); ++q) {
@@ -746,3 +819,20 @@ int Engine::run() {
 }
 
 }  // namespace me
+
+extern "C" {
+
+int me_step_form(int block_width, int range, int64_t rows) {
+  int lg = 0;
+  while (rows > 0 && ((int64_t)1 << (lg + 1)) <= rows) ++lg;
+  std::lock_guard<std::mutex> l(me::g_form_mu);
+  const auto it = me::g_form.find({block_width, range, lg});
+  return it == me::g_form.end() ? -1 : it->second;
+}
+
+void me_step_form_reset(void) {
+  std::lock_guard<std::mutex> l(me::g_form_mu);
+  me::g_form.clear();
+}
+
+}  // extern "C"

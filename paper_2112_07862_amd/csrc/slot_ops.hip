@@ -590,14 +590,14 @@ static ChebView<T> cheb_view_host(const SlotDev& d, int r, int yin, int yout) {
 
 template <typename T, int KB, bool PK>
 static void launch_cheb_step(const SlotDev* sl, const SlotDev* host_sl, const TileSet& ts, int k,
-                             int r, int yin, int yout, hipStream_t s) {
+                             int r, int yin, int yout, int form, hipStream_t s) {
   const dim3 grid(xcd_grid(ts.n_gather)), blk(RowCfg<T, KB>::THREADS);
   if (ts.buf && ts.nslots == 1) {
     const ChebView<T> v = cheb_view_host<T>(host_sl[ts.ids[0]], r, yin, yout);
     const int64_t nb = (v.n + kStep1Rows - 1) / kStep1Rows;
     const dim3 g1(xcd_grid(nb)), b1(step1_threads<T, KB>());
     if constexpr (PK && sizeof(T) == 4) {
-      const int lds = halo_lds_bytes<KB>(v);
+      const int lds = form == kFormGather ? 0 : halo_lds_bytes<KB>(v);
       if (lds > 0) {
         const int64_t nh = (v.n + kHaloRows - 1) / kHaloRows;
         const dim3 gh(xcd_grid(nh)), bh(halo_threads<KB>());
@@ -642,15 +642,15 @@ static void launch_cheb_step(const SlotDev* sl, const SlotDev* host_sl, const Ti
 
 template <typename T>
 void sl_cheb_step(const SlotDev* sl, const SlotDev* host_sl, const TileSet& ts, int k, int r,
-                  int yin, int yout, hipStream_t s) {
+                  int yin, int yout, hipStream_t s, int form) {
   if (ts.n_gather == 0) return;
   ME_DISPATCH_KB(ts.kb, {
     static_assert(RowCfg<T, KB>::ROWS == kGatherRows, "gather tile rows");
     if constexpr (sizeof(T) == 4) {
-      if (ts.pk) launch_cheb_step<T, KB, true>(sl, host_sl, ts, k, r, yin, yout, s);
-      else launch_cheb_step<T, KB, false>(sl, host_sl, ts, k, r, yin, yout, s);
+      if (ts.pk) launch_cheb_step<T, KB, true>(sl, host_sl, ts, k, r, yin, yout, form, s);
+      else launch_cheb_step<T, KB, false>(sl, host_sl, ts, k, r, yin, yout, form, s);
     } else {
-      launch_cheb_step<T, KB, false>(sl, host_sl, ts, k, r, yin, yout, s);
+      launch_cheb_step<T, KB, false>(sl, host_sl, ts, k, r, yin, yout, form, s);
     }
   });
 }
@@ -808,9 +808,9 @@ void sl_to64_h(const SlotDev* sl, const TileSet& ts, int from, int to, hipStream
 template void sl_cheb_first<double>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
 template void sl_cheb_first<float>(const SlotDev*, const TileSet&, int, int, int, hipStream_t);
 template void sl_cheb_step<double>(const SlotDev*, const SlotDev*, const TileSet&, int, int,
-                                   int, int, hipStream_t);
+                                   int, int, hipStream_t, int);
 template void sl_cheb_step<float>(const SlotDev*, const SlotDev*, const TileSet&, int, int, int,
-                                  int, hipStream_t);
+                                  int, hipStream_t, int);
 
 // ---------------------------------------------------------------------------
 // Residual R = AX - B X Lambda; W = R or D^-1 R (Jacobi); per tile: column

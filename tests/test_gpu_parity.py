@@ -584,3 +584,30 @@ def test_embed_without_halos(me):
     assert oracle.sin_principal_angle_b(Xn, V_o[:, :K], ops["b"]) <= 1e-5
     X2, lam2, info2 = me.embed(g, K, tol=tol, seed=1, precision="mixed", addressing="global")
     assert torch.equal(X, X2) and torch.equal(lam, lam2)
+
+
+def test_step_form_tuning_leaves_results_unchanged(me):
+    """The run-time tuner times the halo-staged and the gathering forms of
+    the preconditioner step in the first iteration of a kind of solve and
+    keeps the faster: the first solve (mixed forms), the next (the kept
+    form) and the 64-bit-address form agree bit for bit, and both kinds of
+    the solve (the embedding's one-hop steps, the eps solve's two-hop
+    steps) get a choice.  A 40 000-node square: above the size whose
+    rounds replay as a HIP graph."""
+    g = sg.manifold_graph("square", 40000, 8, 11)
+    me.step_form_reset()
+    assert me.step_form(8, 1, g.n) == -1
+    h = me.build_graph_ops(g, precision="mixed")
+    X1, l1, i1 = me.embed(h, 8, tol=1e-6, seed=0, precision="mixed")
+    f_embed, f_eps = me.step_form(8, 1, g.n), me.step_form(4, 2, g.n)
+    print(f"[gpu] step forms: embedding {f_embed}, eps {f_eps}", flush=True)
+    assert f_embed in (0, 1) and f_eps in (0, 1)
+    X2, l2, i2 = me.embed(h, 8, tol=1e-6, seed=0, precision="mixed")
+    assert i1["status"] == 0 and i1["iterations"] == i2["iterations"]
+    assert torch.equal(X1, X2) and torch.equal(l1, l2)
+    h3 = me.build_graph_ops(g, precision="mixed", addressing="global")
+    assert h3.eps == h.eps
+    X3, l3, _ = me.embed(h3, 8, tol=1e-6, seed=0, precision="mixed", addressing="global")
+    assert torch.equal(X1, X3) and torch.equal(l1, l3)
+    h.close()
+    h3.close()
