@@ -308,13 +308,16 @@ class Engine {
   hipStream_t cap_s_ = nullptr;  // private capture stream
   bool capturing_ = false;        // iterations are being recorded into a graph
   // run-time choice of the one-slot preconditioner step's form: the first
-  // iteration of a kind of slot not seen before in this process times half
-  // its steps in each form; the faster is kept for that kind
+  // iteration of a kind of slot not seen before in this process runs its
+  // steps in blocks of kTuneBlock, alternating the two forms, and times each
+  // block; the form with the shorter time per step is kept for that kind
+  static constexpr int kTuneBlock = 8;
   struct FormTune {
     bool live = false;
-    int key[3] = {0, 0, 0};  // block width, entry range, log2 of the rows
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    int n0 = 0, n1 = 0;      // steps timed in each form
+    int key[3] = {0, 0, 0};      // block width, entry range, log2 of the rows
+    std::vector<hipEvent_t> ev;  // block boundaries
+    std::vector<int> steps;      // steps of each block (even blocks: halo form)
+    int used = 0;                // boundaries recorded
   } tune_;
   int step_form(const TileSet& ts, bool* tune);
   void finish_tune();

@@ -140,8 +140,7 @@ Engine::~Engine() {
     std::lock_guard<std::mutex> l(g_form_mu);
     g_form.erase({tune_.key[0], tune_.key[1], tune_.key[2]});
   }
-  for (auto& e : tune_.ev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto& e : tune_.ev) (void)hipEventDestroy(e);
   drop_graph();
   if (cap_s_) (void)hipStreamDestroy(cap_s_);
   free_sets(&sets_);
@@ -447,10 +446,18 @@ int Engine::step_form(const TileSet& ts, bool* tune) {
 void Engine::finish_tune() {
   if (!tune_.live) return;
   tune_.live = false;
-  float t0 = 0.f, t1 = 0.f;
-  const bool ok = hipEventElapsedTime(&t0, tune_.ev[0], tune_.ev[1]) == hipSuccess &&
-                  hipEventElapsedTime(&t1, tune_.ev[1], tune_.ev[2]) == hipSuccess &&
-                  tune_.n0 > 0 && tune_.n1 > 0;
+  double t[2] = {0.0, 0.0};
+  int n[2] = {0, 0};
+  bool ok = tune_.used >= 3;
+  for (int b = 0; ok && b + 1 < tune_.used; ++b) {
+    float ms = 0.f;
+    ok = hipEventElapsedTime(&ms, tune_.ev[b], tune_.ev[b + 1]) == hipSuccess;
+    t[b % 2] += ms;
+    n[b % 2] += tune_.steps[b];
+  }
+  ok = ok && n[0] > 0 && n[1] > 0;
+  const double t0 = ok ? t[0] : 0.0, t1 = ok ? t[1] : 0.0;
+  const int n0 = n[0], n1 = n[1];
   const std::array<int, 3> key{tune_.key[0], tune_.key[1], tune_.key[2]};
   std::lock_guard<std::mutex> l(g_form_mu);
   if (!ok) {
@@ -458,7 +465,7 @@ void Engine::finish_tune() {
     g_form.erase(key);  // time it again later
     return;
   }
-  g_form[key] = (double)t1 / tune_.n1 < (double)t0 / tune_.n0 ? kFormGather : kFormHalo;
+  g_form[key] = t1 / n1 < t0 / n0 ? kFormGather : kFormHalo;
 }
 
 void Engine::iteration(const TileSet& ts) {
@@ -516,28 +523,37 @@ void Engine::iteration(const TileSet& ts) {
       KScope ks(tm ? KT_CHEB : -1, s_, (deg - 1) * cb, tag_, deg - 1);
       bool tune = false;
       int form = h16 ? kFormHalo : step_form(ts, &tune);
-      const int half = deg / 2;  // timed: steps 1 .. half - 1 halo, the rest gathering
-      if (tune) {
-        for (auto& e : tune_.ev)
-          if (!e && hipEventCreate(&e) != hipSuccess) tune = false;
+      if (tune) {  // blocks of kTuneBlock steps, alternating halo and gathering
+        const int nb = (deg - 1 + kTuneBlock - 1) / kTuneBlock;
+        while ((int)tune_.ev.size() < nb + 1) {
+          hipEvent_t e = nullptr;
+          if (hipEventCreate(&e) != hipSuccess) break;
+          tune_.ev.push_back(e);
+        }
+        tune = (int)tune_.ev.size() >= nb + 1;
         if (tune) {
           tune_.live = true;
-          tune_.n0 = half - 1;
-          tune_.n1 = deg - half;
-          (void)hipEventRecord(tune_.ev[0], s_);
+          tune_.used = 0;
+          tune_.steps.assign(nb, 0);
         }
       }
       for (int k = 1; k < deg; ++k) {
-        if (tune && k == half) {
-          (void)hipEventRecord(tune_.ev[1], s_);
-          form = kFormGather;
+        if (tune && (k - 1) % kTuneBlock == 0) {
+          const int b = (k - 1) / kTuneBlock;
+          (void)hipEventRecord(tune_.ev[b], s_);
+          tune_.used = b + 1;
+          form = b % 2 == 0 ? kFormHalo : kFormGather;
         }
+        if (tune) ++tune_.steps[(k - 1) / kTuneBlock];
         if (h16) sl_cheb_step_h(hdev_.data(), ts, k, r, cur, nxt, s_);
         else if (cheb32_) sl_cheb_step<float>(d_slots_, hdev_.data(), ts, k, r, cur, nxt, s_, form);
         else sl_cheb_step<double>(d_slots_, hdev_.data(), ts, k, r, cur, nxt, s_);
         std::swap(cur, nxt);
       }
-      if (tune) (void)hipEventRecord(tune_.ev[2], s_);
+      if (tune) {
+        (void)hipEventRecord(tune_.ev[tune_.used], s_);
+        ++tune_.used;
+      }
     }
     if (h16) sl_to64_h(d_slots_, ts, BW32, BW, s_);
     else if (cheb32_) sl_to64(d_slots_, ts, BW32, BW, s_);
