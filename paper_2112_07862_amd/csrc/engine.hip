@@ -465,7 +465,8 @@ void Engine::finish_tune() {
     g_form.erase(key);  // time it again later
     return;
   }
-  g_form[key] = t1 / n1 < t0 / n0 ? kFormGather : kFormHalo;
+  // the halo form unless the gathering one is clearly faster (timing noise)
+  g_form[key] = t1 / n1 < 0.97 * (t0 / n0) ? kFormGather : kFormHalo;
 }
 
 void Engine::iteration(const TileSet& ts) {
