@@ -1561,8 +1561,9 @@ int build_pre_a(const me_csr* W, const me_opts* o, DevHeap& heap, hipStream_t s,
 }
 
 size_t build_mem1_bytes(int64_t n, int64_t nnz) {
+  const int64_t ne = nnz > 0 ? nnz : 1;  // W's arrays hold one entry at least
   size_t b1 = 0;
-  b1 += Arena::round((n + 1) * 8) + Arena::round(nnz * 4) + Arena::round(nnz * 8);  // W
+  b1 += Arena::round((n + 1) * 8) + Arena::round(ne * 4) + Arena::round(ne * 8);  // W
   b1 += Arena::round((n + 1) * 8) + Arena::round(n * 4);                            // t_rp, t_cnt
   b1 += 9 * Arena::round(n * 8) + 5 * Arena::round(n * 4);                          // per node
   b1 += 2 * Arena::round((n + 1) * 4);                                              // a_rp, a_tp

@@ -162,6 +162,46 @@ def test_embed_eps_zero_graph(me):
     assert np.max(np.abs(X[:, 0] - c)) <= 1e-6
 
 
+
+@pytest.mark.parametrize("n,K", [(2, 1), (2, 2), (3, 2), (3, 3)])
+def test_smallest_graphs(me, n, K):
+    """Paths of two and three nodes: no node of either has a two-hop pair
+    that keeps the two-hop graph connected (n = 2: T empty; n = 3: only the
+    ends pair up), so eps = mu = 0 and A = L (Section 4.2); the K smallest
+    generalized pairs of (L, B), up to K = n, against the oracle's dense
+    solve."""
+    g = sg.line(n, 1.5)
+    ops = oracle.build_ops(g.n, g.rowptr, g.col, g.val)
+    h = me.build_graph_ops(g)
+    assert h.eps == 0.0 and h.mu == 0.0
+    lam_o, V_o = oracle.generalized_eigs(ops["A"], ops["b"], K)
+    X, lam, info = me.embed(g, K, tol=1e-10, seed=0)
+    assert info["status_name"] == "ME_WARN_EPS_ZERO", info
+    X, lam = _np(X), _np(lam)
+    np.testing.assert_allclose(lam, lam_o[:K], rtol=1e-10, atol=1e-12)
+    assert oracle.sin_principal_angle_b(X, V_o[:, :K], ops["b"]) <= 1e-8
+    assert oracle.b_orthonormality_error(X, ops["b"]) <= 1e-12
+
+
+def test_degenerate_inputs_rejected(me):
+    """An empty graph is an invalid argument; graphs without edges (one node,
+    three nodes) have isolated nodes, which the scale b of Section 4.3 cannot
+    take (r_i = 0): rejected as such, also when the caller brings the
+    workspace the query sized."""
+    empty = sg.CSR(0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    with pytest.raises(me.MembedError) as e:
+        me.build_graph_ops(empty)
+    assert e.value.name == "ME_ERR_INVALID_ARG"
+    for n in (1, 3):
+        edgeless = sg.CSR(n, np.zeros(n + 1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+        with pytest.raises(me.MembedError) as e:
+            me.build_graph_ops(edgeless)
+        assert e.value.name == "ME_ERR_ISOLATED_NODE"
+        ws = torch.empty(me.build_workspace_bytes(edgeless), dtype=torch.uint8, device="cuda")
+        with pytest.raises(me.MembedError) as e:
+            me.build_graph_ops(edgeless, workspace=ws)
+        assert e.value.name == "ME_ERR_ISOLATED_NODE"
+
 def test_plain_fp64_square_2000_tol_1e8(me):
     """The plain-method configuration: N = 2000 uniform in the unit square,
     symmetrised 8-NN, K = 4, FP64 throughout, tol 1e-8, seed 0."""
