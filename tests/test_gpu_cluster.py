@@ -75,6 +75,44 @@ def test_kmeans_seeds_match(me):
     np.testing.assert_allclose(_np(cen), cen1, rtol=1e-12, atol=1e-12)
 
 
+def test_kmeans_degenerate_cases(me):
+    """One cluster (its centre is the mean), as many clusters as points (each
+    point its own centre, in k-means++ order) and identical points (every
+    D^2 weight is zero, and both sides then take the last point; ties of
+    the assignment go to the lower centre index on both sides)."""
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((257, 3))
+    cases = [(x, 1, [0.3]), (x[:6], 6, list(rng.random(6))),
+             (np.ones((50, 2)), 3, [0.2, 0.5, 0.7])]
+    for xx, C, u in cases:
+        lab_o, cen_o, it_o = CL.kmeans(xx, C, u)
+        lab, cen, it = me.kmeans(torch.as_tensor(xx, device="cuda"), C, u)
+        assert it == it_o
+        assert np.array_equal(_np(lab), lab_o)
+        np.testing.assert_allclose(_np(cen), cen_o, rtol=1e-12, atol=1e-12)
+
+
+def test_gmm_one_component(me):
+    """C = 1: the weight is 1, the mean is the sample mean and the covariance
+    the sample's maximum-likelihood covariance plus the ridge both sides add
+    (1e-6 times the mean variance of the coordinates)."""
+    x, _ = _blobs(31, 1, 3, 400)
+    lab0 = np.zeros(len(x), dtype=np.int64)
+    lab_o, w_o, mu_o, cov_o, ll_o, it_o = CL.gmm(x, 1, lab0)
+    lab, w, mu, cov, ll, it = me.gmm(torch.as_tensor(x, device="cuda"), 1,
+                                     torch.as_tensor(lab0, device="cuda"))
+    assert it == it_o
+    assert ll == pytest.approx(ll_o, rel=1e-12)
+    assert np.array_equal(_np(lab), lab_o)
+    np.testing.assert_allclose(_np(w), [1.0], rtol=1e-15)
+    np.testing.assert_allclose(_np(mu), mu_o, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(_np(cov), cov_o, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(mu_o[0], x.mean(axis=0), rtol=1e-12)
+    ridge = 1e-6 * np.mean(np.var(x, axis=0))
+    np.testing.assert_allclose(cov_o[0], np.cov(x.T, bias=True) + ridge * np.eye(3),
+                               rtol=1e-10, atol=1e-15)
+
+
 @pytest.mark.parametrize("C,K,n_per,steps", [(3, 2, 400, 100), (5, 4, 250, 100), (4, 8, 200, 7)])
 def test_gmm_matches_oracle(me, C, K, n_per, steps):
     x, y = _blobs(100 + C, C, K, n_per, spread=4.0)

@@ -110,6 +110,7 @@ def test_apply_matches_oracle(me, name, k):
 
 EMBED_CASES = [
     # name, K
+    ("square_2k", 1),
     ("square_2k", 4),
     ("sphere_3k", 16),
     ("torus_2500", 8),

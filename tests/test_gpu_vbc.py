@@ -38,6 +38,9 @@ GRAPHS = {
                                         sg.manifold_graph("square", 300, 8, 3)]),
     "square_2000": lambda: sg.manifold_graph("square", 2000, 8, 0),
     "swiss_2500": lambda: sg.manifold_graph("swiss_roll", 2500, 10, 1),
+    # the smallest inputs: one node without edges, one edge
+    "single": lambda: sg.CSR(1, np.zeros(2, np.int64), np.zeros(0, np.int32), np.zeros(0)),
+    "pair": lambda: sg.line(2),
 }
 
 
