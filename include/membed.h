@@ -46,7 +46,8 @@ typedef enum {
   ME_ERR_INVALID_ARG = -1,   /* null pointer, bad sizes, unsorted/duplicate/out-of-range columns */
   ME_ERR_NOT_SYMMETRIC = -2, /* W_ij != W_ji (Section 3.1)                              */
   ME_ERR_SELF_LOOP = -3,     /* W_ii present                                            */
-  ME_ERR_BAD_WEIGHT = -4,    /* weight not finite or <= 0 (Section 3.1: W_ij > 0)       */
+  ME_ERR_BAD_WEIGHT = -4,    /* weight not finite or <= 0 (Section 3.1: W_ij > 0); in
+                                ME_MIXED also a weight beyond FP32's range              */
   ME_ERR_ISOLATED_NODE = -5, /* node with no edge: r_i = 0, b undefined (Section 4.3)   */
   ME_ERR_K_RANGE = -6,       /* K outside 1..16, or the LOBPCG block does not fit N     */
   ME_ERR_WORKSPACE = -7,     /* workspace missing or smaller than the query returned    */
@@ -57,7 +58,11 @@ typedef enum {
 
 /* Precision of the bulk N-length work (SpMM, Gram products, block updates).
  * The small dense solves (Cholesky, Rayleigh-Ritz) and the final residual
- * certificate are always FP64. */
+ * certificate are always FP64.  ME_MIXED keeps a copy of the weights in FP32
+ * for the preconditioner: a graph with a weight above FP32's largest value
+ * (3.4e38) is refused with ME_ERR_BAD_WEIGHT (ME_FP64 has no such limit), and one with
+ * a weight past FP16's largest finite value (65504) runs its preconditioner
+ * on FP32 weights instead of the packed 16-bit entries. */
 enum { ME_FP64 = 0, ME_MIXED = 1 };
 /* Preconditioner T of the LOBPCG residual (the paper names LOBPCG and leaves
  * T open): none; Jacobi diag(A)^-1; or `cheb_degree` steps of Chebyshev

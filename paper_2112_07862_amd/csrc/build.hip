@@ -1319,10 +1319,11 @@ __global__ void __launch_bounds__(kBlock) k_pack_perm(
     const int64_t* toff, const int64_t* w_rp, const int32_t* w_col, const double* w_val,
     const int64_t* t_rp, const int32_t* t_col, const int32_t* t_cnt, const double* invt,
     int32_t* a_rp, int32_t* a_tp, int32_t* a_col, double* a_w, float* a_w32, uint32_t* a_pk,
-    uint32_t* a_tq, int* max_offset, int* max_tcnt) {
+    uint32_t* a_tq, int* max_offset, int* max_tcnt, int* wide_w) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t far = 0;  // largest |column - row| of this row
   int32_t tmax = 0;  // largest T_j over the row's two-hop columns
+  int wide = 0;      // W weights beyond FP16's finite range (bit 0), beyond FP32's (bit 1)
   if (i <= n) {
     const int64_t ws = woff[i], ts = nnz_w + toff[i];
     a_rp[i] = (int32_t)ws;
@@ -1339,6 +1340,8 @@ __global__ void __launch_bounds__(kBlock) k_pack_perm(
       a_w[ws + t] = v;
       a_w32[ws + t] = (float)v;
       a_pk[ws + t] = pack_entry(i, c, v);
+      wide |= (!(fabsf((float)(_Float16)(float)v) <= 65504.0f) ? 1 : 0) |
+              (!(fabsf((float)v) <= 3.4028234663852886e38f) ? 2 : 0);
       far = max(far, (int64_t)llabs((int64_t)c - i));
     }
     // T entries: weight 1/T_i + 1/T_j of the two-hop term (eq. (Q), reading R1)
@@ -1363,10 +1366,12 @@ __global__ void __launch_bounds__(kBlock) k_pack_perm(
   for (int o = kWave / 2; o > 0; o >>= 1) {
     f = max(f, __shfl_xor(f, o));
     tmax = max(tmax, __shfl_xor(tmax, o));
+    wide |= __shfl_xor(wide, o);
   }
   if ((threadIdx.x & (kWave - 1)) == 0) {
     atomicMax(max_offset, f);
     atomicMax(max_tcnt, tmax);
+    if (wide) atomicOr(wide_w, wide);
   }
 }
 
@@ -1788,10 +1793,11 @@ int build_pre_b(GraphOps* g, hipStream_t s) {
   scan_counts(n, tlen, toff, tile_tmp, s);
   int* max_offset = g->dflags + 12;
   int* max_tcnt = g->dflags + 13;
+  int* wide_w = g->dflags + 18;
   k_pack_perm<<<ceil_div(n + 1, kBlock), kBlock, 0, s>>>(
       n, nnz, g->perm, g->iperm, woff, toff, g->w_rp, g->w_col, g->w_val, g->t_rp, g->t_col,
       g->t_cnt, g->invt, g->a_rp, g->a_tp, g->a_col, g->a_w, g->a_w32, g->a_pk, g->a_tq,
-      max_offset, max_tcnt);
+      max_offset, max_tcnt, wide_w);
   k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->qinv, g->qinv_s,
                                                        g->qinv32_s);
   k_gather_node<<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, g->perm, g->invt, g->invt_s, nullptr);
@@ -1804,7 +1810,9 @@ int build_pre_b(GraphOps* g, hipStream_t s) {
                                                    g->h_list, g->h_cnt_t, g->dflags + 15,
                                                    g->dflags + 17);
   // roots (2), the mu denominator's bits (4, 5), the largest offset (12),
-  // the largest two-hop count of a column (13) and the halo sizes in one read
+  // the largest two-hop count of a column (13), the halo sizes (14-17) and
+  // whether a W weight lies beyond FP16's (18, bit 0) or FP32's (bit 1)
+  // range in one read
   int hf[20];
   ME_TRY(hipMemcpyAsync(hf, g->dflags, sizeof(hf), hipMemcpyDeviceToHost, s));
   ME_TRY(hipStreamSynchronize(s));
@@ -1815,8 +1823,13 @@ int build_pre_b(GraphOps* g, hipStream_t s) {
   double maxden;
   std::memcpy(&maxden, &hmaxden, 8);
   g->maxden = maxden;
-  g->pk_ok = hf[12] <= 32767;
-  g->tq_ok = g->pk_ok && hf[13] <= 65535;
+  // packed entries: every offset fits 16 bits (both packings) and every W
+  // weight FP16 (the FP32 preconditioner's; otherwise it reads the FP32
+  // weights, and its halos go with the packed form)
+  const bool off_ok = hf[12] <= 32767;
+  g->pk_ok = off_ok && (hf[18] & 1) == 0;
+  g->w32_ok = (hf[18] & 2) == 0;
+  g->tq_ok = off_ok && hf[13] <= 65535;
   g->h_max_w = hf[14];
   g->h_max_t = hf[15];
   g->halo_w = g->pk_ok && hf[16] == 0;

@@ -230,6 +230,7 @@ struct GraphOps {
   // every |column - row| fits (pk_ok)
   uint32_t* a_pk = nullptr;
   bool pk_ok = false;
+  bool w32_ok = true;  // every W weight finite in FP32 (the FP32 copies a_w32, a_pk)
   // the two-hop entries packed for the FP64 products: bits 0-15 the column
   // minus the row (int16), bits 16-31 T_j of the column (the weight is
   // 1/T_i + 1/T_j, formed on the fly); usable when offsets and counts fit

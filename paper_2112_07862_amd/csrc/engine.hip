@@ -173,6 +173,9 @@ int Engine::add(const SlotSpec& sp, void* ws, size_t ws_bytes, int* id_out) {
     }
   if (id < 0) return ME_ERR_INVALID_ARG;
   const GraphOps& g = *sp.g;
+  // the FP32 preconditioner and the FP32 product read W's weights in FP32
+  if (sp.op != OP_Q && (cheb32_ || o_.product == ME_PRODUCT_FP32) && !g.w32_ok)
+    return ME_ERR_BAD_WEIGHT;
   const int64_t n = g.n;
   const int kb = sp.kb;
   const size_t need = slot_bytes(n, kb);

@@ -203,6 +203,53 @@ def test_degenerate_inputs_rejected(me):
             me.build_graph_ops(edgeless, workspace=ws)
         assert e.value.name == "ME_ERR_ISOLATED_NODE"
 
+@pytest.mark.parametrize("w", [6e4, 1e5])
+def test_heavy_edge_at_the_fp16_limit(me, w):
+    """One edge of a dense random graph weighted 6e4 (below FP16's largest
+    finite value, 65504: packed FP16 weights) or 1e5 (past it: the
+    mixed-precision preconditioner reads FP32 weights; FP16 would hold
+    infinity and every preconditioned column would be dropped).  The heavy
+    edge leaves lambda_max / lambda_1 near 5e7, so the bar is the oracle's
+    own residual of the returned pairs at tol 1e-5 and B-orthonormality."""
+    g0 = sg.random_graph(300, 0.05, 4)
+    val = g0.val.copy()
+    c = int(g0.col[g0.rowptr[0]])  # the edge (0, c) and its mirror
+    val[g0.rowptr[0]] = w
+    k = g0.rowptr[c] + np.searchsorted(g0.col[g0.rowptr[c]:g0.rowptr[c + 1]], 0)
+    assert g0.col[k] == 0
+    val[k] = w
+    g = sg.CSR(g0.n, g0.rowptr, g0.col, val)
+    ops = oracle.build_ops(g.n, g.rowptr, g.col, g.val)
+    tol = 1e-5
+    X, lam, info = me.embed(g, 4, tol=tol, seed=1, precision="mixed")
+    print(f"[gpu] heavy edge {w:g}: status {info['status_name']} "
+          f"iterations {info['iterations']}", flush=True)
+    assert info["status"] == 0, info
+    X, lam = _np(X), _np(lam)
+    assert oracle.b_orthonormality_error(X, ops["b"]) <= 1e-10
+    assert np.all(oracle.relative_residuals(ops["A"], ops["b"], X, lam) <= tol * 1.01 + 1e-12)
+    lam_o, _ = oracle.generalized_eigs(ops["A"], ops["b"], 4)
+    np.testing.assert_allclose(lam, lam_o[:4], rtol=1e-4)
+
+
+def test_weights_beyond_fp32_refused_in_mixed(me):
+    """A weight above FP32's largest value cannot be held by the mixed
+    preconditioner's FP32 copy: the embedding is refused with a clear status
+    instead of running on infinities; the build itself (FP64) accepts the
+    graph."""
+    g0 = sg.manifold_graph("square", 2000, 8, 0)
+    g = sg.CSR(g0.n, g0.rowptr, g0.col, g0.val * 1e39)
+    h = me.build_graph_ops(g)
+    assert h.eps > 0.0
+    with pytest.raises(me.MembedError) as e:
+        me.embed(g, 4, precision="mixed")
+    assert e.value.name == "ME_ERR_BAD_WEIGHT"
+    # in a batch only that graph fails; its neighbour is solved
+    res = me.embed_batch([g, g0], [4, 4], precision="mixed")
+    assert res[0][0] is None and res[0][2]["status_name"] == "ME_ERR_BAD_WEIGHT"
+    assert res[1][2]["status"] == 0
+
+
 def test_plain_fp64_square_2000_tol_1e8(me):
     """The plain-method configuration: N = 2000 uniform in the unit square,
     symmetrised 8-NN, K = 4, FP64 throughout, tol 1e-8, seed 0."""
