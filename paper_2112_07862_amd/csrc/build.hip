@@ -479,14 +479,17 @@ __device__ __forceinline__ int32_t bfs_levels(const int64_t* __restrict__ rp,
   return lev;
 }
 
-// Exclusive scan of a[0..n) in place by one workgroup; returns the total.
+// Exclusive scan of a[0..n) in place by one workgroup of NT threads
+// (s_wave: NT / kWave ints); returns the total.  COH: a[] was written by
+// other workgroups of the same launch, so it is read past the L1.
+template <int NT = kBfsThreads, bool COH = false>
 __device__ __forceinline__ int32_t block_exclusive_scan(int32_t* a, int32_t n, int32_t* s_wave) {
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-  constexpr int NW = kBfsThreads / kWave;
+  constexpr int NW = NT / kWave;
   int32_t carry = 0;
-  for (int32_t base = 0; base < n; base += kBfsThreads) {
+  for (int32_t base = 0; base < n; base += NT) {
     const int32_t i = base + tid;
-    const int32_t v = i < n ? a[i] : 0;
+    const int32_t v = i < n ? (COH ? ld_coherent(&a[i]) : a[i]) : 0;
     int32_t x = v;
     for (int o = 1; o < kWave; o <<= 1) {
       const int32_t y = __shfl_up(x, o);
@@ -853,6 +856,7 @@ __global__ void k_bfs_start(int32_t* level, int32_t* fa, LevelCtl* ctl, int32_t*
   ctl[2] = LevelCtl{0, 0, 0};
   res[0] = 0;
   res[1] = 0;
+  res[2] = 0;  // the ordering's ticket (k_cm_count)
 }
 
 __global__ void k_store_i32(int32_t* p, int32_t v) { *p = v; }
@@ -903,16 +907,24 @@ __device__ __forceinline__ bool cm_child(const int32_t* level, const int32_t* ke
 }
 
 // Step 2: children per frontier node, and per chunk of kLvlChunk positions
-// (one chunk per workgroup pass, kNodeLanes lanes per node).
+// (one chunk per workgroup pass, kNodeLanes lanes per node); then, in the
+// workgroup that finishes last (a ticket taken after its counts are
+// published), the exclusive scan of the chunk counts in place and the next
+// level's state (its frontier is the children just counted).  The ticket
+// returns to 0 for the next level.
 __global__ void __launch_bounds__(kLvlThreads) k_cm_count(const int64_t* __restrict__ rp,
                                                           const int32_t* __restrict__ col,
                                                           const int32_t* level, const int32_t* key,
                                                           const int32_t* perm, int32_t* cnt,
-                                                          int32_t* partial, const LevelCtl* ctl,
-                                                          int t) {
+                                                          int32_t* partial, LevelCtl* ctl,
+                                                          int32_t* ticket, int t) {
   const LevelCtl* cur = ctl + (t & 1);
+  LevelCtl* nxt = ctl + ((t + 1) & 1);
   const int32_t nin = ld_ctl(&cur->nin);
-  if (nin == 0) return;
+  if (nin == 0) {  // past the end: the empty state carries forward
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nxt = *cur;
+    return;
+  }
   const int32_t lev = cur->lev;
   const int32_t* fin = perm + (cur->placed - nin);
   __shared__ int32_t s_k[kLvlChunk];
@@ -939,25 +951,23 @@ __global__ void __launch_bounds__(kLvlThreads) k_cm_count(const int64_t* __restr
     }
     __syncthreads();
   }
-}
-
-// Step 3 (one workgroup): exclusive scan of the chunk counts in place, and
-// the next level's state (its frontier is the children just counted).
-__global__ void __launch_bounds__(kBfsThreads) k_cm_scan(int32_t* partial, LevelCtl* ctl, int t) {
-  const LevelCtl* cur = ctl + (t & 1);
-  LevelCtl* nxt = ctl + ((t + 1) & 1);
-  const int32_t nin = ld_ctl(&cur->nin);
-  if (nin == 0) {
-    if (threadIdx.x == 0) *nxt = *cur;
-    return;
+  __shared__ int32_t s_last;
+  if (threadIdx.x == 0) {
+    __threadfence();  // this workgroup's counts before its ticket
+    s_last = atomicAdd(ticket, 1) == (int32_t)gridDim.x - 1;
   }
-  __shared__ int32_t s_wave[kBfsThreads / kWave];
-  const int32_t nchunks = (nin + kLvlChunk - 1) / kLvlChunk;
-  const int32_t total = block_exclusive_scan(partial, nchunks, s_wave);
-  if (threadIdx.x == 0) *nxt = LevelCtl{total, cur->lev + 1, cur->placed + total};
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  __shared__ int32_t s_wave[kLvlThreads / kWave];
+  const int32_t total = block_exclusive_scan<kLvlThreads, true>(partial, nchunks, s_wave);
+  if (threadIdx.x == 0) {
+    *nxt = LevelCtl{total, cur->lev + 1, cur->placed + total};
+    *ticket = 0;
+  }
 }
 
-// Step 4: place every child: a chunk starts at its scanned offset, a node at
+// Step 3: place every child: a chunk starts at its scanned offset, a node at
 // the counts of the chunk's nodes before it, and a node's children keep row
 // order.
 __global__ void __launch_bounds__(kLvlThreads) k_cm_place(const int64_t* __restrict__ rp,
@@ -1098,8 +1108,7 @@ static int wide_order(GraphOps* g, OrderArgs* dargs, hipStream_t s) {
     for (int q = 0; q < kLevelsPerRound; ++q, ++t) {
       k_cm_claim<<<kLvlGrid, kLvlThreads, 0, s>>>(a.rp, a.col, a.level, key, a.perm, cc, (int)t);
       k_cm_count<<<kLvlGrid, kLvlThreads, 0, s>>>(a.rp, a.col, a.level, key, a.perm, cnt, partial,
-                                                 cc, (int)t);
-      k_cm_scan<<<1, kBfsThreads, 0, s>>>(partial, cc, (int)t);
+                                                 cc, res + 2, (int)t);
       k_cm_place<<<kLvlGrid, kLvlThreads, 0, s>>>(a.rp, a.col, a.level, key, a.perm, cnt, partial,
                                                  cc, (int)t);
     }
