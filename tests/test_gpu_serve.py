@@ -116,6 +116,20 @@ def test_serve_failing_request_isolated(me):
     assert torch.equal(out[tickets[0]][0], a4[0]) and torch.equal(out[tickets[2]][0], a8[0])
 
 
+def test_serve_weight_beyond_fp32_refused_in_mixed(me):
+    """A request whose weights exceed FP32's range cannot run the mixed
+    preconditioner: it retires with ME_ERR_BAD_WEIGHT and its neighbours
+    are served as if alone."""
+    good = sg.manifold_graph("square", 700, 8, 41)
+    g0 = sg.manifold_graph("square", 600, 8, 42)
+    heavy = sg.CSR(g0.n, g0.rowptr, g0.col, g0.val * 1e39)
+    tickets, out, _ = _drive(me, [(good, 4), (heavy, 4)], 1e-8, stagger=False, seed=1,
+                             precision="mixed")
+    assert out[tickets[1]][2]["status_name"] == "ME_ERR_BAD_WEIGHT"
+    assert out[tickets[1]][0] is None
+    a4 = me.embed_batch([good], [4], tol=1e-8, seed=1, precision="mixed")[0]
+    assert torch.equal(out[tickets[0]][0], a4[0])
+
 @pytest.mark.timeout(600)
 def test_serve_recipe_mix_with_large_requests_equals_alone(me):
     """Requests drawn from the serving recipe (Poisson stream seed 7: N
