@@ -77,25 +77,30 @@ __global__ void k_validate_rows(int64_t n, const int64_t* rp, const int32_t* col
 
 // ---------------------------------------------------------------------------
 // Two-hop pattern.  Row i's candidates are the members of N(k) for k in N(i);
-// T_i is that union minus N(i) and i.  Rows whose candidate count fits the
-// LDS table use an open-addressing hash in LDS (one wave per row); larger
-// rows go to a bitmap kernel.  Output columns are sorted ascending.
+// T_i is that union minus N(i) and i.  Rows whose candidate count fits an
+// LDS table use an open-addressing hash in LDS (one wave per row): a small
+// table first (the rows of kNN graphs; little LDS, many waves per CU), the
+// rows it cannot take a large one, the rest a bitmap kernel.  Output columns
+// are sorted ascending.
 // ---------------------------------------------------------------------------
 
-constexpr int kHashCap = 2048;            // slots per row table (power of two)
-constexpr int kHashMaxKeys = kHashCap / 2; // keys admitted (load factor <= 1/2)
+constexpr int kHashSmall = 512;   // slots per row table (powers of two) ...
+constexpr int kHashLarge = 2048;  // ... admitting half as many keys (load factor <= 1/2)
 
+template <int CAP>
 __device__ inline unsigned hash_slot(int32_t j) {
-  return ((uint32_t)j * 2654435761u) >> (32 - 11);  // 11 = log2(kHashCap)
+  constexpr int bits = __builtin_ctz(CAP);
+  return ((uint32_t)j * 2654435761u) >> (32 - bits);
 }
 
+template <int CAP>
 __device__ inline void hash_insert(int* table, int32_t j, bool excluded) {
   int key = excluded ? -(j + 1) : (j + 1);
-  unsigned h = hash_slot(j);
+  unsigned h = hash_slot<CAP>(j);
   for (;;) {
     int prev = atomicCAS(&table[h], 0, key);
     if (prev == 0 || prev == j + 1 || prev == -(j + 1)) return;
-    h = (h + 1) & (kHashCap - 1);
+    h = (h + 1) & (CAP - 1);
   }
 }
 
@@ -104,20 +109,26 @@ __device__ inline int64_t wave_sum_i64(int64_t v) {
   return v;
 }
 
-// mode 0: count (tcnt[i] = T_i, big rows appended to big_list with tcnt = 0)
-// mode 1: fill (writes sorted columns at t_rp[i]; big rows skipped)
+// Rows `rows[0..nrows)` (rows null: every row, nrows = n) with a table of
+// CAP slots.  mode 0: count (tcnt[i] = T_i; a row with more candidates than
+// the table admits is appended to over_list with tcnt = 0); mode 1: fill
+// (writes sorted columns at t_rp[i]; such rows skipped, over_list unused).
+template <int CAP>
 __global__ void __launch_bounds__(64) k_twohop_lds(int64_t n, const int64_t* rp, const int32_t* col,
                                                    int mode, int32_t* tcnt, const int64_t* t_rp,
-                                                   int32_t* t_col, int32_t* big_list,
-                                                   int32_t* big_count) {
-  __shared__ int table[kHashCap];
-  __shared__ int32_t list[kHashMaxKeys];
+                                                   int32_t* t_col, const int32_t* rows,
+                                                   int64_t nrows, int32_t* over_list,
+                                                   int32_t* over_count) {
+  constexpr int kMaxKeys = CAP / 2;
+  __shared__ int table[CAP];
+  __shared__ int32_t list[kMaxKeys];
   __shared__ int lane_off[kWave];
   const int lane = threadIdx.x;
-  constexpr int per = kHashCap / kWave;  // 32 slots per lane
+  constexpr int per = CAP / kWave;  // slots per lane
   for (int q = 0; q < per; ++q) table[lane * per + q] = 0;
   __syncthreads();
-  for (int64_t row = blockIdx.x; row < n; row += gridDim.x) {
+  for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+    const int64_t row = rows ? (int64_t)rows[r] : r;
     const int64_t s = rp[row], e = rp[row + 1];
     int64_t cand = 0;
     for (int64_t t = s + lane; t < e; t += kWave) {
@@ -125,21 +136,21 @@ __global__ void __launch_bounds__(64) k_twohop_lds(int64_t n, const int64_t* rp,
       cand += rp[k + 1] - rp[k];
     }
     cand = wave_sum_i64(cand);
-    if (cand + (e - s) + 1 > kHashMaxKeys) {
+    if (cand + (e - s) + 1 > kMaxKeys) {
       if (mode == 0 && lane == 0) {
-        int slot = atomicAdd(big_count, 1);
-        big_list[slot] = (int32_t)row;
+        int slot = atomicAdd(over_count, 1);
+        over_list[slot] = (int32_t)row;
         tcnt[row] = 0;
       }
       continue;
     }
-    if (lane == 0) hash_insert(table, (int32_t)row, true);
-    for (int64_t t = s + lane; t < e; t += kWave) hash_insert(table, col[t], true);
+    if (lane == 0) hash_insert<CAP>(table, (int32_t)row, true);
+    for (int64_t t = s + lane; t < e; t += kWave) hash_insert<CAP>(table, col[t], true);
     __syncthreads();
     for (int64_t t = s; t < e; ++t) {
       int32_t k = col[t];
       const int64_t ks = rp[k], ke = rp[k + 1];
-      for (int64_t u = ks + lane; u < ke; u += kWave) hash_insert(table, col[u], false);
+      for (int64_t u = ks + lane; u < ke; u += kWave) hash_insert<CAP>(table, col[u], false);
     }
     __syncthreads();
     int mine = 0;
@@ -1716,11 +1727,22 @@ static int build_pre_a_impl(const me_csr* W, const me_opts* o, DevHeap& heap, hi
   }
 
   // ---- two-hop pattern: count
-  int32_t* big_list = reinterpret_cast<int32_t*>(g->r);  // n int32 fit in n doubles
+  // rows the small table cannot take (mid) and rows the large one cannot
+  // (big): 2n int32 fit in g->r's n doubles
+  int32_t* big_list = reinterpret_cast<int32_t*>(g->r);
+  int32_t* mid_list = big_list + n;
   int32_t* big_count = dflags + 1;
-  const int grid_lds = (int)std::min<int64_t>(n, 256 * 20);
-  k_twohop_lds<<<grid_lds, kWave, 0, s>>>(n, g->w_rp, g->w_col, 0, g->t_cnt, nullptr, nullptr,
-                                          big_list, big_count);
+  int32_t* mid_count = dflags + 19;
+  const int grid_small = (int)std::min<int64_t>(n, 256 * 32);
+  k_twohop_lds<kHashSmall><<<grid_small, kWave, 0, s>>>(
+      n, g->w_rp, g->w_col, 0, g->t_cnt, nullptr, nullptr, nullptr, n, mid_list, mid_count);
+  int nmid = 0;
+  ME_TRY_STATUS(read_scalar(mid_count, &nmid, s));
+  const int grid_mid = (int)std::min<int64_t>(nmid, 256 * 20);
+  if (nmid > 0)
+    k_twohop_lds<kHashLarge><<<grid_mid, kWave, 0, s>>>(n, g->w_rp, g->w_col, 0, g->t_cnt,
+                                                        nullptr, nullptr, mid_list, nmid,
+                                                        big_list, big_count);
   int nbig = 0;
   ME_TRY_STATUS(read_scalar(big_count, &nbig, s));
   uint32_t* bitmaps = nullptr;
@@ -1764,8 +1786,12 @@ static int build_pre_a_impl(const me_csr* W, const me_opts* o, DevHeap& heap, hi
   g->h_list = ar2.take<int32_t>(nnz + nnz_t + 1);
   g->mem_bytes += b2;
 
-  k_twohop_lds<<<grid_lds, kWave, 0, s>>>(n, g->w_rp, g->w_col, 1, g->t_cnt, g->t_rp, g->t_col,
-                                          big_list, big_count);
+  k_twohop_lds<kHashSmall><<<grid_small, kWave, 0, s>>>(
+      n, g->w_rp, g->w_col, 1, g->t_cnt, g->t_rp, g->t_col, nullptr, n, nullptr, nullptr);
+  if (nmid > 0)
+    k_twohop_lds<kHashLarge><<<grid_mid, kWave, 0, s>>>(n, g->w_rp, g->w_col, 1, g->t_cnt,
+                                                        g->t_rp, g->t_col, mid_list, nmid,
+                                                        nullptr, nullptr);
   if (nbig > 0) {
     k_twohop_big<<<grid_big, 256, 0, s>>>(n, g->w_rp, g->w_col, 1, big_list, nbig, bitmaps,
                                           g->t_cnt, g->t_rp, g->t_col);
